@@ -1,0 +1,148 @@
+/*
+ * tr_als.h -- C ABI of the MI355X (gfx950) tensor-ring ALS library.
+ *
+ * Method: "Practical Alternating Least Squares for Tensor Ring Decomposition"
+ * (Yu & Li, arXiv 2210.11362).  The library runs the mode-n ALS update of
+ * Sec. 3 on one GPU:
+ *   (a) the MTTSP  M_n = X_[n] G^{!=n}_[2]  (Alg. 2, MTTSP step), streamed from
+ *       HBM in one pass with the subchain rows formed in LDS;
+ *   (b) the coefficient matrix S_n<2> = (G^{!=n}_[2])^T G^{!=n}_[2] formed from
+ *       per-core Gram matrices multiplied around the ring (Prop. 3.1, Alg. 2);
+ *   (c) the normal-equation solve G_n(2) S_n<2> = M_n (Alg. 2) with iterative
+ *       refinement, or the QR-stabilised update of Alg. 3.
+ *
+ * Conventions
+ *   - Every pointer is a DEVICE pointer unless its comment says "host".
+ *   - Layout follows the paper's index rule (Sec. 2): the first index is fastest.
+ *     X holds prod(I_n) elements with i_1 fastest.  Core n (R_n x I_n x R_{n+1},
+ *     R_{N+1} = R_1) holds element (a, i, b) at offset a + R_n*(i + I_n*b).
+ *   - Matrices returned by the introspection calls are column-major FP64.
+ *   - Work is enqueued on the caller's hipStream_t (passed as void*; NULL means
+ *     the default stream).  A context is used by one host thread at a time;
+ *     separate contexts are independent.
+ *   - Return value: TR_OK (0) or a negative TR_E* code.  tr_als_last_error()
+ *     gives the context's message.  Nothing fails silently: there is no hidden
+ *     regularisation and no CPU fallback.
+ */
+#ifndef TR_ALS_H
+#define TR_ALS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tr_als_ctx tr_als_ctx;
+
+/* Update variant (Alg. 2 normal equation, Alg. 3 QR). */
+enum { TR_NE = 0, TR_QR = 1 };
+
+/* Element types: storage type of X (TR_F64 or TR_F32) and the precision of the
+ * X contraction (all four).  The Gram, ring, solve and QR steps are always FP64. */
+enum { TR_F64 = 0, TR_F32 = 1, TR_BF16 = 2, TR_FP8 = 3 };
+
+/* Status codes. */
+enum {
+  TR_OK = 0,
+  TR_EINVAL = -1,      /* bad argument (sizes, ranks, dtype, variant, NULL) */
+  TR_ENOMEM = -2,      /* device allocation failed */
+  TR_EHIP = -3,        /* a HIP runtime call or launch failed */
+  TR_ESINGULAR = -4,   /* S_n not positive definite / zero pivot in R_[2] */
+  TR_ENONFINITE = -5   /* NaN or Inf met in M_n or in a new core */
+};
+
+/*
+ * tr_als_init -- create a context for one decomposition job.
+ *   ctx      host out: the new context (NULL on failure).
+ *   N        tensor order, 2 <= N <= 8.
+ *   dims     host, I_1..I_N, each >= 1; prod(I_n) < 2^62.
+ *   ranks    host, R_1..R_N, each 1..24 (R_{N+1} = R_1).
+ *   X        the data tensor, prod(I_n) elements of type x_dtype, i_1 fastest.
+ *            Borrowed read-only for the context's lifetime; never written or
+ *            freed by the library.
+ *   x_dtype  TR_F64 or TR_F32.
+ *   cores    host array of N device pointers to FP64 cores in the layout above.
+ *            Read here; overwritten in place at the end of each successful
+ *            tr_als_sweep (stream order).  Caller-owned.
+ *   variant  TR_NE or TR_QR.
+ *   hip_stream  hipStream_t for all work of this context.
+ * Allocates all workspace (freed by tr_als_destroy), computes ||X||_F^2 and the
+ * per-core Grams (NE) or core QRs (QR).  Synchronises the stream once.
+ */
+int tr_als_init(tr_als_ctx** ctx, int N, const int64_t* dims, const int64_t* ranks,
+                const void* X, int x_dtype, double* const* cores, int variant,
+                void* hip_stream);
+
+/*
+ * tr_als_sweep -- run nsweeps ALS sweeps; one sweep updates modes 1..N in order
+ * with each new core used at once (Gauss-Seidel, Alg. 1-3).
+ *   contraction_prec  TR_F64, TR_F32, TR_BF16 or TR_FP8: arithmetic of the X
+ *                     contraction (MFMA with FP32 accumulation for
+ *                     F32/BF16/FP8, FP64 for F64).  BF16/FP8 read a shadow copy
+ *                     of X built on first use (RNE; FP8 E4M3 with one FP32
+ *                     scale per tensor) and kept for the context's lifetime.
+ *   refine_steps      0..4 iterative-refinement steps of the normal-equation
+ *                     solve (NE variant; ignored by TR_QR).
+ * Synchronises the stream once at the end to read the device status word.
+ * On TR_ESINGULAR / TR_ENONFINITE the caller's cores hold the last good mode
+ * update and the context stays usable.
+ */
+int tr_als_sweep(tr_als_ctx* ctx, int nsweeps, int contraction_prec, int refine_steps);
+
+/*
+ * tr_als_fit -- relative error ||X - TR(G)||_F / ||X||_F of the current cores
+ * (Sec. 4 error formula), one streaming pass over X with the reconstruction
+ * formed on the fly and squared differences summed in FP64.
+ *   rel_err  host out.
+ * Synchronises the stream.
+ */
+int tr_als_fit(tr_als_ctx* ctx, double* rel_err);
+
+/* Free the context and everything it allocated.  NULL is accepted. */
+int tr_als_destroy(tr_als_ctx* ctx);
+
+/* Static text for a status code. */
+const char* tr_als_strerror(int status);
+
+/* Text of the context's last error ("" if none).  Valid until the next call on
+ * the context. */
+const char* tr_als_last_error(const tr_als_ctx* ctx);
+
+/* ------------------------------------------------------------------------ *
+ * Introspection of the individual hot-path steps, evaluated on the context's
+ * current cores without changing them.  Outputs are device pointers the
+ * caller allocates; each call synchronises the stream.
+ * ------------------------------------------------------------------------ */
+
+/* M_n = X_[n] G^{!=n}_[2] (Alg. 2 MTTSP), I_n x R_nR_{n+1}, column a + R_n*b,
+ * computed by the same X-streaming kernels a sweep uses, in precision prec. */
+int tr_als_mttsp(tr_als_ctx* ctx, int n /*1..N*/, int prec, double* M_out);
+
+/* S_n<2> (R_nR_{n+1} square) from the Gram ring (Prop. 3.1). */
+int tr_als_coef(tr_als_ctx* ctx, int n /*1..N*/, double* S_out);
+
+/* Gram of core k: E[p, q] = sum_i G_k(2)[i, p] G_k(2)[i, q] (R_kR_{k+1} square). */
+int tr_als_gram(tr_als_ctx* ctx, int k /*1..N*/, double* E_out);
+
+/* One mode update (the body of a sweep for mode n), committed to the
+ * context's internal cores; tr_als_store_cores copies them to the caller's
+ * buffers. */
+int tr_als_update_mode(tr_als_ctx* ctx, int n /*1..N*/, int prec, int refine_steps);
+int tr_als_store_cores(tr_als_ctx* ctx);
+
+/* ||X||_F^2 computed at init (FP64).  host out. */
+int tr_als_xnorm2(const tr_als_ctx* ctx, double* out);
+
+/* Kernel timing of the X-streaming contraction: when enabled, every launch of
+ * the X-stream kernel is bracketed by hipEvents on the context's stream; read
+ * returns the summed kernel time (ms) and launch count since the last reset. */
+int tr_als_profile_enable(tr_als_ctx* ctx, int enable);
+int tr_als_profile_read(tr_als_ctx* ctx, double* xstream_ms /*host*/, int64_t* launches /*host*/,
+                        double* bytes_per_launch /*host, algorithmic X bytes*/);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TR_ALS_H */

@@ -1,0 +1,74 @@
+// Shared declarations of the gfx950 TR-ALS library (device helpers, launch
+// wrappers, status flags).  Internal: not part of the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define TR_MAXN 8
+#define TR_MAXR 24
+
+// Bits latched into the device status word.
+enum { ST_SINGULAR = 1, ST_NONFINITE = 2 };
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// One byte of OCP FP8 E4M3.
+struct fp8e4m3 { uint8_t v; };
+
+// Arguments of the X-streaming contraction (the MTTSP).  The data tensor is
+// seen as a matrix A[i, k] (i = mode-n index, k = the other indices) and the
+// subchain row for k is formed as F1[f1(k)] * F2[f2(k)].
+struct XsArgs {
+  const void* X;
+  int64_t I;          // rows (I_n)
+  int64_t K;          // contraction length (prod_{j != n} I_j)
+  int64_t L;          // extent of the fast group (layout 1)
+  int layout;         // 0: A[i,k] at i + I*k;  1: at (k%L) + L*i + L*I*(k/L)
+  const double* F1;   // K1 entries, each Rb x Rmid, column-major (b fastest)
+  const double* F2;   // K2 entries, each Rmid x Ra, column-major (m fastest)
+  int64_t d1, m1, d2, m2;   // f1(k) = (k/d1) % m1, f2(k) = (k/d2) % m2
+  int Rb, Rmid, Ra;   // R_{n+1}, bond, R_n
+  int MT, NT;         // output tile rows / columns (multiples of 16)
+  int NTb;            // b-values per column tile (NT >= Ra*NTb)
+  int n_mt, n_nt;     // number of tiles along rows / columns
+  int64_t k_per_split;
+  int nsplit;
+  int wgm, wgn;       // 2-D arrangement of the 4 waves over the tile
+  float bscale;       // FP8: generated subchain rows are multiplied by this
+  void* partial;      // [nsplit][n_mt*n_nt][MT][NT] FP32 (FP64 for the FP64 path)
+};
+
+// Host-side launchers (defined in the .hip files).
+hipError_t launch_xstream(const XsArgs& a, int prec, int xdt, int kt, int wlay, size_t lds, hipStream_t s);
+size_t xstream_lds_bytes(const XsArgs& a, int prec, int kt);
+hipError_t launch_xs_reduce(const XsArgs& a, int prec, double out_scale, double* M, int* status, hipStream_t s);
+
+hipError_t launch_core_to_table(const double* core, int Rl, int64_t I, int Rr, double* out, hipStream_t s);
+hipError_t launch_chain_step(const double* T, int64_t J, int Rl, int Rm, const double* core, int64_t I, int Rr,
+                             double* out, hipStream_t s);
+hipError_t launch_identity_table(int R, double* out, hipStream_t s);
+hipError_t launch_core_unfold(const double* core, int Ra, int64_t I, int Rb, double* out, hipStream_t s);
+hipError_t launch_gram(const double* core, int Rl, int64_t I, int Rr, double* E, hipStream_t s);
+
+// Generic FP64 operand view for the small GEMMs: plain column-major matrix, or
+// a Gram E (RlRr x RlRr) read in Kronecker order:
+//   K[(b + Rl*b'), (c + Rr*c')] = E[(b + Rl*c) + RlRr*(b' + Rl*c')].
+struct MatView { const double* p; int64_t ld; int kind; int Rl, Rr; };
+hipError_t launch_gemm64(int64_t M, int64_t N, int64_t K, double alpha, MatView A, MatView B, double beta,
+                         const double* Cin, int64_t ldcin, double* C, int64_t ldc, hipStream_t s);
+hipError_t launch_realign_S(MatView W, int Ra, int Rb, double* S, hipStream_t s);
+hipError_t launch_chol(const double* S, int n, double* L, double* LT, double* work, int* status, hipStream_t s);
+hipError_t launch_chol_solve(const double* L, const double* LT, int n, const double* Rhs, int64_t I,
+                             double* G, int accumulate, const int* status, hipStream_t s);
+hipError_t launch_commit_core(const double* G, int64_t I, int Ra, int Rb, double* core, int* status, hipStream_t s);
+hipError_t launch_sumsq(const void* X, int xdt, int64_t n, double* partials, int nblk, double* out, hipStream_t s);
+hipError_t launch_absmax(const void* X, int xdt, int64_t n, float* partials, int nblk, float* out, hipStream_t s);
+hipError_t launch_to_bf16(const void* X, int xdt, int64_t n, void* out, hipStream_t s);
+hipError_t launch_to_fp8(const void* X, int xdt, int64_t n, const float* absmax, float* scale_out, void* out,
+                         hipStream_t s);
+hipError_t launch_fit(const void* X, int xdt, int64_t I, int64_t K, const double* G0, const double* F1,
+                      const double* F2, int64_t d1, int64_t m1, int64_t d2, int64_t m2, int Rb, int Rmid, int Ra,
+                      double* partials, int nblk, double* out, hipStream_t s);
+hipError_t launch_table_absmax(const double* T, int64_t n, double* out, hipStream_t s);

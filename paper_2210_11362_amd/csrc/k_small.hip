@@ -1,0 +1,525 @@
+// FP64 kernels around the X stream: partial subchain tables, per-core Grams,
+// the ring product of Grams, the normal-equation solve with refinement, the
+// core commit, norms, shadow conversions and the explicit fit.
+#include <algorithm>
+
+#include "common.h"
+#include "../../include/tr_als.h"
+
+namespace {
+
+__device__ __forceinline__ void mma64(f64x4& c, double a, double b) {
+  c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Partial subchain tables (Sec. 2 subchain product).  A table holds K entries,
+// entry k an Rl x Rr matrix stored column-major at k*Rl*Rr.
+// ---------------------------------------------------------------------------
+__global__ void core_to_table_kernel(const double* core, int Rl, int64_t I, int Rr, double* out) {
+  const int64_t n = (int64_t)Rl * I * Rr;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int r = (int)(e % Rl);
+  const int64_t i = (e / Rl) % I;
+  const int c = (int)(e / ((int64_t)Rl * I));
+  out[i * Rl * Rr + r + (int64_t)Rl * c] = core[e];
+}
+
+// out[(j + J*i)] = T[j] * G(i):  T entries Rl x Rm, core Rm x I x Rr.
+__global__ void chain_step_kernel(const double* T, int64_t J, int Rl, int Rm, const double* core, int64_t I, int Rr,
+                                  double* out) {
+  const int64_t sz = (int64_t)Rl * Rr;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= J * I * sz) return;
+  const int64_t ent = e / sz;
+  const int rc = (int)(e % sz);
+  const int r = rc % Rl, c = rc / Rl;
+  const int64_t j = ent % J, i = ent / J;
+  const double* t = T + j * (int64_t)Rl * Rm;
+  const double* g = core + i * Rm + (int64_t)Rm * I * c;
+  double s = 0.0;
+  for (int m = 0; m < Rm; ++m) s += t[r + (int64_t)Rl * m] * g[m];
+  out[e] = s;
+}
+
+// out[i + I*(a + Ra*b)] = core[a + Ra*(i + I*b)]  (classical mode-2 unfolding G_(2))
+__global__ void core_unfold_kernel(const double* core, int Ra, int64_t I, int Rb, double* out) {
+  const int64_t n = (int64_t)Ra * I * Rb;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int a = (int)(e % Ra);
+  const int64_t i = (e / Ra) % I;
+  const int b = (int)(e / ((int64_t)Ra * I));
+  out[i + I * (a + (int64_t)Ra * b)] = core[e];
+}
+
+__global__ void identity_table_kernel(int R, double* out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < R * R) out[e] = (e % R == e / R) ? 1.0 : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Gram of a core (Alg. 2 Gram step, Prop. 3.1): E = G_(2)^T G_(2) with
+// G_(2)[i, a + Rl*b] = core[a + Rl*(i + I*b)].  One wave per 16x16 block.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void gram_kernel(const double* core, int Rl, int64_t I, int Rr, double* E) {
+  const int RR = Rl * Rr;
+  const int nb = (RR + 15) / 16;
+  const int lane = threadIdx.x & 63;
+  const int blk = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (blk >= nb * nb) return;
+  const int bp = blk % nb, bq = blk / nb;
+  const int p = bp * 16 + (lane & 15), q = bq * 16 + (lane & 15);
+  const bool pok = p < RR, qok = q < RR;
+  const int64_t offp = pok ? (p % Rl) + (int64_t)Rl * I * (p / Rl) : 0;
+  const int64_t offq = qok ? (q % Rl) + (int64_t)Rl * I * (q / Rl) : 0;
+  f64x4 acc = {0, 0, 0, 0};
+  for (int64_t i0 = 0; i0 < I; i0 += 4) {
+    const int64_t i = i0 + (lane >> 4);
+    const double av = (pok && i < I) ? core[offp + Rl * i] : 0.0;
+    const double bv = (qok && i < I) ? core[offq + Rl * i] : 0.0;
+    mma64(acc, av, bv);
+  }
+  for (int v = 0; v < 4; ++v) {
+    const int row = bp * 16 + (lane >> 4) + 4 * v, col = bq * 16 + (lane & 15);
+    if (row < RR && col < RR) E[row + (int64_t)RR * col] = acc[v];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Small FP64 GEMM on MFMA: C = alpha*A*B + beta*Cin, operands through MatView.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double view_at(const MatView& v, int64_t r, int64_t c) {
+  if (v.kind == 0) return v.p[r + v.ld * c];
+  const int Rl = v.Rl, Rr = v.Rr;
+  const int64_t b = r % Rl, b2 = r / Rl, cc = c % Rr, c2 = c / Rr;
+  return v.p[(b + Rl * cc) + (int64_t)Rl * Rr * (b2 + Rl * c2)];
+}
+
+__global__ __launch_bounds__(256) void gemm64_kernel(int64_t M, int64_t N, int64_t K, double alpha, MatView A,
+                                                     MatView B, double beta, const double* Cin, int64_t ldcin,
+                                                     double* C, int64_t ldc) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nbm = (M + 15) / 16, nbn = (N + 15) / 16;
+  const int64_t blk = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (blk >= nbm * nbn) return;
+  const int64_t bm = blk % nbm, bn = blk / nbm;
+  const int64_t r = bm * 16 + (lane & 15), c = bn * 16 + (lane & 15);
+  f64x4 acc = {0, 0, 0, 0};
+  for (int64_t k0 = 0; k0 < K; k0 += 4) {
+    const int64_t k = k0 + (lane >> 4);
+    const double av = (r < M && k < K) ? view_at(A, r, k) : 0.0;
+    const double bv = (k < K && c < N) ? view_at(B, k, c) : 0.0;
+    mma64(acc, av, bv);
+  }
+  for (int v = 0; v < 4; ++v) {
+    const int64_t row = bm * 16 + (lane >> 4) + 4 * v, col = bn * 16 + (lane & 15);
+    if (row < M && col < N) {
+      double x = alpha * acc[v];
+      if (beta != 0.0) x += beta * Cin[row + ldcin * col];
+      C[row + ldc * col] = x;
+    }
+  }
+}
+
+// S[(a + Ra*b), (a' + Ra*b')] = W[(b + Rb*b'), (a + Ra*a')]  (S_n<2> from the
+// ring product, Prop. 3.1 with the Kronecker form of the Gram chain).
+__global__ void realign_S_kernel(MatView W, int Ra, int Rb, double* S) {
+  const int64_t RR = (int64_t)Ra * Rb;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= RR * RR) return;
+  const int64_t row = e % RR, col = e / RR;
+  const int64_t a = row % Ra, b = row / Ra, a2 = col % Ra, b2 = col / Ra;
+  S[e] = view_at(W, b + Rb * b2, a + Ra * a2);
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky S = L L^T in one workgroup (right-looking, column by column).  A
+// non-positive or non-finite pivot latches ST_SINGULAR.
+// ---------------------------------------------------------------------------
+template <bool IN_LDS>
+__global__ __launch_bounds__(1024) void chol_kernel(const double* S, int n, double* L, double* LT, double* work,
+                                                    int* status) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* A = IN_LDS ? reinterpret_cast<double*>(smem_raw) : work;
+  __shared__ int bad;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (tid == 0) bad = (*status != 0);
+  for (int e = tid; e < n * n; e += nt) A[e] = S[e];
+  __syncthreads();
+  if (bad) return;
+  for (int k = 0; k < n; ++k) {
+    const double d = A[k + n * k];
+    if (!(d > 0.0) || !isfinite(d)) {
+      if (tid == 0) atomicOr(status, ST_SINGULAR);
+      return;  // uniform: every thread read the same pivot
+    }
+    const double piv = sqrt(d);
+    __syncthreads();
+    for (int i = k + 1 + tid; i < n; i += nt) A[i + n * k] /= piv;
+    if (tid == 0) A[k + n * k] = piv;
+    __syncthreads();
+    const int m = n - k - 1;
+    for (int e = tid; e < m * m; e += nt) {
+      const int jj = e / m, ii = e % m;
+      if (ii >= jj) {
+        const int i = k + 1 + ii, j = k + 1 + jj;
+        A[i + n * j] -= A[i + n * k] * A[j + n * k];
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < n * n; e += nt) {
+    const int i = e % n, j = e / n;
+    const double v = (i >= j) ? A[e] : 0.0;
+    L[e] = v;
+    LT[j + n * i] = v;
+  }
+}
+
+// Solve G S = Rhs row by row with S = L L^T:  L y = rhs^T, L^T x = y.
+// One wave per right-hand side; y lives in LDS.
+__global__ __launch_bounds__(256) void chol_solve_kernel(const double* L, const double* LT, int n, const double* Rhs,
+                                                         int64_t I, double* G, int accumulate, const int* status) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  if (*status != 0) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t r = (int64_t)blockIdx.x * 4 + wave;
+  if (r >= I) return;
+  double* y = reinterpret_cast<double*>(smem_raw) + (size_t)wave * n;
+  for (int j = lane; j < n; j += 64) y[j] = Rhs[r + I * j];
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  for (int k = 0; k < n; ++k) {
+    const double yk = y[k] / L[k + (int64_t)n * k];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) y[k] = yk;
+    for (int j = k + 1 + lane; j < n; j += 64) y[j] -= L[j + (int64_t)n * k] * yk;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    const double xk = y[k] / L[k + (int64_t)n * k];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) y[k] = xk;
+    for (int j = lane; j < k; j += 64) y[j] -= LT[j + (int64_t)n * k] * xk;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+  for (int j = lane; j < n; j += 64) {
+    if (accumulate) G[r + I * j] += y[j];
+    else G[r + I * j] = y[j];
+  }
+}
+
+// core[a + Ra*(i + I*b)] = G[i + I*(a + Ra*b)] when the status word is clean
+// and G is finite; otherwise the core keeps its last good value.
+__global__ __launch_bounds__(1024) void commit_core_kernel(const double* G, int64_t I, int Ra, int Rb, double* core,
+                                                           int* status) {
+  __shared__ int bad;
+  const int64_t n = I * Ra * Rb;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  int mybad = 0;
+  for (int64_t e = threadIdx.x; e < n; e += blockDim.x)
+    if (!isfinite(G[e])) mybad = 1;
+  if (mybad) atomicOr(&bad, 1);
+  __syncthreads();
+  if (bad) {
+    if (threadIdx.x == 0) atomicOr(status, ST_NONFINITE);
+    return;
+  }
+  if (*status != 0) return;
+  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
+    const int64_t i = e % I, c = e / I;
+    const int64_t a = c % Ra, b = c / Ra;
+    core[a + Ra * (i + I * b)] = G[e];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Reductions and shadow conversions of X.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void sumsq_kernel(const T* X, int64_t n, double* partials) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const double v = (double)X[e];
+    s += v * v;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+__global__ void sum_partials_kernel(const double* partials, int n, double* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += partials[i];
+    *out = s;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void absmax_kernel(const T* X, int64_t n, float* partials) {
+  __shared__ float red[256];
+  float s = 0.0f;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    s = fmaxf(s, fabsf((float)X[e]));
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+__global__ void max_partials_kernel(const float* partials, int n, float* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    float s = 0.0f;
+    for (int i = 0; i < n; ++i) s = fmaxf(s, partials[i]);
+    *out = s;
+  }
+}
+
+__global__ void table_absmax_kernel(const double* T, int64_t n, double* out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) s = fmax(s, fabs(T[e]));
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+template <typename T>
+__global__ void to_bf16_kernel(const T* X, int64_t n, __bf16* out) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = (__bf16)(float)X[e];
+}
+
+// FP8 E4M3 (OCP) with one scale per tensor: q = fp8(x * s), s = 448 / max|x|.
+template <typename T>
+__global__ void to_fp8_kernel(const T* X, int64_t n, const float* absmax, float* scale_out, uint8_t* out) {
+  const float am = *absmax;
+  const float s = am > 0.0f ? 448.0f / am : 1.0f;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *scale_out = s;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32((float)X[e] * s, 0.0f, 0, false) & 0xff);
+}
+
+// ---------------------------------------------------------------------------
+// Explicit fit (Sec. 4 error formula): sum over X of (X - Xhat)^2 with
+// Xhat_(1)[i, k] = sum_c G_1(2)[i, c] B[k][c] and B[k] = G^{!=1}(k) formed
+// from the mode-1 partial-subchain tables.  FP64 throughout.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void fit_kernel(const T* X, int64_t I, int64_t K, const double* G0, const double* F1,
+                                                  const double* F2, int64_t d1, int64_t m1, int64_t d2, int64_t m2,
+                                                  int Rb, int Rmid, int Ra, int FIT_KT, double* partials) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int RR = Ra * Rb;
+  const int RR4 = (RR + 3) & ~3;
+  double* Bs = reinterpret_cast<double*>(smem_raw);  // [FIT_KT][RR4 + 1]
+  const int BST = RR4 + 1;
+  __shared__ double red[256];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t ntile = (K + FIT_KT - 1) / FIT_KT;
+  const int nbr = (int)((I + 15) / 16);
+  double sacc = 0.0;
+  for (int64_t t = blockIdx.x; t < ntile; t += gridDim.x) {
+    const int64_t k0 = t * FIT_KT;
+    const int kvalid = (int)min((int64_t)FIT_KT, K - k0);
+    __syncthreads();
+    for (int e = tid; e < FIT_KT * BST; e += 256) {
+      const int kk = e / BST, c = e % BST;
+      double s = 0.0;
+      if (kk < kvalid && c < RR) {
+        const int64_t k = k0 + kk;
+        const double* f1 = F1 + ((k / d1) % m1) * (int64_t)(Rb * Rmid);
+        const double* f2 = F2 + ((k / d2) % m2) * (int64_t)(Rmid * Ra);
+        const int aa = c % Ra, b = c / Ra;
+        for (int m = 0; m < Rmid; ++m) s += f1[b + Rb * m] * f2[m + Rmid * aa];
+      }
+      Bs[e] = s;
+    }
+    __syncthreads();
+    // output blocks: (row block, column block of 16 k's)
+    const int ncb = FIT_KT / 16;
+    for (int ob = wave; ob < nbr * ncb; ob += 4) {
+      const int br = ob / ncb, bc = ob % ncb;
+      const int64_t i = (int64_t)br * 16 + (lane & 15);
+      const int kkb = bc * 16 + (lane & 15);
+      f64x4 acc = {0, 0, 0, 0};
+      for (int c0 = 0; c0 < RR4; c0 += 4) {
+        const int c = c0 + (lane >> 4);
+        const double av = (i < I && c < RR) ? G0[i + I * c] : 0.0;
+        const double bv = Bs[kkb * BST + c];
+        mma64(acc, av, bv);
+      }
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = (int64_t)br * 16 + (lane >> 4) + 4 * v;
+        const int kk = bc * 16 + (lane & 15);
+        if (row < I && kk < kvalid) {
+          const double d = (double)X[row + I * (k0 + kk)] - acc[v];
+          sacc += d * d;
+        }
+      }
+    }
+  }
+  red[tid] = sacc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) partials[blockIdx.x] = red[0];
+}
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace
+
+hipError_t launch_core_to_table(const double* core, int Rl, int64_t I, int Rr, double* out, hipStream_t s) {
+  const int64_t n = (int64_t)Rl * I * Rr;
+  hipLaunchKernelGGL(core_to_table_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, core, Rl, I, Rr, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_chain_step(const double* T, int64_t J, int Rl, int Rm, const double* core, int64_t I, int Rr,
+                             double* out, hipStream_t s) {
+  const int64_t n = J * I * Rl * Rr;
+  hipLaunchKernelGGL(chain_step_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, T, J, Rl, Rm, core, I, Rr, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_core_unfold(const double* core, int Ra, int64_t I, int Rb, double* out, hipStream_t s) {
+  const int64_t n = (int64_t)Ra * I * Rb;
+  hipLaunchKernelGGL(core_unfold_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, core, Ra, I, Rb, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_identity_table(int R, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(identity_table_kernel, dim3(cdiv((int64_t)R * R, 256)), dim3(256), 0, s, R, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram(const double* core, int Rl, int64_t I, int Rr, double* E, hipStream_t s) {
+  const int nb = (Rl * Rr + 15) / 16;
+  hipLaunchKernelGGL(gram_kernel, dim3(cdiv((int64_t)nb * nb, 4)), dim3(256), 0, s, core, Rl, I, Rr, E);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm64(int64_t M, int64_t N, int64_t K, double alpha, MatView A, MatView B, double beta,
+                         const double* Cin, int64_t ldcin, double* C, int64_t ldc, hipStream_t s) {
+  const int64_t nblk = cdiv(M, 16) * cdiv(N, 16);
+  hipLaunchKernelGGL(gemm64_kernel, dim3(cdiv(nblk, 4)), dim3(256), 0, s, M, N, K, alpha, A, B, beta, Cin, ldcin, C,
+                     ldc);
+  return hipGetLastError();
+}
+
+hipError_t launch_realign_S(MatView W, int Ra, int Rb, double* S, hipStream_t s) {
+  const int64_t n = (int64_t)Ra * Rb * Ra * Rb;
+  hipLaunchKernelGGL(realign_S_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, W, Ra, Rb, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_chol(const double* S, int n, double* L, double* LT, double* work, int* status, hipStream_t s) {
+  const size_t bytes = (size_t)n * n * sizeof(double);
+  if (bytes <= 150 * 1024) {
+    if (bytes > 64 * 1024)
+      hipFuncSetAttribute((const void*)chol_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    hipLaunchKernelGGL(chol_kernel<true>, dim3(1), dim3(1024), bytes, s, S, n, L, LT, work, status);
+  } else {
+    hipLaunchKernelGGL(chol_kernel<false>, dim3(1), dim3(1024), 0, s, S, n, L, LT, work, status);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_chol_solve(const double* L, const double* LT, int n, const double* Rhs, int64_t I, double* G,
+                             int accumulate, const int* status, hipStream_t s) {
+  const size_t lds = 4 * (size_t)n * sizeof(double);
+  hipLaunchKernelGGL(chol_solve_kernel, dim3(cdiv(I, 4)), dim3(256), lds, s, L, LT, n, Rhs, I, G, accumulate, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_commit_core(const double* G, int64_t I, int Ra, int Rb, double* core, int* status, hipStream_t s) {
+  hipLaunchKernelGGL(commit_core_kernel, dim3(1), dim3(1024), 0, s, G, I, Ra, Rb, core, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_sumsq(const void* X, int xdt, int64_t n, double* partials, int nblk, double* out, hipStream_t s) {
+  if (xdt == TR_F64)
+    hipLaunchKernelGGL(sumsq_kernel<double>, dim3(nblk), dim3(256), 0, s, (const double*)X, n, partials);
+  else
+    hipLaunchKernelGGL(sumsq_kernel<float>, dim3(nblk), dim3(256), 0, s, (const float*)X, n, partials);
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(64), 0, s, partials, nblk, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_absmax(const void* X, int xdt, int64_t n, float* partials, int nblk, float* out, hipStream_t s) {
+  if (xdt == TR_F64)
+    hipLaunchKernelGGL(absmax_kernel<double>, dim3(nblk), dim3(256), 0, s, (const double*)X, n, partials);
+  else
+    hipLaunchKernelGGL(absmax_kernel<float>, dim3(nblk), dim3(256), 0, s, (const float*)X, n, partials);
+  hipLaunchKernelGGL(max_partials_kernel, dim3(1), dim3(64), 0, s, partials, nblk, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_table_absmax(const double* T, int64_t n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(table_absmax_kernel, dim3(1), dim3(256), 0, s, T, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_bf16(const void* X, int xdt, int64_t n, void* out, hipStream_t s) {
+  const int64_t grid = std::min<int64_t>(cdiv(n, 256), 65536);
+  if (xdt == TR_F64)
+    hipLaunchKernelGGL(to_bf16_kernel<double>, dim3(grid), dim3(256), 0, s, (const double*)X, n, (__bf16*)out);
+  else
+    hipLaunchKernelGGL(to_bf16_kernel<float>, dim3(grid), dim3(256), 0, s, (const float*)X, n, (__bf16*)out);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_fp8(const void* X, int xdt, int64_t n, const float* absmax, float* scale_out, void* out,
+                         hipStream_t s) {
+  const int64_t grid = std::min<int64_t>(cdiv(n, 256), 65536);
+  if (xdt == TR_F64)
+    hipLaunchKernelGGL(to_fp8_kernel<double>, dim3(grid), dim3(256), 0, s, (const double*)X, n, absmax, scale_out,
+                       (uint8_t*)out);
+  else
+    hipLaunchKernelGGL(to_fp8_kernel<float>, dim3(grid), dim3(256), 0, s, (const float*)X, n, absmax, scale_out,
+                       (uint8_t*)out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fit(const void* X, int xdt, int64_t I, int64_t K, const double* G0, const double* F1,
+                      const double* F2, int64_t d1, int64_t m1, int64_t d2, int64_t m2, int Rb, int Rmid, int Ra,
+                      double* partials, int nblk, double* out, hipStream_t s) {
+  const int RR4 = (Ra * Rb + 3) & ~3;
+  const int kt = RR4 > 448 ? 16 : 32;
+  const size_t lds = (size_t)kt * (RR4 + 1) * sizeof(double);
+  if (lds > 64 * 1024) {
+    hipFuncSetAttribute((const void*)fit_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipFuncSetAttribute((const void*)fit_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  }
+  if (xdt == TR_F64)
+    hipLaunchKernelGGL(fit_kernel<double>, dim3(nblk), dim3(256), lds, s, (const double*)X, I, K, G0, F1, F2, d1, m1,
+                       d2, m2, Rb, Rmid, Ra, kt, partials);
+  else
+    hipLaunchKernelGGL(fit_kernel<float>, dim3(nblk), dim3(256), lds, s, (const float*)X, I, K, G0, F1, F2, d1, m1,
+                       d2, m2, Rb, Rmid, Ra, kt, partials);
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(64), 0, s, partials, nblk, out);
+  return hipGetLastError();
+}

@@ -1,0 +1,647 @@
+// Host runtime of the TR-ALS library: context, per-mode plans, workspace, the
+// Gauss-Seidel sweep driver (Alg. 2 / Alg. 3) and the C ABI of tr_als.h.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "../../include/tr_als.h"
+
+namespace {
+
+// How mode m's subchain G^{!=m} is split into two partial-subchain tables and
+// how the contraction index k (the other modes, memory order) maps onto them.
+struct Plan {
+  int64_t I = 0, K = 0, L = 1;
+  int layout = 0;
+  std::vector<int> f1c, f2c;  // cores (0-based, chain order) of each factor
+  int64_t K1 = 1, K2 = 1, d1 = 1, m1 = 1, d2 = 1, m2 = 1;
+  int Rb = 1, Rmid = 1, Ra = 1;
+};
+
+}  // namespace
+
+struct tr_als_ctx {
+  int N = 0;
+  int64_t dims[TR_MAXN] = {0};
+  int R[TR_MAXN + 1] = {0};
+  int variant = TR_NE;
+  int xdt = TR_F32;
+  const void* X = nullptr;
+  int64_t numel = 0;
+  std::vector<double*> user_cores;
+  hipStream_t stream = nullptr;
+  double* cores[TR_MAXN] = {nullptr};
+  double* gram[TR_MAXN] = {nullptr};
+  Plan plan[TR_MAXN];
+  // workspace
+  std::vector<void*> allocs;
+  double *F1 = nullptr, *F2 = nullptr, *T0 = nullptr, *T1 = nullptr;
+  double *M = nullptr, *S = nullptr, *W0 = nullptr, *W1 = nullptr, *Lf = nullptr, *LTf = nullptr, *cholw = nullptr;
+  double *Gn = nullptr, *Res = nullptr, *G0u = nullptr;
+  void* partial = nullptr;
+  size_t partial_bytes = 0;
+  double* dpart = nullptr;
+  float* fpart = nullptr;
+  double* dscal = nullptr;   // [0] ||X||^2, [1] fit sum, [2] table max 1, [3] table max 2
+  float* fscal = nullptr;    // [0] |X| max, [1] fp8 scale
+  int* status = nullptr;
+  void* xbf16 = nullptr;
+  void* xfp8 = nullptr;
+  float fp8_scale = 1.0f;
+  double xnorm2 = 0.0;
+  int nred = 1024;
+  std::string err;
+  // profiling of the X-stream kernel
+  bool prof = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
+  double prof_ms = 0.0;
+  int64_t prof_launches = 0;
+  double prof_bytes = 0.0;
+};
+
+namespace {
+
+int fail(tr_als_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                    \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return fail(ctx, TR_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));         \
+  } while (0)
+
+int alloc(tr_als_ctx* c, void** p, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(c, TR_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  c->allocs.push_back(*p);
+  return TR_OK;
+}
+
+int64_t prod(const int64_t* d, int a, int b) {  // prod of dims[a..b)
+  int64_t p = 1;
+  for (int j = a; j < b; ++j) p *= d[j];
+  return p;
+}
+
+// Build the plan of mode m (0-based).
+Plan make_plan(const tr_als_ctx* c, int m) {
+  const int N = c->N;
+  const int* R = c->R;  // R[N] == R[0]
+  Plan p;
+  p.I = c->dims[m];
+  p.K = c->numel / p.I;
+  p.Ra = R[m];
+  p.Rb = R[m + 1];
+  if (m == 0) {
+    p.layout = 0;
+    p.L = 1;
+    if (N == 2) {
+      p.f1c = {1};
+      p.Rmid = R[2];
+    } else {
+      int best = -1;
+      int64_t bestT = 0;
+      for (int q = 1; q <= N - 2; ++q) {  // F1 = cores 1..q, F2 = cores q+1..N-1
+        const int64_t T1 = prod(c->dims, 1, q + 1), T2 = prod(c->dims, q + 1, N);
+        const int rm = R[q + 1];
+        const int64_t tb = std::max(T1, T2);
+        if (best < 0 || rm < R[best + 1] || (rm == R[best + 1] && tb < bestT)) { best = q; bestT = tb; }
+      }
+      for (int j = 1; j <= best; ++j) p.f1c.push_back(j);
+      for (int j = best + 1; j <= N - 1; ++j) p.f2c.push_back(j);
+      p.Rmid = R[best + 1];
+    }
+    p.K1 = 1;
+    for (int j : p.f1c) p.K1 *= c->dims[j];
+    p.K2 = 1;
+    for (int j : p.f2c) p.K2 *= c->dims[j];
+    p.d1 = 1; p.m1 = p.K1; p.d2 = p.K1; p.m2 = p.K2;
+  } else if (m == N - 1) {
+    p.layout = 1;
+    p.L = p.K;
+    if (N == 2) {
+      p.f1c = {0};
+      p.Rmid = R[1];
+    } else {
+      int best = -1;
+      int64_t bestT = 0;
+      for (int q = 1; q <= N - 2; ++q) {  // F1 = cores 0..q-1, F2 = cores q..N-2
+        const int64_t T1 = prod(c->dims, 0, q), T2 = prod(c->dims, q, N - 1);
+        const int rm = R[q];
+        const int64_t tb = std::max(T1, T2);
+        if (best < 0 || rm < R[best] || (rm == R[best] && tb < bestT)) { best = q; bestT = tb; }
+      }
+      for (int j = 0; j < best; ++j) p.f1c.push_back(j);
+      for (int j = best; j <= N - 2; ++j) p.f2c.push_back(j);
+      p.Rmid = R[best];
+    }
+    p.K1 = 1;
+    for (int j : p.f1c) p.K1 *= c->dims[j];
+    p.K2 = 1;
+    for (int j : p.f2c) p.K2 *= c->dims[j];
+    p.d1 = 1; p.m1 = p.K1; p.d2 = p.K1; p.m2 = p.K2;
+  } else {
+    p.layout = 1;
+    p.L = prod(c->dims, 0, m);
+    for (int j = m + 1; j < N; ++j) p.f1c.push_back(j);
+    for (int j = 0; j < m; ++j) p.f2c.push_back(j);
+    p.Rmid = R[0];
+    p.K1 = prod(c->dims, m + 1, N);
+    p.K2 = p.L;
+    p.d1 = p.L; p.m1 = p.K1; p.d2 = 1; p.m2 = p.L;
+  }
+  return p;
+}
+
+int64_t table_elems(const tr_als_ctx* c, const std::vector<int>& cl, int Rdefault) {
+  if (cl.empty()) return (int64_t)Rdefault * Rdefault;
+  int64_t K = 1;
+  for (int j : cl) K *= c->dims[j];
+  return K * c->R[cl.front()] * c->R[cl.back() + 1];
+}
+
+// Intermediate sizes of building a table chain (for the ping-pong buffers).
+int64_t table_build_max(const tr_als_ctx* c, const std::vector<int>& cl) {
+  int64_t mx = 0, J = 1;
+  for (size_t s = 0; s < cl.size(); ++s) {
+    J *= c->dims[cl[s]];
+    mx = std::max(mx, J * c->R[cl.front()] * c->R[cl[s] + 1]);
+  }
+  return mx;
+}
+
+// Table of the partial subchain of cores `cl` (chain order, first index fastest).
+int build_table(tr_als_ctx* c, const std::vector<int>& cl, int Rid, double* out) {
+  hipStream_t s = c->stream;
+  if (cl.empty()) {
+    HIPCHK(c, launch_identity_table(Rid, out, s));
+    return TR_OK;
+  }
+  const int Rl = c->R[cl.front()];
+  double* cur = (cl.size() == 1) ? out : c->T0;
+  HIPCHK(c, launch_core_to_table(c->cores[cl[0]], Rl, c->dims[cl[0]], c->R[cl[0] + 1], cur, s));
+  int64_t J = c->dims[cl[0]];
+  for (size_t q = 1; q < cl.size(); ++q) {
+    const int k = cl[q];
+    double* nxt = (q + 1 == cl.size()) ? out : (cur == c->T0 ? c->T1 : c->T0);
+    HIPCHK(c, launch_chain_step(cur, J, Rl, c->R[k], c->cores[k], c->dims[k], c->R[k + 1], nxt, s));
+    J *= c->dims[k];
+    cur = nxt;
+  }
+  return TR_OK;
+}
+
+struct XsCfg {
+  XsArgs a;
+  int kt = 64, wlay = 0;
+  size_t lds = 0;
+};
+
+// Tile / split configuration of the X-stream kernel for mode m in precision prec.
+XsCfg xs_config(const tr_als_ctx* c, int m, int prec) {
+  const Plan& p = c->plan[m];
+  XsCfg x;
+  XsArgs& a = x.a;
+  a.I = p.I; a.K = p.K; a.L = p.L; a.layout = p.layout;
+  a.F1 = c->F1; a.F2 = c->F2;
+  a.d1 = p.d1; a.m1 = p.m1; a.d2 = p.d2; a.m2 = p.m2;
+  a.Rb = p.Rb; a.Rmid = p.Rmid; a.Ra = p.Ra;
+  a.bscale = 1.0f;
+  a.partial = c->partial;
+  if (p.I <= 128) { a.MT = (int)((p.I + 15) / 16 * 16); a.n_mt = 1; }
+  else { a.MT = 128; a.n_mt = (int)((p.I + 127) / 128); }
+  if (p.Ra * p.Rb <= 128) { a.NTb = p.Rb; a.NT = (p.Ra * p.Rb + 15) / 16 * 16; a.n_nt = 1; }
+  else {
+    a.NTb = std::max(4, (128 / p.Ra) / 4 * 4);
+    a.NT = (p.Ra * a.NTb + 15) / 16 * 16;
+    a.n_nt = (p.Rb + a.NTb - 1) / a.NTb;
+  }
+  // K tile: the largest that leaves room for >= 3 workgroups per CU, else the
+  // largest that fits the 160 KB of LDS (x.lds == 0 marks "does not fit")
+  const int cand_f64[2] = {32, 16}, cand_lo[2] = {64, 32};
+  const int* cand = (prec == TR_F64) ? cand_f64 : cand_lo;
+  x.kt = 0;
+  for (int pass = 0; pass < 2 && x.kt == 0; ++pass)
+    for (int q = 0; q < 2; ++q)
+      if (xstream_lds_bytes(a, prec, cand[q]) <= (pass == 0 ? 52u : 160u) * 1024u) { x.kt = cand[q]; break; }
+  x.lds = x.kt ? xstream_lds_bytes(a, prec, x.kt) : 0;
+  if (!x.kt) x.kt = cand[1];
+  // wave arrangement
+  const int MB = a.MT / 16, NB = a.NT / 16;
+  struct Opt { int wgm, wgn, wm, wn, lay; } opts[3] = {{2, 2, 4, 4, 0}, {1, 4, 8, 2, 1}, {4, 1, 2, 8, 2}};
+  int best = -1, bestv = 1 << 30;
+  for (int o = 0; o < 3; ++o) {
+    const int pm = (MB + opts[o].wgm - 1) / opts[o].wgm, pn = (NB + opts[o].wgn - 1) / opts[o].wgn;
+    if (pm > opts[o].wm || pn > opts[o].wn) continue;
+    const int v = pm * pn;
+    if (v < bestv) { bestv = v; best = o; }
+  }
+  a.wgm = opts[best].wgm; a.wgn = opts[best].wgn; x.wlay = opts[best].lay;
+  // split-K
+  const int64_t ktiles = (p.K + x.kt - 1) / x.kt;
+  const int64_t ntiles = (int64_t)a.n_mt * a.n_nt;
+  int64_t nsplit = std::max<int64_t>(1, (768 + ntiles - 1) / ntiles);
+  nsplit = std::min<int64_t>(nsplit, std::max<int64_t>(1, ktiles / 4));
+  const int64_t tps = (ktiles + nsplit - 1) / nsplit;
+  a.k_per_split = tps * x.kt;
+  a.nsplit = (int)((p.K + a.k_per_split - 1) / a.k_per_split);
+  return x;
+}
+
+size_t partial_bytes_needed(const XsCfg& x, int prec) {
+  return (size_t)x.a.nsplit * x.a.n_mt * x.a.n_nt * x.a.MT * x.a.NT * (prec == TR_F64 ? 8 : 4);
+}
+
+int ensure_shadow(tr_als_ctx* c, int prec) {
+  hipStream_t s = c->stream;
+  if (prec == TR_BF16 && !c->xbf16) {
+    int rc = alloc(c, &c->xbf16, (size_t)c->numel * 2);
+    if (rc) return rc;
+    HIPCHK(c, launch_to_bf16(c->X, c->xdt, c->numel, c->xbf16, s));
+  }
+  if (prec == TR_FP8 && !c->xfp8) {
+    int rc = alloc(c, &c->xfp8, (size_t)c->numel);
+    if (rc) return rc;
+    HIPCHK(c, launch_absmax(c->X, c->xdt, c->numel, c->fpart, c->nred, c->fscal, s));
+    HIPCHK(c, launch_to_fp8(c->X, c->xdt, c->numel, c->fscal, c->fscal + 1, c->xfp8, s));
+    HIPCHK(c, hipMemcpyAsync(&c->fp8_scale, c->fscal + 1, sizeof(float), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+  }
+  return TR_OK;
+}
+
+// M_n = X_[n] G^{!=n}_[2] for the context's current cores (tables + X stream +
+// ordered split-K reduction).
+int compute_mttsp(tr_als_ctx* c, int m, int prec, double* Mout) {
+  hipStream_t s = c->stream;
+  const Plan& p = c->plan[m];
+  int rc = build_table(c, p.f1c, p.Rmid, c->F1);
+  if (rc) return rc;
+  rc = build_table(c, p.f2c, p.Rmid, c->F2);
+  if (rc) return rc;
+  rc = ensure_shadow(c, prec);
+  if (rc) return rc;
+  XsCfg x = xs_config(c, m, prec);
+  if (x.lds == 0) return fail(c, TR_EINVAL, "ranks too large for the LDS tiles of the X stream");
+  if (partial_bytes_needed(x, prec) > c->partial_bytes) return fail(c, TR_EHIP, "internal: partial buffer too small");
+  double out_scale = 1.0;
+  if (prec == TR_BF16) x.a.X = c->xbf16;
+  else if (prec == TR_FP8) {
+    x.a.X = c->xfp8;
+    // scale the generated subchain rows into the E4M3 range using a bound of
+    // max|F1 F2| <= Rmid * max|F1| * max|F2|
+    const int64_t n1 = table_elems(c, p.f1c, p.Rmid), n2 = table_elems(c, p.f2c, p.Rmid);
+    HIPCHK(c, launch_table_absmax(c->F1, n1, c->dscal + 2, s));
+    HIPCHK(c, launch_table_absmax(c->F2, n2, c->dscal + 3, s));
+    double tm[2];
+    HIPCHK(c, hipMemcpyAsync(tm, c->dscal + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    double bound = tm[0] * tm[1] * p.Rmid;
+    double bs = bound > 0 ? 448.0 / bound : 1.0;
+    bs = std::ldexp(1.0, (int)std::floor(std::log2(bs)));  // power of two: exact rescale
+    x.a.bscale = (float)bs;
+    out_scale = 1.0 / ((double)c->fp8_scale * bs);
+  } else x.a.X = c->X;
+  const bool prof = c->prof;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (prof) {
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    HIPCHK(c, hipEventRecord(e0, s));
+  }
+  HIPCHK(c, launch_xstream(x.a, prec, (prec == TR_F64 || prec == TR_F32) ? c->xdt : prec, x.kt, x.wlay, x.lds, s));
+  if (prof) {
+    HIPCHK(c, hipEventRecord(e1, s));
+    c->evs.push_back({e0, e1});
+    const double eb = prec == TR_F64 ? (c->xdt == TR_F64 ? 8 : 4) : prec == TR_F32 ? (c->xdt == TR_F64 ? 8 : 4)
+                    : prec == TR_BF16 ? 2 : 1;
+    c->prof_bytes = eb * (double)c->numel;
+  }
+  HIPCHK(c, launch_xs_reduce(x.a, prec, out_scale, Mout, c->status, s));
+  return TR_OK;
+}
+
+// S_n<2> from the Gram ring: W = K_{m+1} K_{m+2} ... K_{m-1} (Kronecker-order
+// Grams), then realigned.
+int compute_coef(tr_als_ctx* c, int m, double* Sout) {
+  hipStream_t s = c->stream;
+  const int N = c->N;
+  std::vector<int> chain;
+  for (int k = 1; k < N; ++k) chain.push_back((m + k) % N);
+  auto gview = [&](int k) {
+    MatView v;
+    v.p = c->gram[k]; v.ld = 0; v.kind = 1; v.Rl = c->R[k]; v.Rr = c->R[k + 1];
+    return v;
+  };
+  MatView W = gview(chain[0]);
+  double* bufs[2] = {c->W0, c->W1};
+  int cur = 0;
+  int64_t rows = (int64_t)c->R[chain[0]] * c->R[chain[0]];
+  for (size_t q = 1; q < chain.size(); ++q) {
+    const int k = chain[q];
+    const int64_t inner = (int64_t)c->R[k] * c->R[k];
+    const int64_t cols = (int64_t)c->R[k + 1] * c->R[k + 1];
+    MatView B = gview(k);
+    HIPCHK(c, launch_gemm64(rows, cols, inner, 1.0, W, B, 0.0, nullptr, 0, bufs[cur], rows, s));
+    W.p = bufs[cur]; W.ld = rows; W.kind = 0;
+    cur ^= 1;
+  }
+  HIPCHK(c, launch_realign_S(W, c->R[m], c->R[m + 1], Sout, s));
+  return TR_OK;
+}
+
+int update_mode_ne(tr_als_ctx* c, int m, int prec, int refine) {
+  hipStream_t s = c->stream;
+  const Plan& p = c->plan[m];
+  const int n = p.Ra * p.Rb;
+  int rc = compute_mttsp(c, m, prec, c->M);
+  if (rc) return rc;
+  rc = compute_coef(c, m, c->S);
+  if (rc) return rc;
+  HIPCHK(c, launch_chol(c->S, n, c->Lf, c->LTf, c->cholw, c->status, s));
+  HIPCHK(c, launch_chol_solve(c->Lf, c->LTf, n, c->M, p.I, c->Gn, 0, c->status, s));
+  for (int r = 0; r < refine; ++r) {
+    MatView G{c->Gn, p.I, 0, 0, 0}, Sv{c->S, n, 0, 0, 0};
+    HIPCHK(c, launch_gemm64(p.I, n, n, -1.0, G, Sv, 1.0, c->M, p.I, c->Res, p.I, s));
+    HIPCHK(c, launch_chol_solve(c->Lf, c->LTf, n, c->Res, p.I, c->Gn, 1, c->status, s));
+  }
+  HIPCHK(c, launch_commit_core(c->Gn, p.I, p.Ra, p.Rb, c->cores[m], c->status, s));
+  HIPCHK(c, launch_gram(c->cores[m], c->R[m], c->dims[m], c->R[m + 1], c->gram[m], s));
+  return TR_OK;
+}
+
+int read_status(tr_als_ctx* c) {
+  int st = 0;
+  HIPCHK(c, hipMemcpyAsync(&st, c->status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->prof) {
+    for (auto& e : c->evs) {
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess) { c->prof_ms += ms; c->prof_launches++; }
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+    c->evs.clear();
+  }
+  if (st == 0) return TR_OK;
+  // the context stays usable: clear the latched word for the next call
+  HIPCHK(c, hipMemsetAsync(c->status, 0, sizeof(int), c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (st & ST_NONFINITE) return fail(c, TR_ENONFINITE, "non-finite value in M_n or in an updated core");
+  return fail(c, TR_ESINGULAR, "coefficient matrix not positive definite (or zero pivot)");
+}
+
+int store_cores(tr_als_ctx* c) {
+  for (int k = 0; k < c->N; ++k) {
+    const size_t bytes = (size_t)c->R[k] * c->dims[k] * c->R[k + 1] * sizeof(double);
+    HIPCHK(c, hipMemcpyAsync(c->user_cores[k], c->cores[k], bytes, hipMemcpyDeviceToDevice, c->stream));
+  }
+  return TR_OK;
+}
+
+int valid_ctx(const tr_als_ctx* c) { return c != nullptr && c->N >= 2; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* tr_als_strerror(int status) {
+  switch (status) {
+    case TR_OK: return "ok";
+    case TR_EINVAL: return "invalid argument";
+    case TR_ENOMEM: return "out of device memory";
+    case TR_EHIP: return "HIP runtime error";
+    case TR_ESINGULAR: return "singular coefficient matrix";
+    case TR_ENONFINITE: return "non-finite value";
+    default: return "unknown status";
+  }
+}
+
+const char* tr_als_last_error(const tr_als_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int tr_als_destroy(tr_als_ctx* ctx) {
+  if (!ctx) return TR_OK;
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  for (auto& e : ctx->evs) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+  for (void* p : ctx->allocs) (void)hipFree(p);
+  delete ctx;
+  return TR_OK;
+}
+
+int tr_als_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ranks, const void* X, int x_dtype,
+                double* const* cores, int variant, void* hip_stream) {
+  if (!out) return TR_EINVAL;
+  *out = nullptr;
+  if (N < 2 || N > TR_MAXN || !dims || !ranks || !X || !cores) return TR_EINVAL;
+  if (x_dtype != TR_F64 && x_dtype != TR_F32) return TR_EINVAL;
+  if (variant != TR_NE && variant != TR_QR) return TR_EINVAL;
+  int64_t numel = 1;
+  for (int k = 0; k < N; ++k) {
+    if (dims[k] < 1 || ranks[k] < 1 || ranks[k] > TR_MAXR) return TR_EINVAL;
+    if (numel > (int64_t(1) << 62) / dims[k]) return TR_EINVAL;
+    numel *= dims[k];
+    if (!cores[k]) return TR_EINVAL;
+  }
+  tr_als_ctx* c = new tr_als_ctx();
+  c->N = N;
+  for (int k = 0; k < N; ++k) { c->dims[k] = dims[k]; c->R[k] = (int)ranks[k]; }
+  c->R[N] = c->R[0];
+  c->variant = variant;
+  c->xdt = x_dtype;
+  c->X = X;
+  c->numel = numel;
+  c->stream = (hipStream_t)hip_stream;
+  c->user_cores.assign(cores, cores + N);
+  for (int m = 0; m < N; ++m) c->plan[m] = make_plan(c, m);
+
+  // workspace sizes
+  int64_t maxI = 0, maxRR = 0, maxF = 0, maxT = 0, maxW = 0;
+  for (int k = 0; k < N; ++k) {
+    maxI = std::max<int64_t>(maxI, dims[k]);
+    maxRR = std::max<int64_t>(maxRR, (int64_t)c->R[k] * c->R[k + 1]);
+    maxW = std::max<int64_t>(maxW, (int64_t)c->R[k] * c->R[k] * c->R[k + 1] * c->R[k + 1]);
+  }
+  for (int m = 0; m < N; ++m) {
+    const Plan& p = c->plan[m];
+    maxF = std::max(maxF, std::max(table_elems(c, p.f1c, p.Rmid), table_elems(c, p.f2c, p.Rmid)));
+    maxT = std::max(maxT, std::max(table_build_max(c, p.f1c), table_build_max(c, p.f2c)));
+  }
+  size_t pbytes = 0;
+  int rc = TR_OK;
+  auto A = [&](void** p, size_t b) { if (rc == TR_OK) rc = alloc(c, p, b); };
+  for (int k = 0; k < N; ++k) {
+    A((void**)&c->cores[k], (size_t)c->R[k] * dims[k] * c->R[k + 1] * 8);
+    A((void**)&c->gram[k], (size_t)c->R[k] * c->R[k + 1] * c->R[k] * c->R[k + 1] * 8);
+  }
+  A((void**)&c->F1, (size_t)maxF * 8);
+  A((void**)&c->F2, (size_t)maxF * 8);
+  A((void**)&c->T0, (size_t)maxT * 8);
+  A((void**)&c->T1, (size_t)maxT * 8);
+  A((void**)&c->M, (size_t)maxI * maxRR * 8);
+  A((void**)&c->Gn, (size_t)maxI * maxRR * 8);
+  A((void**)&c->Res, (size_t)maxI * maxRR * 8);
+  A((void**)&c->G0u, (size_t)maxI * maxRR * 8);
+  A((void**)&c->S, (size_t)maxRR * maxRR * 8);
+  A((void**)&c->Lf, (size_t)maxRR * maxRR * 8);
+  A((void**)&c->LTf, (size_t)maxRR * maxRR * 8);
+  A((void**)&c->cholw, (size_t)maxRR * maxRR * 8);
+  A((void**)&c->W0, (size_t)maxW * 8);
+  A((void**)&c->W1, (size_t)maxW * 8);
+  A((void**)&c->dpart, (size_t)c->nred * 8);
+  A((void**)&c->fpart, (size_t)c->nred * 4);
+  A((void**)&c->dscal, 8 * 8);
+  A((void**)&c->fscal, 8 * 4);
+  A((void**)&c->status, 16);
+  if (rc) { std::string e = c->err; tr_als_destroy(c); (void)e; return rc; }
+  for (int m = 0; m < N; ++m)
+    for (int prec = TR_F64; prec <= TR_FP8; ++prec) {
+      XsCfg x = xs_config(c, m, prec);
+      pbytes = std::max(pbytes, partial_bytes_needed(x, prec));
+    }
+  A(&c->partial, pbytes);
+  c->partial_bytes = pbytes;
+  if (rc) { tr_als_destroy(c); return rc; }
+
+  hipStream_t s = c->stream;
+  auto hipfail = [&](hipError_t e, const char* what) {
+    if (e == hipSuccess) return false;
+    c->err = std::string(what) + ": " + hipGetErrorString(e);
+    return true;
+  };
+  if (hipfail(hipMemsetAsync(c->status, 0, 16, s), "memset")) { tr_als_destroy(c); return TR_EHIP; }
+  for (int k = 0; k < N; ++k) {
+    const size_t bytes = (size_t)c->R[k] * dims[k] * c->R[k + 1] * 8;
+    if (hipfail(hipMemcpyAsync(c->cores[k], cores[k], bytes, hipMemcpyDeviceToDevice, s), "copy cores") ||
+        hipfail(launch_gram(c->cores[k], c->R[k], dims[k], c->R[k + 1], c->gram[k], s), "gram")) {
+      tr_als_destroy(c);
+      return TR_EHIP;
+    }
+  }
+  if (hipfail(launch_sumsq(X, x_dtype, numel, c->dpart, c->nred, c->dscal, s), "sumsq") ||
+      hipfail(hipMemcpyAsync(&c->xnorm2, c->dscal, 8, hipMemcpyDeviceToHost, s), "copy norm") ||
+      hipfail(hipStreamSynchronize(s), "sync")) {
+    tr_als_destroy(c);
+    return TR_EHIP;
+  }
+  *out = c;
+  return TR_OK;
+}
+
+static int update_mode(tr_als_ctx* c, int m, int prec, int refine) {
+  if (c->variant == TR_QR) return fail(c, TR_EINVAL, "QR variant not available in this build");
+  return update_mode_ne(c, m, prec, refine);
+}
+
+int tr_als_sweep(tr_als_ctx* c, int nsweeps, int prec, int refine) {
+  if (!valid_ctx(c)) return TR_EINVAL;
+  if (nsweeps < 0 || prec < TR_F64 || prec > TR_FP8 || refine < 0 || refine > 4)
+    return fail(c, TR_EINVAL, "bad sweep arguments");
+  c->err.clear();
+  for (int sw = 0; sw < nsweeps; ++sw)
+    for (int m = 0; m < c->N; ++m) {
+      int rc = update_mode(c, m, prec, refine);
+      if (rc) return rc;
+    }
+  int rc = read_status(c);
+  // cores written back in either case: on error they hold the last good update
+  int rc2 = store_cores(c);
+  if (rc2) return rc2;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return rc;
+}
+
+int tr_als_update_mode(tr_als_ctx* c, int n, int prec, int refine) {
+  if (!valid_ctx(c) || n < 1 || n > c->N || prec < TR_F64 || prec > TR_FP8 || refine < 0 || refine > 4)
+    return c ? fail(c, TR_EINVAL, "bad arguments") : TR_EINVAL;
+  int rc = update_mode(c, n - 1, prec, refine);
+  if (rc) return rc;
+  return read_status(c);
+}
+
+int tr_als_store_cores(tr_als_ctx* c) {
+  if (!valid_ctx(c)) return TR_EINVAL;
+  int rc = store_cores(c);
+  if (rc) return rc;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return TR_OK;
+}
+
+int tr_als_mttsp(tr_als_ctx* c, int n, int prec, double* Mout) {
+  if (!valid_ctx(c) || n < 1 || n > c->N || prec < TR_F64 || prec > TR_FP8 || !Mout)
+    return c ? fail(c, TR_EINVAL, "bad arguments") : TR_EINVAL;
+  int rc = compute_mttsp(c, n - 1, prec, Mout);
+  if (rc) return rc;
+  return read_status(c);
+}
+
+int tr_als_coef(tr_als_ctx* c, int n, double* Sout) {
+  if (!valid_ctx(c) || n < 1 || n > c->N || !Sout) return c ? fail(c, TR_EINVAL, "bad arguments") : TR_EINVAL;
+  int rc = compute_coef(c, n - 1, Sout);
+  if (rc) return rc;
+  return read_status(c);
+}
+
+int tr_als_gram(tr_als_ctx* c, int k, double* Eout) {
+  if (!valid_ctx(c) || k < 1 || k > c->N || !Eout) return c ? fail(c, TR_EINVAL, "bad arguments") : TR_EINVAL;
+  const int m = k - 1;
+  const size_t n = (size_t)c->R[m] * c->R[m + 1];
+  HIPCHK(c, hipMemcpyAsync(Eout, c->gram[m], n * n * 8, hipMemcpyDeviceToDevice, c->stream));
+  return read_status(c);
+}
+
+int tr_als_xnorm2(const tr_als_ctx* c, double* out) {
+  if (!c || !out) return TR_EINVAL;
+  *out = c->xnorm2;
+  return TR_OK;
+}
+
+int tr_als_fit(tr_als_ctx* c, double* rel_err) {
+  if (!valid_ctx(c) || !rel_err) return c ? fail(c, TR_EINVAL, "bad arguments") : TR_EINVAL;
+  hipStream_t s = c->stream;
+  const Plan& p = c->plan[0];
+  int rc = build_table(c, p.f1c, p.Rmid, c->F1);
+  if (rc) return rc;
+  rc = build_table(c, p.f2c, p.Rmid, c->F2);
+  if (rc) return rc;
+  HIPCHK(c, launch_core_unfold(c->cores[0], p.Ra, p.I, p.Rb, c->G0u, s));
+  HIPCHK(c, launch_fit(c->X, c->xdt, p.I, p.K, c->G0u, c->F1, c->F2, p.d1, p.m1, p.d2, p.m2, p.Rb, p.Rmid, p.Ra,
+                       c->dpart, c->nred, c->dscal + 1, s));
+  double ss = 0.0;
+  HIPCHK(c, hipMemcpyAsync(&ss, c->dscal + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  *rel_err = c->xnorm2 > 0 ? std::sqrt(std::max(0.0, ss)) / std::sqrt(c->xnorm2) : 0.0;
+  return read_status(c);
+}
+
+int tr_als_profile_enable(tr_als_ctx* c, int enable) {
+  if (!valid_ctx(c)) return TR_EINVAL;
+  c->prof = enable != 0;
+  c->prof_ms = 0.0;
+  c->prof_launches = 0;
+  return TR_OK;
+}
+
+int tr_als_profile_read(tr_als_ctx* c, double* ms, int64_t* launches, double* bytes_per_launch) {
+  if (!valid_ctx(c) || !ms || !launches || !bytes_per_launch) return TR_EINVAL;
+  *ms = c->prof_ms;
+  *launches = c->prof_launches;
+  *bytes_per_launch = c->prof_bytes;
+  return TR_OK;
+}
+
+}  // extern "C"
