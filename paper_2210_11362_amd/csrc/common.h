@@ -40,7 +40,32 @@ struct XsArgs {
   void* partial;      // [nsplit][n_mt*n_nt][MT][NT] FP32 (FP64 for the FP64 path)
 };
 
+// Arguments of the two-stage MTTSP's stage 1: Y[r, c] = sum_k A[r, k] B[k, c]
+// with A = X as a matrix (nn: A[r,k] = X[r + M*k]; else A[r,k] = X[k + K*r])
+// and B stored transposed (Bt[c*ldb + k], zero-padded to n_nt*NT rows).
+struct XgArgs {
+  const void* X;
+  int64_t M, K;
+  int C;              // columns of Y (bond pairs)
+  int nn;             // 1: group = slowest modes; 0: group = fastest modes
+  int vec_ok;         // rows of A start 16-byte aligned (K-contiguous case)
+  int MT, NT, n_mt, n_nt;
+  const void* Bt;
+  int64_t ldb;
+  int64_t k_per_split;
+  int nsplit;
+  void* partial;      // [nsplit][n_mt*n_nt][MT][NT] FP32 (FP64 for the FP64 path)
+};
+
 // Host-side launchers (defined in the .hip files).
+int xgemm_kt(int prec);
+hipError_t launch_xgemm(const XgArgs& g, int prec, int xdt, hipStream_t s);
+hipError_t launch_xg_reduce(const XgArgs& g, int prec, double out_scale, double* Y, int* status, hipStream_t s);
+hipError_t launch_table_to_bt(const double* T, int64_t K, int C, int Crows, int64_t ldb, int prec, double scale,
+                              void* Bt, hipStream_t s);
+hipError_t launch_absorb(const double* Y, int64_t lo, int64_t I, int64_t hi, int Ru, int Rc, const double* core,
+                         int Rl, int Rr, int side, int final_out, double* out, hipStream_t s);
+hipError_t launch_bond_to_M(const double* Y, int64_t In, int Ru, int Rc, double* M, hipStream_t s);
 hipError_t launch_xstream(const XsArgs& a, int prec, int xdt, int kt, int wlay, size_t lds, hipStream_t s);
 size_t xstream_lds_bytes(const XsArgs& a, int prec, int kt);
 hipError_t launch_xs_reduce(const XsArgs& a, int prec, double out_scale, double* M, int* status, hipStream_t s);
@@ -52,17 +77,26 @@ hipError_t launch_identity_table(int R, double* out, hipStream_t s);
 hipError_t launch_core_unfold(const double* core, int Ra, int64_t I, int Rb, double* out, hipStream_t s);
 hipError_t launch_gram(const double* core, int Rl, int64_t I, int Rr, double* E, hipStream_t s);
 
-// Generic FP64 operand view for the small GEMMs: plain column-major matrix, or
-// a Gram E (RlRr x RlRr) read in Kronecker order:
+// Generic FP64 operand view for the small GEMMs: plain column-major matrix
+// (kind 0), its transpose (kind 2), or a Gram E (RlRr x RlRr) read in Kronecker
+// order (kind 1):
 //   K[(b + Rl*b'), (c + Rr*c')] = E[(b + Rl*c) + RlRr*(b' + Rl*c')].
 struct MatView { const double* p; int64_t ld; int kind; int Rl, Rr; };
 hipError_t launch_gemm64(int64_t M, int64_t N, int64_t K, double alpha, MatView A, MatView B, double beta,
-                         const double* Cin, int64_t ldcin, double* C, int64_t ldc, hipStream_t s);
+                         const double* Cin, int64_t ldcin, double* C, int64_t ldc, hipStream_t s,
+                         int* finite_status = nullptr);
 hipError_t launch_realign_S(MatView W, int Ra, int Rb, double* S, hipStream_t s);
 hipError_t launch_chol(const double* S, int n, double* L, double* LT, double* work, int* status, hipStream_t s);
+bool solve_in_lds(int n);
+hipError_t launch_chol_lds(const double* S, int n, double* L, double* LT, double* rdiag, int* status, hipStream_t s);
+hipError_t launch_trsm_rhs(const double* L, const double* rdiag, int n, const double* Rhs, int64_t I, double* G,
+                           int accumulate, const int* status, hipStream_t s);
+hipError_t launch_chol_inv(const double* S, int n, double* L, double* LT, double* LinvT, double* work, int* status,
+                           hipStream_t s);
 hipError_t launch_chol_solve(const double* L, const double* LT, int n, const double* Rhs, int64_t I,
                              double* G, int accumulate, const int* status, hipStream_t s);
-hipError_t launch_commit_core(const double* G, int64_t I, int Ra, int Rb, double* core, int* status, hipStream_t s);
+hipError_t launch_commit_core(const double* G, int64_t I, int Ra, int Rb, double* core, int* status, hipStream_t s,
+                              bool checked = false);
 hipError_t launch_sumsq(const void* X, int xdt, int64_t n, double* partials, int nblk, double* out, hipStream_t s);
 hipError_t launch_absmax(const void* X, int xdt, int64_t n, float* partials, int nblk, float* out, hipStream_t s);
 hipError_t launch_to_bf16(const void* X, int xdt, int64_t n, void* out, hipStream_t s);

@@ -64,26 +64,34 @@ __global__ void identity_table_kernel(int R, double* out) {
 // G_(2)[i, a + Rl*b] = core[a + Rl*(i + I*b)].  One wave per 16x16 block.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void gram_kernel(const double* core, int Rl, int64_t I, int Rr, double* E) {
+  // one 16x16 block of E per workgroup; the 4 waves split the i range
+  __shared__ double red[4][64][4];
   const int RR = Rl * Rr;
   const int nb = (RR + 15) / 16;
-  const int lane = threadIdx.x & 63;
-  const int blk = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (blk >= nb * nb) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int blk = blockIdx.x;
   const int bp = blk % nb, bq = blk / nb;
   const int p = bp * 16 + (lane & 15), q = bq * 16 + (lane & 15);
   const bool pok = p < RR, qok = q < RR;
   const int64_t offp = pok ? (p % Rl) + (int64_t)Rl * I * (p / Rl) : 0;
   const int64_t offq = qok ? (q % Rl) + (int64_t)Rl * I * (q / Rl) : 0;
+  const int64_t nst = (I + 3) / 4;
+  const int64_t s0 = nst * wave / 4, s1 = nst * (wave + 1) / 4;
   f64x4 acc = {0, 0, 0, 0};
-  for (int64_t i0 = 0; i0 < I; i0 += 4) {
-    const int64_t i = i0 + (lane >> 4);
+  for (int64_t st = s0; st < s1; ++st) {
+    const int64_t i = st * 4 + (lane >> 4);
     const double av = (pok && i < I) ? core[offp + Rl * i] : 0.0;
     const double bv = (qok && i < I) ? core[offq + Rl * i] : 0.0;
     mma64(acc, av, bv);
   }
-  for (int v = 0; v < 4; ++v) {
-    const int row = bp * 16 + (lane >> 4) + 4 * v, col = bq * 16 + (lane & 15);
-    if (row < RR && col < RR) E[row + (int64_t)RR * col] = acc[v];
+  for (int v = 0; v < 4; ++v) red[wave][lane][v] = acc[v];
+  __syncthreads();
+  if (wave == 0) {
+    for (int v = 0; v < 4; ++v) {
+      const int row = bp * 16 + (lane >> 4) + 4 * v, col = bq * 16 + (lane & 15);
+      const double x = (red[0][lane][v] + red[1][lane][v]) + (red[2][lane][v] + red[3][lane][v]);
+      if (row < RR && col < RR) E[row + (int64_t)RR * col] = x;
+    }
   }
 }
 
@@ -92,6 +100,7 @@ __global__ __launch_bounds__(256) void gram_kernel(const double* core, int Rl, i
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double view_at(const MatView& v, int64_t r, int64_t c) {
   if (v.kind == 0) return v.p[r + v.ld * c];
+  if (v.kind == 2) return v.p[c + v.ld * r];
   const int Rl = v.Rl, Rr = v.Rr;
   const int64_t b = r % Rl, b2 = r / Rl, cc = c % Rr, c2 = c / Rr;
   return v.p[(b + Rl * cc) + (int64_t)Rl * Rr * (b2 + Rl * c2)];
@@ -99,26 +108,35 @@ __device__ __forceinline__ double view_at(const MatView& v, int64_t r, int64_t c
 
 __global__ __launch_bounds__(256) void gemm64_kernel(int64_t M, int64_t N, int64_t K, double alpha, MatView A,
                                                      MatView B, double beta, const double* Cin, int64_t ldcin,
-                                                     double* C, int64_t ldc) {
-  const int lane = threadIdx.x & 63;
-  const int64_t nbm = (M + 15) / 16, nbn = (N + 15) / 16;
-  const int64_t blk = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (blk >= nbm * nbn) return;
+                                                     double* C, int64_t ldc, int* finite_status) {
+  // one 16x16 block of C per workgroup; the 4 waves split the K range
+  __shared__ double red[4][64][4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t nbm = (M + 15) / 16;
+  const int64_t blk = blockIdx.x;
   const int64_t bm = blk % nbm, bn = blk / nbm;
   const int64_t r = bm * 16 + (lane & 15), c = bn * 16 + (lane & 15);
+  const int64_t nst = (K + 3) / 4;
+  const int64_t s0 = nst * wave / 4, s1 = nst * (wave + 1) / 4;
   f64x4 acc = {0, 0, 0, 0};
-  for (int64_t k0 = 0; k0 < K; k0 += 4) {
-    const int64_t k = k0 + (lane >> 4);
+#pragma unroll 4
+  for (int64_t st = s0; st < s1; ++st) {
+    const int64_t k = st * 4 + (lane >> 4);
     const double av = (r < M && k < K) ? view_at(A, r, k) : 0.0;
     const double bv = (k < K && c < N) ? view_at(B, k, c) : 0.0;
     mma64(acc, av, bv);
   }
-  for (int v = 0; v < 4; ++v) {
-    const int64_t row = bm * 16 + (lane >> 4) + 4 * v, col = bn * 16 + (lane & 15);
-    if (row < M && col < N) {
-      double x = alpha * acc[v];
-      if (beta != 0.0) x += beta * Cin[row + ldcin * col];
-      C[row + ldc * col] = x;
+  for (int v = 0; v < 4; ++v) red[wave][lane][v] = acc[v];
+  __syncthreads();
+  if (wave == 0) {
+    for (int v = 0; v < 4; ++v) {
+      const int64_t row = bm * 16 + (lane >> 4) + 4 * v, col = bn * 16 + (lane & 15);
+      if (row < M && col < N) {
+        double x = alpha * ((red[0][lane][v] + red[1][lane][v]) + (red[2][lane][v] + red[3][lane][v]));
+        if (beta != 0.0) x += beta * Cin[row + ldcin * col];
+        C[row + ldc * col] = x;
+        if (finite_status && !isfinite(x)) atomicOr(finite_status, ST_NONFINITE);
+      }
     }
   }
 }
@@ -178,6 +196,123 @@ __global__ __launch_bounds__(1024) void chol_kernel(const double* S, int n, doub
   }
 }
 
+// Cholesky S = L L^T and the triangular inverse Linv = L^{-1} in one
+// workgroup of 1024 threads, the lower triangle held in registers (EPT packed
+// elements per thread, n(n+1)/2 <= 1024*EPT).  Columns are broadcast through
+// LDS; a non-positive or non-finite pivot latches ST_SINGULAR.  Writes L, L^T
+// and Linv^T (all column-major, zero above/below the triangle).
+template <int EPT>
+__global__ __launch_bounds__(1024) void chol_inv_reg_kernel(const double* S, int n, double* L, double* LT,
+                                                            double* LinvT, int* status) {
+  __shared__ double colv[2][256];
+  __shared__ double rowv[2][256];
+  __shared__ double diag[256];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  const int ntri = n * (n + 1) / 2;
+  double a[EPT], x[EPT];
+  int ij[EPT];  // i | (j << 16), or -1 when the slot is unused
+  {
+    // packed column-major lower triangle: column j holds rows j..n-1
+    int j = 0, off = 0;
+#pragma unroll
+    for (int r = 0; r < EPT; ++r) {
+      const int e = tid + 1024 * r;
+      ij[r] = -1; a[r] = 0.0; x[r] = 0.0;
+      if (e < ntri) {
+        while (off + (n - j) <= e) { off += n - j; ++j; }
+        const int i = j + (e - off);
+        ij[r] = i | (j << 16);
+        a[r] = S[i + (int64_t)n * j];
+        x[r] = (i == j) ? 1.0 : 0.0;
+      }
+    }
+  }
+  if (tid == 0) bad = (*status != 0);
+  __syncthreads();
+  if (bad) return;
+#define IOF(r) (ij[r] & 0xffff)
+#define JOF(r) (ij[r] >> 16)
+  // ---- Cholesky, right-looking ----
+  for (int k = 0; k < n; ++k) {
+    const int kk = k | (k << 16);
+#pragma unroll
+    for (int r = 0; r < EPT; ++r)
+      if (ij[r] == kk) {
+        const double d = a[r];
+        if (!(d > 0.0) || !isfinite(d)) bad = 1;
+        else { a[r] = sqrt(d); diag[k] = a[r]; }
+      }
+    __syncthreads();
+    if (bad) {
+      if (tid == 0) atomicOr(status, ST_SINGULAR);
+      return;
+    }
+    const double piv = diag[k];
+    double* col = colv[k & 1];
+#pragma unroll
+    for (int r = 0; r < EPT; ++r)
+      if (ij[r] >= 0 && JOF(r) == k && IOF(r) > k) { a[r] /= piv; col[IOF(r)] = a[r]; }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < EPT; ++r)
+      if (ij[r] >= 0 && JOF(r) > k) a[r] -= col[IOF(r)] * col[JOF(r)];
+  }
+  __syncthreads();
+  // ---- Linv = L^{-1}: for k, scale row k of X by 1/L_kk, then X[i,:] -= L_ik X[k,:] (i > k) ----
+  for (int k = 0; k < n; ++k) {
+    double* col = colv[k & 1];
+    double* row = rowv[k & 1];
+    const double inv = 1.0 / diag[k];
+#pragma unroll
+    for (int r = 0; r < EPT; ++r) {
+      if (ij[r] >= 0 && IOF(r) == k) { x[r] *= inv; row[JOF(r)] = x[r]; }
+      if (ij[r] >= 0 && JOF(r) == k && IOF(r) > k) col[IOF(r)] = a[r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < EPT; ++r)
+      if (ij[r] >= 0 && IOF(r) > k && JOF(r) <= k) x[r] -= col[IOF(r)] * row[JOF(r)];
+  }
+  for (int e = tid; e < n * n; e += 1024) {
+    const int i = e % n, j = e / n;
+    if (i < j) { L[e] = 0.0; LinvT[j + (int64_t)n * i] = 0.0; LT[j + (int64_t)n * i] = 0.0; }
+  }
+#pragma unroll
+  for (int r = 0; r < EPT; ++r)
+    if (ij[r] >= 0) {
+      const int i = IOF(r), j = JOF(r);
+      L[i + (int64_t)n * j] = a[r];
+      LT[j + (int64_t)n * i] = a[r];
+      LinvT[j + (int64_t)n * i] = x[r];
+    }
+#undef IOF
+#undef JOF
+}
+
+// Triangular inverse for the large-n fallback: Linv^T from L (one workgroup,
+// row-oriented forward substitution over all columns at once, X in global).
+__global__ __launch_bounds__(1024) void trinv_kernel(const double* L, int n, double* X, double* LinvT,
+                                                     const int* status) {
+  if (*status != 0) return;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < n * n; e += 1024) X[e] = 0.0;
+  __syncthreads();
+  for (int i = 0; i < n; ++i) {
+    // X[i][j] = (delta_ij - sum_{t=j}^{i-1} L[i][t] X[t][j]) / L[i][i], j <= i
+    for (int j = tid; j <= i; j += 1024) {
+      double s = (i == j) ? 1.0 : 0.0;
+      for (int t = j; t < i; ++t) s -= L[i + (int64_t)n * t] * X[t + (int64_t)n * j];
+      X[i + (int64_t)n * j] = s / L[i + (int64_t)n * i];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < n * n; e += 1024) {
+    const int i = e % n, j = e / n;
+    LinvT[j + (int64_t)n * i] = X[e];
+  }
+}
+
 // Solve G S = Rhs row by row with S = L L^T:  L y = rhs^T, L^T x = y.
 // One wave per right-hand side; y lives in LDS.
 __global__ __launch_bounds__(256) void chol_solve_kernel(const double* L, const double* LT, int n, const double* Rhs,
@@ -188,7 +323,7 @@ __global__ __launch_bounds__(256) void chol_solve_kernel(const double* L, const 
   const int64_t r = (int64_t)blockIdx.x * 4 + wave;
   if (r >= I) return;
   double* y = reinterpret_cast<double*>(smem_raw) + (size_t)wave * n;
-  for (int j = lane; j < n; j += 64) y[j] = Rhs[r + I * j];
+  for (int j = lane; j < n; j += 64) y[j] = Rhs ? Rhs[r + I * j] : (r == j ? 1.0 : 0.0);
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
   for (int k = 0; k < n; ++k) {
@@ -215,29 +350,24 @@ __global__ __launch_bounds__(256) void chol_solve_kernel(const double* L, const 
   }
 }
 
-// core[a + Ra*(i + I*b)] = G[i + I*(a + Ra*b)] when the status word is clean
-// and G is finite; otherwise the core keeps its last good value.
-__global__ __launch_bounds__(1024) void commit_core_kernel(const double* G, int64_t I, int Ra, int Rb, double* core,
-                                                           int* status) {
-  __shared__ int bad;
-  const int64_t n = I * Ra * Rb;
-  if (threadIdx.x == 0) bad = 0;
-  __syncthreads();
-  int mybad = 0;
-  for (int64_t e = threadIdx.x; e < n; e += blockDim.x)
-    if (!isfinite(G[e])) mybad = 1;
-  if (mybad) atomicOr(&bad, 1);
-  __syncthreads();
-  if (bad) {
-    if (threadIdx.x == 0) atomicOr(status, ST_NONFINITE);
-    return;
-  }
+// A non-finite value in the new core latches ST_NONFINITE.
+__global__ void check_finite_kernel(const double* G, int64_t n, int* status) {
+  if (*status != 0) return;   // the solve was skipped: G holds no new core
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n && !isfinite(G[e])) atomicOr(status, ST_NONFINITE);
+}
+
+// core[a + Ra*(i + I*b)] = G[i + I*(a + Ra*b)] when the status word is clean;
+// otherwise the core keeps its last good value.
+__global__ void commit_core_kernel(const double* G, int64_t I, int Ra, int Rb, double* core, const int* status) {
   if (*status != 0) return;
-  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
-    const int64_t i = e % I, c = e / I;
-    const int64_t a = c % Ra, b = c / Ra;
-    core[a + Ra * (i + I * b)] = G[e];
-  }
+  const int64_t n = I * Ra * Rb;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int a = (int)(e % Ra);
+  const int64_t i = (e / Ra) % I;
+  const int b = (int)(e / ((int64_t)Ra * I));
+  core[e] = G[i + I * (a + (int64_t)Ra * b)];
 }
 
 // ---------------------------------------------------------------------------
@@ -418,15 +548,16 @@ hipError_t launch_identity_table(int R, double* out, hipStream_t s) {
 
 hipError_t launch_gram(const double* core, int Rl, int64_t I, int Rr, double* E, hipStream_t s) {
   const int nb = (Rl * Rr + 15) / 16;
-  hipLaunchKernelGGL(gram_kernel, dim3(cdiv((int64_t)nb * nb, 4)), dim3(256), 0, s, core, Rl, I, Rr, E);
+  hipLaunchKernelGGL(gram_kernel, dim3((unsigned)(nb * nb)), dim3(256), 0, s, core, Rl, I, Rr, E);
   return hipGetLastError();
 }
 
 hipError_t launch_gemm64(int64_t M, int64_t N, int64_t K, double alpha, MatView A, MatView B, double beta,
-                         const double* Cin, int64_t ldcin, double* C, int64_t ldc, hipStream_t s) {
+                         const double* Cin, int64_t ldcin, double* C, int64_t ldc, hipStream_t s,
+                         int* finite_status) {
   const int64_t nblk = cdiv(M, 16) * cdiv(N, 16);
-  hipLaunchKernelGGL(gemm64_kernel, dim3(cdiv(nblk, 4)), dim3(256), 0, s, M, N, K, alpha, A, B, beta, Cin, ldcin, C,
-                     ldc);
+  hipLaunchKernelGGL(gemm64_kernel, dim3((unsigned)nblk), dim3(256), 0, s, M, N, K, alpha, A, B, beta, Cin, ldcin, C,
+                     ldc, finite_status);
   return hipGetLastError();
 }
 
@@ -448,6 +579,23 @@ hipError_t launch_chol(const double* S, int n, double* L, double* LT, double* wo
   return hipGetLastError();
 }
 
+hipError_t launch_chol_inv(const double* S, int n, double* L, double* LT, double* LinvT, double* work, int* status,
+                           hipStream_t s) {
+  const int ntri = n * (n + 1) / 2;
+  if (n <= 256 && ntri <= 1024 * 4) {
+    hipLaunchKernelGGL(chol_inv_reg_kernel<4>, dim3(1), dim3(1024), 0, s, S, n, L, LT, LinvT, status);
+  } else if (n <= 256 && ntri <= 1024 * 11) {
+    hipLaunchKernelGGL(chol_inv_reg_kernel<11>, dim3(1), dim3(1024), 0, s, S, n, L, LT, LinvT, status);
+  } else if (n <= 256 && ntri <= 1024 * 20) {
+    hipLaunchKernelGGL(chol_inv_reg_kernel<20>, dim3(1), dim3(1024), 0, s, S, n, L, LT, LinvT, status);
+  } else {
+    hipError_t e = launch_chol(S, n, L, LT, work, status, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(trinv_kernel, dim3(1), dim3(1024), 0, s, L, n, work, LinvT, status);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_chol_solve(const double* L, const double* LT, int n, const double* Rhs, int64_t I, double* G,
                              int accumulate, const int* status, hipStream_t s) {
   const size_t lds = 4 * (size_t)n * sizeof(double);
@@ -455,8 +603,11 @@ hipError_t launch_chol_solve(const double* L, const double* LT, int n, const dou
   return hipGetLastError();
 }
 
-hipError_t launch_commit_core(const double* G, int64_t I, int Ra, int Rb, double* core, int* status, hipStream_t s) {
-  hipLaunchKernelGGL(commit_core_kernel, dim3(1), dim3(1024), 0, s, G, I, Ra, Rb, core, status);
+hipError_t launch_commit_core(const double* G, int64_t I, int Ra, int Rb, double* core, int* status, hipStream_t s,
+                              bool checked) {
+  const int64_t n = I * Ra * Rb;
+  if (!checked) hipLaunchKernelGGL(check_finite_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, G, n, status);
+  hipLaunchKernelGGL(commit_core_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, G, I, Ra, Rb, core, (const int*)status);
   return hipGetLastError();
 }
 

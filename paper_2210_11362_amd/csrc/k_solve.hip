@@ -1,0 +1,257 @@
+// FP64 normal-equation solve G S = M with S = L L^T (Alg. 2's solve step):
+// a blocked Cholesky in one workgroup (matrix in LDS) and a blocked
+// forward/backward substitution that runs 16 right-hand sides per workgroup
+// with L staged in LDS.  A non-positive or non-finite pivot latches
+// ST_SINGULAR; later steps see the status word and leave their outputs alone.
+#include "common.h"
+#include "../../include/tr_als.h"
+
+namespace {
+
+#ifndef TR_SOLVE_NB
+#define TR_SOLVE_NB 8
+#endif
+constexpr int NB = TR_SOLVE_NB;   // block size of the blocked algorithms
+constexpr int NRHS = 16;    // right-hand sides per workgroup
+
+// Value of v held by lane src (uniform src), as a wave-wide broadcast.
+__device__ __forceinline__ double bcast(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+// Right-looking blocked Cholesky.  The matrix is padded in LDS to np (a
+// multiple of 16) with an identity block, so every block has 16 columns and
+// the inner loops have fixed trip counts: blockdiag(S, I) = blockdiag(L, I) L^T.
+__global__ __launch_bounds__(256) void chol_lds_kernel(const double* S, int n, double* L, double* LT, int* status,
+                                                       double* rdg) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* A = reinterpret_cast<double*>(smem_raw);
+  __shared__ int bad;
+  __shared__ double rdiag[256];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int np = (n + NB - 1) / NB * NB;
+  if (tid == 0) bad = (*status != 0);
+  for (int e = tid; e < np * np; e += 256) {
+    const int i = e % np, j = e / np;
+    A[e] = (i < n && j < n) ? S[i + n * j] : (i == j ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  if (bad) return;
+  for (int J = 0; J < np; J += NB) {
+    if (wave == 0) {
+      // diagonal block: lane i < 16 holds row J+i in registers; pivots and
+      // column entries are broadcast with readlane (no LDS round trips)
+      double a[NB];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) a[j] = (lane < NB && j <= lane) ? A[(J + lane) + np * (J + j)] : 0.0;
+      bool okall = true;
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        const double d = bcast(a[k], k);
+        const bool ok = (d > 0.0) && isfinite(d);
+        okall = okall && ok;
+        const double piv = ok ? sqrt(d) : 1.0;
+        const double rp = 1.0 / piv;
+        if (lane == k) { a[k] = piv; rdiag[J + k] = rp; }
+        if (lane > k) a[k] *= rp;
+#pragma unroll
+        for (int j = k + 1; j < NB; ++j) {
+          const double ljk = bcast(a[k], j);
+          if (lane >= j) a[j] -= a[k] * ljk;
+        }
+      }
+      if (!okall && lane == 0) bad = 1;
+      if (lane < NB) {
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+          if (j <= lane) A[(J + lane) + np * (J + j)] = a[j];
+      }
+    }
+    __syncthreads();
+    if (bad) {
+      if (tid == 0) atomicOr(status, ST_SINGULAR);
+      return;
+    }
+    // panel: rows below the block, X L_JJ^T = A_panel
+    const int m = np - J - NB;
+    if (tid < m) {
+      const int i = J + NB + tid;
+      double x[NB];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) x[c] = A[i + np * (J + c)];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        double v = x[c];
+#pragma unroll
+        for (int t = 0; t < c; ++t) v -= x[t] * A[(J + c) + np * (J + t)];
+        x[c] = v * rdiag[J + c];
+      }
+#pragma unroll
+      for (int c = 0; c < NB; ++c) A[i + np * (J + c)] = x[c];
+    }
+    __syncthreads();
+    // trailing update of the lower triangle in 4x4 register tiles
+    const int mt = m / 4;
+    const int ntiles = mt * (mt + 1) / 2;
+    for (int t = tid; t < ntiles; t += 256) {
+      int ti = 0, acc0 = 0;
+      while (acc0 + ti + 1 <= t) { acc0 += ti + 1; ++ti; }
+      const int tj = t - acc0;   // 0..ti
+      const int i0 = J + NB + 4 * ti, j0 = J + NB + 4 * tj;
+      double acc[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        double pi[4], pj[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          pi[a] = A[(i0 + a) + np * (J + c)];
+          pj[a] = A[(j0 + a) + np * (J + c)];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[a][b] += pi[a] * pj[b];
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          if (j0 + b <= i0 + a) A[(i0 + a) + np * (j0 + b)] -= acc[a][b];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < n * n; e += 256) {
+    const int i = e % n, j = e / n;
+    const double v = (i >= j) ? A[i + np * j] : 0.0;
+    L[e] = v;
+    LT[j + n * i] = v;
+  }
+  for (int e = tid; e < np; e += 256) rdg[e] = rdiag[e];
+}
+
+// G[r, :] (+)= solution g of g S = rhs[r, :] for 16 rows r per workgroup
+// (Rhs == nullptr stands for the n x n identity, giving G = S^{-1}):
+// forward L z^T = rhs^T, then backward L^T g^T = z^T, both blocked by 16 on
+// an identity-padded copy of L (fixed trip counts in every inner loop).
+__global__ __launch_bounds__(256) void trsm_rhs_kernel(const double* Lg, const double* rdg, int n, const double* Rhs,
+                                                       int64_t I, double* G, int accumulate, const int* status) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double rd[256];
+  if (*status != 0) return;
+  const int np = (n + NB - 1) / NB * NB;
+  for (int e = threadIdx.x; e < np; e += 256) rd[e] = rdg[e];
+  double* Ls = reinterpret_cast<double*>(smem_raw);   // np x np column-major
+  double* B = Ls + (size_t)np * np;                   // NRHS x np, row r at B[r + NRHS*j]
+  const int tid = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * NRHS;
+  for (int e = tid; e < np * np; e += 256) {
+    const int i = e % np, j = e / np;
+    Ls[e] = (i < n && j < n) ? Lg[i + n * j] : (i == j ? 1.0 : 0.0);
+  }
+  for (int e = tid; e < NRHS * np; e += 256) {
+    const int r = e % NRHS, j = e / NRHS;
+    double v = 0.0;
+    if (r0 + r < I && j < n) v = Rhs ? Rhs[(r0 + r) + I * j] : (r0 + r == j ? 1.0 : 0.0);
+    B[e] = v;
+  }
+  __syncthreads();
+  // forward: z_j = (b_j - sum_{t<j} L[j,t] z_t) / L[j,j]
+  for (int J = 0; J < np; J += NB) {
+    if (tid < NRHS) {
+      const int r = tid;
+      double z[NB];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) z[c] = B[r + NRHS * (J + c)];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        double v = z[c];
+#pragma unroll
+        for (int t = 0; t < c; ++t) v -= Ls[(J + c) + np * (J + t)] * z[t];
+        z[c] = v * rd[J + c];
+      }
+#pragma unroll
+      for (int c = 0; c < NB; ++c) B[r + NRHS * (J + c)] = z[c];
+    }
+    __syncthreads();
+    for (int e = tid; e < NRHS * (np - J - NB); e += 256) {
+      const int r = e % NRHS, j = J + NB + e / NRHS;
+      double v = 0.0;
+#pragma unroll
+      for (int c = 0; c < NB; ++c) v += Ls[j + np * (J + c)] * B[r + NRHS * (J + c)];
+      B[r + NRHS * j] -= v;
+    }
+    __syncthreads();
+  }
+  // backward: g_j = (z_j - sum_{t>j} L[t,j] g_t) / L[j,j]
+  for (int J = np - NB; J >= 0; J -= NB) {
+    if (tid < NRHS) {
+      const int r = tid;
+      double g[NB];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) g[c] = B[r + NRHS * (J + c)];
+#pragma unroll
+      for (int cc = 0; cc < NB; ++cc) {
+        const int c = NB - 1 - cc;
+        double v = g[c];
+#pragma unroll
+        for (int t = c + 1; t < NB; ++t) v -= Ls[(J + t) + np * (J + c)] * g[t];
+        g[c] = v * rd[J + c];
+      }
+#pragma unroll
+      for (int c = 0; c < NB; ++c) B[r + NRHS * (J + c)] = g[c];
+    }
+    __syncthreads();
+    for (int e = tid; e < NRHS * J; e += 256) {
+      const int r = e % NRHS, j = e / NRHS;
+      double v = 0.0;
+#pragma unroll
+      for (int c = 0; c < NB; ++c) v += Ls[(J + c) + np * j] * B[r + NRHS * (J + c)];
+      B[r + NRHS * j] -= v;
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < NRHS * n; e += 256) {
+    const int r = e % NRHS, j = e / NRHS;
+    if (r0 + r < I) {
+      if (accumulate) G[(r0 + r) + I * j] += B[e];
+      else G[(r0 + r) + I * j] = B[e];
+    }
+  }
+}
+
+}  // namespace
+
+// LDS-resident versions for n <= 128; larger systems use the global-memory
+// Cholesky and the one-wave-per-row solve.
+bool solve_in_lds(int n) { return n <= 128; }
+
+hipError_t launch_chol_lds(const double* S, int n, double* L, double* LT, double* rdiag, int* status, hipStream_t s) {
+  const int np = (n + NB - 1) / NB * NB;
+  const size_t lds = (size_t)np * np * sizeof(double);
+  if (lds > 64 * 1024) hipFuncSetAttribute((const void*)chol_lds_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(chol_lds_kernel, dim3(1), dim3(256), lds, s, S, n, L, LT, status, rdiag);
+  return hipGetLastError();
+}
+
+hipError_t launch_trsm_rhs(const double* L, const double* rdiag, int n, const double* Rhs, int64_t I, double* G,
+                           int accumulate, const int* status, hipStream_t s) {
+  const int np = (n + NB - 1) / NB * NB;
+  const size_t lds = ((size_t)np * np + (size_t)NRHS * np) * sizeof(double);
+  if (lds > 64 * 1024) hipFuncSetAttribute((const void*)trsm_rhs_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(trsm_rhs_kernel, dim3((unsigned)((I + NRHS - 1) / NRHS)), dim3(256), lds, s, L, rdiag, n, Rhs,
+                     I, G, accumulate, status);
+  return hipGetLastError();
+}

@@ -1,0 +1,406 @@
+// Two-stage MTTSP (the compressible case of Alg. 2's MTTSP step).
+//
+// Stage 1 contracts X over one memory-contiguous group of modes g with the
+// partial subchain of those modes (a table B, Sec. 2 subchain product):
+//   Y[r, c] = sum_k A[r, k] B[k, c],  A = X seen as a matrix whose columns
+//   (NN: A[r,k] = X[r + M*k], group = slowest modes) or rows (TN: A[r,k] =
+//   X[k + K*r], group = fastest modes) run over the group.
+// It is a tall-skinny GEMM on MFMA that reads X exactly once; split-K partial
+// tiles are summed in a fixed order in FP64.  Stage 2 absorbs the remaining
+// modes other than n one at a time into the small intermediate (FP64).
+#include <algorithm>
+#include <type_traits>
+
+#include "common.h"
+#include "../../include/tr_als.h"
+
+namespace {
+
+template <int P> struct PT;
+template <> struct PT<TR_F64>  { using op_t = double;  using acc_t = f64x4; static constexpr int KS = 4;  };
+template <> struct PT<TR_F32>  { using op_t = float;   using acc_t = f32x4; static constexpr int KS = 4;  };
+template <> struct PT<TR_BF16> { using op_t = __bf16;  using acc_t = f32x4; static constexpr int KS = 32; };
+template <> struct PT<TR_FP8>  { using op_t = uint8_t; using acc_t = f32x4; static constexpr int KS = 32; };
+
+template <int P> struct Pad { static constexpr int v = 4; };
+template <> struct Pad<TR_F64> { static constexpr int v = 2; };
+template <> struct Pad<TR_BF16> { static constexpr int v = 8; };
+template <> struct Pad<TR_FP8> { static constexpr int v = 16; };
+
+__device__ __forceinline__ void mma(f32x4& c, float a, float b) { c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+__device__ __forceinline__ void mma(f64x4& c, double a, double b) { c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+__device__ __forceinline__ void mma(f32x4& c, bf16x8 a, bf16x8 b) { c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+__device__ __forceinline__ void mma(f32x4& c, long a, long b) { c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0); }
+
+template <int P> struct Frag;
+template <> struct Frag<TR_F64> {
+  using t = double;
+  static __device__ __forceinline__ t ld(const double* p, int row, int st, int kb, int lane) { return p[row * st + kb + (lane >> 4)]; }
+};
+template <> struct Frag<TR_F32> {
+  using t = float;
+  static __device__ __forceinline__ t ld(const float* p, int row, int st, int kb, int lane) { return p[row * st + kb + (lane >> 4)]; }
+};
+template <> struct Frag<TR_BF16> {
+  using t = bf16x8;
+  static __device__ __forceinline__ t ld(const __bf16* p, int row, int st, int kb, int lane) {
+    return *reinterpret_cast<const bf16x8*>(p + row * st + kb + 8 * (lane >> 4));
+  }
+};
+template <> struct Frag<TR_FP8> {
+  using t = long;
+  static __device__ __forceinline__ t ld(const uint8_t* p, int row, int st, int kb, int lane) {
+    return *reinterpret_cast<const long*>(p + row * st + kb + 8 * (lane >> 4));
+  }
+};
+
+template <int P, typename Tin> __device__ __forceinline__ typename PT<P>::op_t x_to_op(Tin v);
+template <> __device__ __forceinline__ double x_to_op<TR_F64, double>(double v) { return v; }
+template <> __device__ __forceinline__ double x_to_op<TR_F64, float>(float v) { return (double)v; }
+template <> __device__ __forceinline__ float x_to_op<TR_F32, float>(float v) { return v; }
+template <> __device__ __forceinline__ float x_to_op<TR_F32, double>(double v) { return (float)v; }
+template <> __device__ __forceinline__ __bf16 x_to_op<TR_BF16, __bf16>(__bf16 v) { return v; }
+template <> __device__ __forceinline__ uint8_t x_to_op<TR_FP8, uint8_t>(uint8_t v) { return v; }
+
+template <int P> __device__ __forceinline__ int acc_row(int lane, int v) { return 4 * (lane >> 4) + v; }
+template <> __device__ __forceinline__ int acc_row<TR_F64>(int lane, int v) { return (lane >> 4) + 4 * v; }
+
+constexpr int NTHR = 256;
+
+// Elements per 16-byte vector of the operand type.
+template <int P> struct Vec { static constexpr int n = 16 / sizeof(typename PT<P>::op_t); };
+
+template <int P, typename Tin, bool NN, int MT, int KT, int NBMAX>
+__global__ __launch_bounds__(NTHR) void xgemm_kernel(XgArgs g) {
+  using op_t = typename PT<P>::op_t;
+  using acc_t = typename PT<P>::acc_t;
+  using frag_t = typename Frag<P>::t;
+  constexpr int KS = PT<P>::KS;
+  constexpr int ST = KT + Pad<P>::v;
+  constexpr int V = Vec<P>::n;
+  constexpr int AV = MT * KT / V / NTHR;
+  constexpr int KV = KT / V;                  // packed vectors along a tile row
+  constexpr int MBW = MT / 64;                // row blocks per wave (waves stacked along rows)
+  extern __shared__ __align__(16) unsigned char smem[];
+  op_t* As = reinterpret_cast<op_t*>(smem);
+  op_t* Bs = As + MT * ST;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int mt = blockIdx.x % g.n_mt, nt = blockIdx.x / g.n_mt;
+  const int split = blockIdx.y;
+  const int64_t r0 = (int64_t)mt * MT;
+  const int NT = g.NT, NB = NT / 16;
+  const Tin* X = reinterpret_cast<const Tin*>(g.X);
+  const op_t* Bt = reinterpret_cast<const op_t*>(g.Bt) + (size_t)nt * NT * g.ldb;
+
+  const int64_t kbeg = (int64_t)split * g.k_per_split;
+  const int64_t kend = min(g.K, kbeg + g.k_per_split);
+
+  acc_t acc[MBW][NBMAX];
+#pragma unroll
+  for (int r = 0; r < MBW; ++r)
+#pragma unroll
+    for (int c = 0; c < NBMAX; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[r][c][v] = 0;
+
+  // per-thread coordinates of its packed A vectors: (row, kvec)
+  op_t areg[AV][V];
+  auto load_a = [&](int64_t k0) {
+#pragma unroll
+    for (int q = 0; q < AV; ++q) {
+      const int e = tid + q * NTHR;
+      int row, kv;
+      if (NN) { row = e % MT; kv = e / MT; }   // consecutive threads walk rows (contiguous in X)
+      else { kv = e % KV; row = e / KV; }      // consecutive threads walk k (contiguous in X)
+      const int64_t r = r0 + row;
+      const int64_t kb = k0 + kv * V;
+      if (!NN && sizeof(Tin) == sizeof(op_t) && g.vec_ok && r < g.M && kb + V <= kend) {
+        // K-contiguous rows with 16-byte aligned starts: one vector load
+        const uint4 w = *reinterpret_cast<const uint4*>(X + kb + g.K * r);
+        *reinterpret_cast<uint4*>(&areg[q][0]) = w;
+        continue;
+      }
+#pragma unroll
+      for (int j = 0; j < V; ++j) {
+        const int64_t k = kb + j;
+        op_t v = x_to_op<P, Tin>((Tin)0);
+        if (r < g.M && k < kend) v = x_to_op<P, Tin>(NN ? X[r + g.M * k] : X[k + g.K * r]);
+        areg[q][j] = v;
+      }
+    }
+  };
+  auto store_a = [&]() {
+#pragma unroll
+    for (int q = 0; q < AV; ++q) {
+      const int e = tid + q * NTHR;
+      int row, kv;
+      if (NN) { row = e % MT; kv = e / MT; }
+      else { kv = e % KV; row = e / KV; }
+      op_t* dst = As + row * ST + kv * V;
+#pragma unroll
+      for (int j = 0; j < V; ++j) dst[j] = areg[q][j];
+    }
+  };
+  // B tile: NT rows of KT contiguous elements, zero-padded in the table itself
+  auto copy_b = [&](int64_t k0) {
+    const int nvec = NT * KV;
+    for (int e = tid; e < nvec; e += NTHR) {
+      const int row = e / KV, kv = e % KV;
+      const uint4 v = *reinterpret_cast<const uint4*>(Bt + (size_t)row * g.ldb + k0 + kv * V);
+      *reinterpret_cast<uint4*>(Bs + row * ST + kv * V) = v;
+    }
+  };
+
+  if (kbeg < kend) load_a(kbeg);
+  for (int64_t k0 = kbeg; k0 < kend; k0 += KT) {
+    __syncthreads();
+    store_a();
+    copy_b(k0);
+    __syncthreads();
+    if (k0 + KT < kend) load_a(k0 + KT);     // next tile's global loads overlap the MFMAs below
+#pragma unroll
+    for (int kb = 0; kb < KT; kb += KS) {
+      frag_t af[MBW];
+#pragma unroll
+      for (int r = 0; r < MBW; ++r) af[r] = Frag<P>::ld(As, (wave * MBW + r) * 16 + (lane & 15), ST, kb, lane);
+#pragma unroll
+      for (int c = 0; c < NBMAX; ++c) {
+        if (c < NB) {
+          const frag_t bf = Frag<P>::ld(Bs, c * 16 + (lane & 15), ST, kb, lane);
+#pragma unroll
+          for (int r = 0; r < MBW; ++r) mma(acc[r][c], af[r], bf);
+        }
+      }
+    }
+  }
+
+  using part_t = typename std::conditional<P == TR_F64, double, float>::type;
+  part_t* out = reinterpret_cast<part_t*>(g.partial) + ((size_t)split * gridDim.x + blockIdx.x) * (size_t)MT * NT;
+#pragma unroll
+  for (int r = 0; r < MBW; ++r)
+#pragma unroll
+    for (int c = 0; c < NBMAX; ++c)
+      if (c < NB) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = (wave * MBW + r) * 16 + acc_row<P>(lane, v);
+          out[(size_t)row * NT + c * 16 + (lane & 15)] = (part_t)acc[r][c][v];
+        }
+      }
+}
+
+// Y[r + M*c] = out_scale * sum over splits of the partial tiles (fixed order).
+template <int P>
+__global__ void xg_reduce_kernel(XgArgs g, int MT, double out_scale, double* Y, int* status) {
+  using part_t = typename std::conditional<P == TR_F64, double, float>::type;
+  const int64_t tsz = (int64_t)MT * g.NT;
+  const int64_t ntile = (int64_t)g.n_mt * g.n_nt;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= ntile * tsz) return;
+  const int64_t tile = idx / tsz;
+  const int row = (int)((idx % tsz) / g.NT), col = (int)(idx % g.NT);
+  const int mt = (int)(tile % g.n_mt), nt = (int)(tile / g.n_mt);
+  const int64_t r = (int64_t)mt * MT + row;
+  const int64_t c = (int64_t)nt * g.NT + col;
+  if (r >= g.M || c >= g.C) return;
+  const part_t* p = reinterpret_cast<const part_t*>(g.partial) + idx;
+  const size_t ss = (size_t)(ntile * tsz);
+  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  int sp = 0;
+  for (; sp + 4 <= g.nsplit; sp += 4) {
+    s0 += (double)p[(sp + 0) * ss];
+    s1 += (double)p[(sp + 1) * ss];
+    s2 += (double)p[(sp + 2) * ss];
+    s3 += (double)p[(sp + 3) * ss];
+  }
+  for (; sp < g.nsplit; ++sp) s0 += (double)p[sp * ss];
+  const double s = ((s0 + s1) + (s2 + s3)) * out_scale;
+  if (!isfinite(s)) atomicOr(status, ST_NONFINITE);
+  Y[r + g.M * c] = s;
+}
+
+// Bt[c * ldb + k] = op(T[k * C + c] * scale), zero for k >= K or c >= C (padding).
+template <typename O>
+__global__ void table_to_bt_kernel(const double* T, int64_t K, int C, int Crows, int64_t ldb, double scale, O* Bt) {
+  const int64_t c = blockIdx.y;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ldb; k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = c * ldb + k;
+    const double v = (c < C && k < K) ? T[k * C + c] * scale : 0.0;
+    if constexpr (std::is_same<O, uint8_t>::value)
+      Bt[e] = (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32((float)v, 0.0f, 0, false) & 0xff);
+    else if constexpr (std::is_same<O, __bf16>::value)
+      Bt[e] = (__bf16)(float)v;
+    else
+      Bt[e] = (O)v;
+  }
+}
+
+// Stage 2: absorb one mode of the intermediate.  Y is [lo][I][hi][bond] with
+// bond = u + Ru*c.  side 0 contracts u with the core's right index (new u =
+// core's left index); side 1 contracts c with the core's left index (new c =
+// core's right index).  Out is [lo][hi][bond'].  When final != 0 the one mode
+// left (lo*hi = I_n) is written as M[i + I_n*(c + Rc*u)]: the column order
+// a + R_n*b of G_n(2) with a = c, b = u.
+//
+// Lanes run over l when lo is wide (coalesced reads of Y); otherwise one
+// workgroup reduces one output over (i, x).  Either way the reduction order is
+// fixed, so the result is deterministic.
+struct AbsorbArgs {
+  const double* Y; int64_t lo, I, hi; int Ru, Rc; const double* core; int Rl, Rr, side, final_out; double* out;
+};
+
+__device__ __forceinline__ double absorb_term2(const AbsorbArgs& a, int64_t l, int64_t h, int u2, int c2, int64_t i,
+                                              int x) {
+  const int64_t sI = a.lo, sH = a.lo * a.I, sB = a.lo * a.I * a.hi;
+  if (a.side == 0)
+    return a.core[u2 + (int64_t)a.Rl * (i + a.I * x)] * a.Y[l + sI * i + sH * h + sB * (x + (int64_t)a.Ru * c2)];
+  return a.Y[l + sI * i + sH * h + sB * (u2 + (int64_t)a.Ru * x)] * a.core[x + (int64_t)a.Rc * (i + a.I * c2)];
+}
+
+__device__ __forceinline__ void absorb_store(const AbsorbArgs& a, int64_t l, int64_t h, int u2, int c2, double v) {
+  const int Ru2 = a.side == 0 ? a.Rl : a.Ru;
+  const int Rc2 = a.side == 0 ? a.Rc : a.Rr;
+  if (a.final_out) a.out[(l + a.lo * h) + a.lo * a.hi * (c2 + (int64_t)Rc2 * u2)] = v;
+  else a.out[l + a.lo * (h + a.hi * (u2 + (int64_t)Ru2 * c2))] = v;
+}
+
+// lanes over 64 consecutive l; 16 waves split the i range, each keeping 4 rows
+// of loads in flight; grid (l-blocks, hi, bond')
+__global__ __launch_bounds__(1024) void absorb_lanes_kernel(AbsorbArgs a) {
+  __shared__ double red[16][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t l = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t h = blockIdx.y;
+  const int Ru2 = a.side == 0 ? a.Rl : a.Ru;
+  const int bnd = blockIdx.z;
+  const int u2 = bnd % Ru2, c2 = bnd / Ru2;
+  const int R = a.side == 0 ? a.Ru : a.Rc;
+  const int64_t i0 = a.I * wave / 16, i1 = a.I * (wave + 1) / 16;
+  double s = 0.0;
+  if (l < a.lo) {
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int x = 0; x < R; ++x) {
+      int64_t i = i0;
+      for (; i + 4 <= i1; i += 4) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s4[q] += absorb_term2(a, l, h, u2, c2, i + q, x);
+      }
+      for (; i < i1; ++i) s4[0] += absorb_term2(a, l, h, u2, c2, i, x);
+    }
+    s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+  }
+  red[wave][lane] = s;
+  __syncthreads();
+  if (wave == 0 && l < a.lo) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) t += red[w][lane];
+    absorb_store(a, l, h, u2, c2, t);
+  }
+}
+
+// one workgroup per output; 256 threads split the (i, x) range
+__global__ __launch_bounds__(256) void absorb_block_kernel(AbsorbArgs a) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  const int Ru2 = a.side == 0 ? a.Rl : a.Ru;
+  const int64_t e = blockIdx.x;
+  const int64_t l = e % a.lo, h = (e / a.lo) % a.hi;
+  const int bnd = (int)(e / (a.lo * a.hi));
+  const int u2 = bnd % Ru2, c2 = bnd / Ru2;
+  const int R = a.side == 0 ? a.Ru : a.Rc;
+  const int64_t T = a.I * R;
+  double s = 0.0;
+  for (int64_t t = tid; t < T; t += 256) s += absorb_term2(a, l, h, u2, c2, t / R, (int)(t % R));
+  red[tid] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) absorb_store(a, l, h, u2, c2, red[0]);
+}
+
+// M[i + In*(c + Rc*u)] = Y[i + In*(u + Ru*c)] : final reordering when no mode is
+// left to absorb.
+__global__ void bond_to_M_kernel(const double* Y, int64_t In, int Ru, int Rc, double* M) {
+  const int64_t n = In * Ru * Rc;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int64_t i = e % In;
+  const int b = (int)(e / In);
+  const int u = b % Ru, c = b / Ru;
+  M[i + In * (c + (int64_t)Rc * u)] = Y[e];
+}
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+template <int P, typename Tin, bool NN, int MT, int KT>
+hipError_t launch_g(const XgArgs& g, hipStream_t s) {
+  using op_t = typename PT<P>::op_t;
+  const size_t lds = (size_t)(MT + g.NT) * (KT + Pad<P>::v) * sizeof(op_t);
+  dim3 grid(g.n_mt * g.n_nt, g.nsplit);
+  auto k = xgemm_kernel<P, Tin, NN, MT, KT, 8>;
+  if (lds > 64 * 1024) hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(k, grid, dim3(NTHR), lds, s, g);
+  return hipGetLastError();
+}
+
+template <int P, typename Tin>
+hipError_t launch_p(const XgArgs& g, hipStream_t s) {
+  constexpr int KT = (P == TR_F64) ? 32 : 64;
+  if (g.MT == 64) return g.nn ? launch_g<P, Tin, true, 64, KT>(g, s) : launch_g<P, Tin, false, 64, KT>(g, s);
+  return g.nn ? launch_g<P, Tin, true, 128, KT>(g, s) : launch_g<P, Tin, false, 128, KT>(g, s);
+}
+
+}  // namespace
+
+int xgemm_kt(int prec) { return prec == TR_F64 ? 32 : 64; }
+
+hipError_t launch_xgemm(const XgArgs& g, int prec, int xdt, hipStream_t s) {
+  if (prec == TR_F64) return xdt == TR_F64 ? launch_p<TR_F64, double>(g, s) : launch_p<TR_F64, float>(g, s);
+  if (prec == TR_F32) return xdt == TR_F64 ? launch_p<TR_F32, double>(g, s) : launch_p<TR_F32, float>(g, s);
+  if (prec == TR_BF16) return launch_p<TR_BF16, __bf16>(g, s);
+  return launch_p<TR_FP8, uint8_t>(g, s);
+}
+
+hipError_t launch_xg_reduce(const XgArgs& g, int prec, double out_scale, double* Y, int* status, hipStream_t s) {
+  const int64_t n = (int64_t)g.n_mt * g.n_nt * g.MT * g.NT;
+  if (prec == TR_F64)
+    hipLaunchKernelGGL(xg_reduce_kernel<TR_F64>, dim3(cdiv(n, 256)), dim3(256), 0, s, g, g.MT, out_scale, Y, status);
+  else
+    hipLaunchKernelGGL(xg_reduce_kernel<TR_F32>, dim3(cdiv(n, 256)), dim3(256), 0, s, g, g.MT, out_scale, Y, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_table_to_bt(const double* T, int64_t K, int C, int Crows, int64_t ldb, int prec, double scale,
+                              void* Bt, hipStream_t s) {
+  const dim3 grid((unsigned)std::min<int64_t>(cdiv(ldb, 256), 64), (unsigned)Crows);
+  switch (prec) {
+    case TR_F64: hipLaunchKernelGGL(table_to_bt_kernel<double>, dim3(grid), dim3(256), 0, s, T, K, C, Crows, ldb, scale, (double*)Bt); break;
+    case TR_F32: hipLaunchKernelGGL(table_to_bt_kernel<float>, dim3(grid), dim3(256), 0, s, T, K, C, Crows, ldb, scale, (float*)Bt); break;
+    case TR_BF16: hipLaunchKernelGGL(table_to_bt_kernel<__bf16>, dim3(grid), dim3(256), 0, s, T, K, C, Crows, ldb, scale, (__bf16*)Bt); break;
+    default: hipLaunchKernelGGL(table_to_bt_kernel<uint8_t>, dim3(grid), dim3(256), 0, s, T, K, C, Crows, ldb, scale, (uint8_t*)Bt); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_absorb(const double* Y, int64_t lo, int64_t I, int64_t hi, int Ru, int Rc, const double* core,
+                         int Rl, int Rr, int side, int final_out, double* out, hipStream_t s) {
+  const int Ru2 = side == 0 ? Rl : Ru, Rc2 = side == 0 ? Rc : Rr;
+  AbsorbArgs a{Y, lo, I, hi, Ru, Rc, core, Rl, Rr, side, final_out, out};
+  if (lo >= 32) {
+    dim3 grid((unsigned)cdiv(lo, 64), (unsigned)hi, (unsigned)(Ru2 * Rc2));
+    hipLaunchKernelGGL(absorb_lanes_kernel, grid, dim3(1024), 0, s, a);
+  } else {
+    hipLaunchKernelGGL(absorb_block_kernel, dim3((unsigned)(lo * hi * Ru2 * Rc2)), dim3(256), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_bond_to_M(const double* Y, int64_t In, int Ru, int Rc, double* M, hipStream_t s) {
+  const int64_t n = In * Ru * Rc;
+  hipLaunchKernelGGL(bond_to_M_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, Y, In, Ru, Rc, M);
+  return hipGetLastError();
+}

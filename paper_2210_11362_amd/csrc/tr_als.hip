@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -20,6 +21,15 @@ struct Plan {
   std::vector<int> f1c, f2c;  // cores (0-based, chain order) of each factor
   int64_t K1 = 1, K2 = 1, d1 = 1, m1 = 1, d2 = 1, m2 = 1;
   int Rb = 1, Rmid = 1, Ra = 1;
+  // two-stage MTTSP (regime 1): stage-1 group of modes and the stage-2 steps
+  int regime = 2;
+  int nn = 1;                 // 1: group = slowest modes, 0: fastest modes
+  std::vector<int> gcores;    // group cores in chain (= memory) order
+  int64_t gK = 1, gM = 1;     // group size and rows of the intermediate
+  int gC = 1, gRu = 1, gRc = 1;
+  bool reuse_prev = false;    // same group table as the previous mode of the sweep
+  struct Step { int64_t lo, I, hi; int Ru, Rc, core, side; };
+  std::vector<Step> steps;
 };
 
 }  // namespace
@@ -34,6 +44,13 @@ struct tr_als_ctx {
   int64_t numel = 0;
   std::vector<double*> user_cores;
   hipStream_t stream = nullptr;
+  hipStream_t stream2 = nullptr;             // coefficient-matrix branch (default priority)
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  double* Sinv = nullptr;
+  double* rdiag = nullptr;                   // reciprocal pivots of the Cholesky factor
+  // captured sweeps, one per (precision, refinement steps)
+  hipGraphExec_t graphs[4][5] = {{nullptr}};
+  bool graphs_ok = true;
   double* cores[TR_MAXN] = {nullptr};
   double* gram[TR_MAXN] = {nullptr};
   Plan plan[TR_MAXN];
@@ -41,7 +58,10 @@ struct tr_als_ctx {
   std::vector<void*> allocs;
   double *F1 = nullptr, *F2 = nullptr, *T0 = nullptr, *T1 = nullptr;
   double *M = nullptr, *S = nullptr, *W0 = nullptr, *W1 = nullptr, *Lf = nullptr, *LTf = nullptr, *cholw = nullptr;
-  double *Gn = nullptr, *Res = nullptr, *G0u = nullptr;
+  double *Gn = nullptr, *Res = nullptr, *G0u = nullptr, *LinvT = nullptr, *Tsol = nullptr;
+  double *Y0 = nullptr, *Y1 = nullptr;   // stage-2 intermediates
+  void* Bt = nullptr;                    // stage-1 table, transposed, operand type
+  size_t bt_bytes = 0;
   void* partial = nullptr;
   size_t partial_bytes = 0;
   double* dpart = nullptr;
@@ -162,6 +182,61 @@ Plan make_plan(const tr_als_ctx* c, int m) {
     p.K2 = p.L;
     p.d1 = p.L; p.m1 = p.K1; p.d2 = 1; p.m2 = p.L;
   }
+  // Two-stage MTTSP: contract X over the contiguous group of modes that keeps
+  // both the group's partial-subchain table (#K x C) and the intermediate
+  // (numel/#K x C) small; taken when their sum is at most a tenth of X.
+  double bestc = -1;
+  int bnn = 1, bp = -1;
+  for (int q = m + 1; q < N; ++q) {  // slowest modes q..N-1
+    const int64_t K = prod(c->dims, q, N);
+    const int C = R[q] * R[0];
+    const double cost = ((double)K + (double)c->numel / K) * C;
+    if (C <= 1024 && (bestc < 0 || cost < bestc)) { bestc = cost; bnn = 1; bp = q; }
+  }
+  for (int q = 0; q < m; ++q) {      // fastest modes 0..q
+    const int64_t K = prod(c->dims, 0, q + 1);
+    const int C = R[0] * R[q + 1];
+    const double cost = ((double)K + (double)c->numel / K) * C;
+    if (C <= 1024 && (bestc < 0 || cost < bestc)) { bestc = cost; bnn = 0; bp = q; }
+  }
+  // TR_ALS_FORCE_REGIME=1|2 pins the choice (used by the tests to run both
+  // kernels on every shape)
+  const char* fr = getenv("TR_ALS_FORCE_REGIME");
+  const int force = fr ? atoi(fr) : 0;
+  const bool take = bp >= 0 && (force == 1 || (force != 2 && bestc <= 0.1 * (double)c->numel));
+  if (take) {
+    p.regime = 1;
+    p.nn = bnn;
+    if (bnn) {
+      for (int j = bp; j < N; ++j) p.gcores.push_back(j);
+      p.gK = prod(c->dims, bp, N);
+      p.gRu = R[bp]; p.gRc = R[0];
+      int Ru = p.gRu, Rc = p.gRc;
+      for (int j = bp - 1; j > m; --j) {   // slow side, next to bond u
+        p.steps.push_back({prod(c->dims, 0, j), c->dims[j], 1, Ru, Rc, j, 0});
+        Ru = R[j];
+      }
+      for (int j = 0; j < m; ++j) {        // fast side, next to bond c
+        p.steps.push_back({1, c->dims[j], prod(c->dims, j + 1, m + 1), Ru, Rc, j, 1});
+        Rc = R[j + 1];
+      }
+    } else {
+      for (int j = 0; j <= bp; ++j) p.gcores.push_back(j);
+      p.gK = prod(c->dims, 0, bp + 1);
+      p.gRu = R[0]; p.gRc = R[bp + 1];
+      int Ru = p.gRu, Rc = p.gRc;
+      for (int j = bp + 1; j < m; ++j) {   // fast side, next to bond c
+        p.steps.push_back({1, c->dims[j], prod(c->dims, j + 1, N), Ru, Rc, j, 1});
+        Rc = R[j + 1];
+      }
+      for (int j = N - 1; j > m; --j) {    // slow side, next to bond u
+        p.steps.push_back({prod(c->dims, m, j), c->dims[j], 1, Ru, Rc, j, 0});
+        Ru = R[j];
+      }
+    }
+    p.gC = p.gRu * p.gRc;
+    p.gM = c->numel / p.gK;
+  }
   return p;
 }
 
@@ -260,6 +335,39 @@ XsCfg xs_config(const tr_als_ctx* c, int m, int prec) {
   return x;
 }
 
+XgArgs xg_config(const tr_als_ctx* c, int m, int prec, const void* X, int esize) {
+  const Plan& p = c->plan[m];
+  XgArgs g;
+  g.X = X;
+  g.M = p.gM; g.K = p.gK; g.C = p.gC; g.nn = p.nn;
+  g.vec_ok = (!p.nn && ((p.gK * esize) % 16 == 0) && (((uintptr_t)X) % 16 == 0)) ? 1 : 0;
+  g.MT = p.gM > 8192 ? 128 : 64;
+  g.n_mt = (int)((p.gM + g.MT - 1) / g.MT);
+  if (p.gC <= 128) { g.NT = (p.gC + 15) / 16 * 16; g.n_nt = 1; }
+  else { g.NT = 128; g.n_nt = (p.gC + 127) / 128; }
+  const int kt = xgemm_kt(prec);
+  g.ldb = (p.gK + kt - 1) / kt * kt;
+  const int64_t ktiles = g.ldb / kt;
+  const int64_t tiles = (int64_t)g.n_mt * g.n_nt;
+  int64_t ns = std::max<int64_t>(1, (640 + tiles - 1) / tiles);
+  ns = std::min<int64_t>(ns, std::max<int64_t>(1, ktiles / 2));
+  const int64_t tps = (ktiles + ns - 1) / ns;
+  g.k_per_split = tps * kt;
+  g.nsplit = (int)((p.gK + g.k_per_split - 1) / g.k_per_split);
+  g.Bt = c->Bt;
+  g.partial = c->partial;
+  return g;
+}
+
+size_t xg_partial_bytes(const XgArgs& g, int prec) {
+  return (size_t)g.nsplit * g.n_mt * g.n_nt * g.MT * g.NT * (prec == TR_F64 ? 8 : 4);
+}
+
+size_t xg_bt_bytes(const XgArgs& g, int prec) {
+  const size_t es = prec == TR_F64 ? 8 : prec == TR_F32 ? 4 : prec == TR_BF16 ? 2 : 1;
+  return (size_t)g.n_nt * g.NT * g.ldb * es;
+}
+
 size_t partial_bytes_needed(const XsCfg& x, int prec) {
   return (size_t)x.a.nsplit * x.a.n_mt * x.a.n_nt * x.a.MT * x.a.NT * (prec == TR_F64 ? 8 : 4);
 }
@@ -282,11 +390,67 @@ int ensure_shadow(tr_als_ctx* c, int prec) {
   return TR_OK;
 }
 
-// M_n = X_[n] G^{!=n}_[2] for the context's current cores (tables + X stream +
-// ordered split-K reduction).
-int compute_mttsp(tr_als_ctx* c, int m, int prec, double* Mout) {
+// Two-stage M_n: group table -> transposed operand table -> stage-1 GEMM over
+// X -> ordered reduction -> stage-2 absorptions.
+int compute_mttsp_two_stage(tr_als_ctx* c, int m, int prec, double* Mout, bool in_sweep) {
   hipStream_t s = c->stream;
   const Plan& p = c->plan[m];
+  const bool reuse = in_sweep && p.reuse_prev && prec != TR_FP8;
+  int rc = reuse ? TR_OK : build_table(c, p.gcores, 1, c->F1);
+  if (rc) return rc;
+  rc = ensure_shadow(c, prec);
+  if (rc) return rc;
+  const void* X = prec == TR_BF16 ? c->xbf16 : prec == TR_FP8 ? c->xfp8 : c->X;
+  const int esize = prec == TR_BF16 ? 2 : prec == TR_FP8 ? 1 : (c->xdt == TR_F64 ? 8 : 4);
+  XgArgs g = xg_config(c, m, prec, X, esize);
+  if (xg_partial_bytes(g, prec) > c->partial_bytes || xg_bt_bytes(g, prec) > c->bt_bytes)
+    return fail(c, TR_EHIP, "internal: stage-1 buffers too small");
+  double bscale = 1.0, out_scale = 1.0;
+  if (prec == TR_FP8) {
+    HIPCHK(c, launch_table_absmax(c->F1, p.gK * p.gC, c->dscal + 2, s));
+    double tm = 0;
+    HIPCHK(c, hipMemcpyAsync(&tm, c->dscal + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    bscale = tm > 0 ? std::ldexp(1.0, (int)std::floor(std::log2(448.0 / tm))) : 1.0;
+    out_scale = 1.0 / ((double)c->fp8_scale * bscale);
+  }
+  if (!reuse) HIPCHK(c, launch_table_to_bt(c->F1, p.gK, p.gC, g.n_nt * g.NT, g.ldb, prec, bscale, c->Bt, s));
+  const bool prof = c->prof;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (prof) {
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    HIPCHK(c, hipEventRecord(e0, s));
+  }
+  HIPCHK(c, launch_xgemm(g, prec, (prec == TR_F64 || prec == TR_F32) ? c->xdt : prec, s));
+  if (prof) {
+    HIPCHK(c, hipEventRecord(e1, s));
+    c->evs.push_back({e0, e1});
+    c->prof_bytes = (double)esize * (double)c->numel;
+  }
+  double* cur = p.steps.empty() ? c->Y1 : c->Y0;
+  HIPCHK(c, launch_xg_reduce(g, prec, out_scale, cur, c->status, s));
+  if (p.steps.empty()) {
+    HIPCHK(c, launch_bond_to_M(cur, p.I, p.gRu, p.gRc, Mout, s));
+    return TR_OK;
+  }
+  for (size_t q = 0; q < p.steps.size(); ++q) {
+    const Plan::Step& st = p.steps[q];
+    const bool last = q + 1 == p.steps.size();
+    double* nxt = last ? Mout : (cur == c->Y0 ? c->Y1 : c->Y0);
+    HIPCHK(c, launch_absorb(cur, st.lo, st.I, st.hi, st.Ru, st.Rc, c->cores[st.core], c->R[st.core],
+                            c->R[st.core + 1], st.side, last ? 1 : 0, nxt, s));
+    cur = nxt;
+  }
+  return TR_OK;
+}
+
+// M_n = X_[n] G^{!=n}_[2] for the context's current cores (tables + X stream +
+// ordered split-K reduction).
+int compute_mttsp(tr_als_ctx* c, int m, int prec, double* Mout, bool in_sweep = false) {
+  hipStream_t s = c->stream;
+  const Plan& p = c->plan[m];
+  if (p.regime == 1) return compute_mttsp_two_stage(c, m, prec, Mout, in_sweep);
   int rc = build_table(c, p.f1c, p.Rmid, c->F1);
   if (rc) return rc;
   rc = build_table(c, p.f2c, p.Rmid, c->F2);
@@ -335,8 +499,7 @@ int compute_mttsp(tr_als_ctx* c, int m, int prec, double* Mout) {
 
 // S_n<2> from the Gram ring: W = K_{m+1} K_{m+2} ... K_{m-1} (Kronecker-order
 // Grams), then realigned.
-int compute_coef(tr_als_ctx* c, int m, double* Sout) {
-  hipStream_t s = c->stream;
+int compute_coef(tr_als_ctx* c, int m, double* Sout, hipStream_t s) {
   const int N = c->N;
   std::vector<int> chain;
   for (int k = 1; k < N; ++k) chain.push_back((m + k) % N);
@@ -362,22 +525,39 @@ int compute_coef(tr_als_ctx* c, int m, double* Sout) {
   return TR_OK;
 }
 
-int update_mode_ne(tr_als_ctx* c, int m, int prec, int refine) {
-  hipStream_t s = c->stream;
+// One NE mode update.  The coefficient branch (Gram ring -> S_n -> Cholesky ->
+// S_n^{-1}) does not depend on X and runs on a second stream concurrently with
+// the MTTSP; the solve is then G = M S^{-1} with iterative refinement
+// G += (M - G S) S^{-1}, all on FP64 MFMA.
+int update_mode_ne(tr_als_ctx* c, int m, int prec, int refine, bool in_sweep) {
+  hipStream_t s = c->stream, s2 = c->stream2;
   const Plan& p = c->plan[m];
   const int n = p.Ra * p.Rb;
-  int rc = compute_mttsp(c, m, prec, c->M);
+  HIPCHK(c, hipEventRecord(c->ev_fork, s));
+  HIPCHK(c, hipStreamWaitEvent(s2, c->ev_fork, 0));
+  int rc = compute_coef(c, m, c->S, s2);
   if (rc) return rc;
-  rc = compute_coef(c, m, c->S);
-  if (rc) return rc;
-  HIPCHK(c, launch_chol(c->S, n, c->Lf, c->LTf, c->cholw, c->status, s));
-  HIPCHK(c, launch_chol_solve(c->Lf, c->LTf, n, c->M, p.I, c->Gn, 0, c->status, s));
-  for (int r = 0; r < refine; ++r) {
-    MatView G{c->Gn, p.I, 0, 0, 0}, Sv{c->S, n, 0, 0, 0};
-    HIPCHK(c, launch_gemm64(p.I, n, n, -1.0, G, Sv, 1.0, c->M, p.I, c->Res, p.I, s));
-    HIPCHK(c, launch_chol_solve(c->Lf, c->LTf, n, c->Res, p.I, c->Gn, 1, c->status, s));
+  if (solve_in_lds(n)) {
+    HIPCHK(c, launch_chol_lds(c->S, n, c->Lf, c->LTf, c->rdiag, c->status, s2));
+    HIPCHK(c, launch_trsm_rhs(c->Lf, c->rdiag, n, nullptr, n, c->Sinv, 0, c->status, s2));
+  } else {
+    HIPCHK(c, launch_chol(c->S, n, c->Lf, c->LTf, c->cholw, c->status, s2));
+    HIPCHK(c, launch_chol_solve(c->Lf, c->LTf, n, nullptr, n, c->Sinv, 0, c->status, s2));
   }
-  HIPCHK(c, launch_commit_core(c->Gn, p.I, p.Ra, p.Rb, c->cores[m], c->status, s));
+  HIPCHK(c, hipEventRecord(c->ev_join, s2));
+  rc = compute_mttsp(c, m, prec, c->M, in_sweep);
+  if (rc) return rc;
+  HIPCHK(c, hipStreamWaitEvent(s, c->ev_join, 0));
+  MatView Mv{c->M, p.I, 0, 0, 0}, Si{c->Sinv, n, 0, 0, 0};
+  HIPCHK(c, launch_gemm64(p.I, n, n, 1.0, Mv, Si, 0.0, nullptr, 0, c->Gn, p.I, s, refine == 0 ? c->status : nullptr));
+  for (int r = 0; r < refine; ++r) {
+    MatView G{c->Gn, p.I, 0, 0, 0}, Sv{c->S, n, 0, 0, 0}, Rv{c->Res, p.I, 0, 0, 0};
+    HIPCHK(c, launch_gemm64(p.I, n, n, -1.0, G, Sv, 1.0, c->M, p.I, c->Res, p.I, s));
+    HIPCHK(c, launch_gemm64(p.I, n, n, 1.0, Rv, Si, 1.0, c->Gn, p.I, c->Gn, p.I, s,
+                            r + 1 == refine ? c->status : nullptr));
+  }
+  // the last solve GEMM latched any non-finite entry of the new core
+  HIPCHK(c, launch_commit_core(c->Gn, p.I, p.Ra, p.Rb, c->cores[m], c->status, s, true));
   HIPCHK(c, launch_gram(c->cores[m], c->R[m], c->dims[m], c->R[m + 1], c->gram[m], s));
   return TR_OK;
 }
@@ -399,8 +579,8 @@ int read_status(tr_als_ctx* c) {
   // the context stays usable: clear the latched word for the next call
   HIPCHK(c, hipMemsetAsync(c->status, 0, sizeof(int), c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  if (st & ST_NONFINITE) return fail(c, TR_ENONFINITE, "non-finite value in M_n or in an updated core");
-  return fail(c, TR_ESINGULAR, "coefficient matrix not positive definite (or zero pivot)");
+  if (st & ST_SINGULAR) return fail(c, TR_ESINGULAR, "coefficient matrix not positive definite (or zero pivot)");
+  return fail(c, TR_ENONFINITE, "non-finite value in M_n or in an updated core");
 }
 
 int store_cores(tr_als_ctx* c) {
@@ -438,6 +618,12 @@ int tr_als_destroy(tr_als_ctx* ctx) {
   if (!ctx) return TR_OK;
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   for (auto& e : ctx->evs) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+  for (auto& row : ctx->graphs)
+    for (auto& g : row)
+      if (g) (void)hipGraphExecDestroy(g);
+  if (ctx->stream2) { (void)hipStreamSynchronize(ctx->stream2); (void)hipStreamDestroy(ctx->stream2); }
+  if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+  if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
   for (void* p : ctx->allocs) (void)hipFree(p);
   delete ctx;
   return TR_OK;
@@ -467,7 +653,16 @@ int tr_als_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ran
   c->numel = numel;
   c->stream = (hipStream_t)hip_stream;
   c->user_cores.assign(cores, cores + N);
+  if (const char* ev = getenv("TR_ALS_NO_GRAPH")) c->graphs_ok = (ev[0] == '0');
   for (int m = 0; m < N; ++m) c->plan[m] = make_plan(c, m);
+  // within a sweep, mode m can reuse mode m-1's group table when the groups
+  // match and the core updated by mode m-1 is not part of it
+  for (int m = 1; m < N; ++m) {
+    const Plan& a = c->plan[m - 1];
+    Plan& b = c->plan[m];
+    b.reuse_prev = a.regime == 1 && b.regime == 1 && a.gcores == b.gcores &&
+                   std::find(b.gcores.begin(), b.gcores.end(), m - 1) == b.gcores.end();
+  }
 
   // workspace sizes
   int64_t maxI = 0, maxRR = 0, maxF = 0, maxT = 0, maxW = 0;
@@ -476,10 +671,16 @@ int tr_als_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ran
     maxRR = std::max<int64_t>(maxRR, (int64_t)c->R[k] * c->R[k + 1]);
     maxW = std::max<int64_t>(maxW, (int64_t)c->R[k] * c->R[k] * c->R[k + 1] * c->R[k + 1]);
   }
+  int64_t maxY = 16;
   for (int m = 0; m < N; ++m) {
     const Plan& p = c->plan[m];
     maxF = std::max(maxF, std::max(table_elems(c, p.f1c, p.Rmid), table_elems(c, p.f2c, p.Rmid)));
     maxT = std::max(maxT, std::max(table_build_max(c, p.f1c), table_build_max(c, p.f2c)));
+    if (p.regime == 1) {
+      maxF = std::max(maxF, table_elems(c, p.gcores, 1));
+      maxT = std::max(maxT, table_build_max(c, p.gcores));
+      maxY = std::max(maxY, p.gM * p.gC);
+    }
   }
   size_t pbytes = 0;
   int rc = TR_OK;
@@ -500,7 +701,13 @@ int tr_als_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ran
   A((void**)&c->Lf, (size_t)maxRR * maxRR * 8);
   A((void**)&c->LTf, (size_t)maxRR * maxRR * 8);
   A((void**)&c->cholw, (size_t)maxRR * maxRR * 8);
+  A((void**)&c->LinvT, (size_t)maxRR * maxRR * 8);
+  A((void**)&c->Sinv, (size_t)maxRR * maxRR * 8);
+  A((void**)&c->rdiag, 256 * 8);
+  A((void**)&c->Tsol, (size_t)maxI * maxRR * 8);
   A((void**)&c->W0, (size_t)maxW * 8);
+  A((void**)&c->Y0, (size_t)maxY * 8);
+  A((void**)&c->Y1, (size_t)maxY * 8);
   A((void**)&c->W1, (size_t)maxW * 8);
   A((void**)&c->dpart, (size_t)c->nred * 8);
   A((void**)&c->fpart, (size_t)c->nred * 4);
@@ -508,13 +715,23 @@ int tr_als_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ran
   A((void**)&c->fscal, 8 * 4);
   A((void**)&c->status, 16);
   if (rc) { std::string e = c->err; tr_als_destroy(c); (void)e; return rc; }
+  size_t btb = 16;
   for (int m = 0; m < N; ++m)
     for (int prec = TR_F64; prec <= TR_FP8; ++prec) {
-      XsCfg x = xs_config(c, m, prec);
-      pbytes = std::max(pbytes, partial_bytes_needed(x, prec));
+      if (c->plan[m].regime == 1) {
+        const int es = prec == TR_BF16 ? 2 : prec == TR_FP8 ? 1 : (x_dtype == TR_F64 ? 8 : 4);
+        XgArgs g = xg_config(c, m, prec, X, es);
+        pbytes = std::max(pbytes, xg_partial_bytes(g, prec));
+        btb = std::max(btb, xg_bt_bytes(g, prec));
+      } else {
+        XsCfg x = xs_config(c, m, prec);
+        pbytes = std::max(pbytes, partial_bytes_needed(x, prec));
+      }
     }
   A(&c->partial, pbytes);
   c->partial_bytes = pbytes;
+  A(&c->Bt, btb);
+  c->bt_bytes = btb;
   if (rc) { tr_als_destroy(c); return rc; }
 
   hipStream_t s = c->stream;
@@ -523,7 +740,13 @@ int tr_als_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ran
     c->err = std::string(what) + ": " + hipGetErrorString(e);
     return true;
   };
-  if (hipfail(hipMemsetAsync(c->status, 0, 16, s), "memset")) { tr_als_destroy(c); return TR_EHIP; }
+  if (hipfail(hipMemsetAsync(c->status, 0, 16, s), "memset") ||
+      hipfail(hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking), "stream") ||
+      hipfail(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming), "event") ||
+      hipfail(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming), "event")) {
+    tr_als_destroy(c);
+    return TR_EHIP;
+  }
   for (int k = 0; k < N; ++k) {
     const size_t bytes = (size_t)c->R[k] * dims[k] * c->R[k + 1] * 8;
     if (hipfail(hipMemcpyAsync(c->cores[k], cores[k], bytes, hipMemcpyDeviceToDevice, s), "copy cores") ||
@@ -542,9 +765,38 @@ int tr_als_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ran
   return TR_OK;
 }
 
-static int update_mode(tr_als_ctx* c, int m, int prec, int refine) {
+static int update_mode(tr_als_ctx* c, int m, int prec, int refine, bool in_sweep) {
   if (c->variant == TR_QR) return fail(c, TR_EINVAL, "QR variant not available in this build");
-  return update_mode_ne(c, m, prec, refine);
+  return update_mode_ne(c, m, prec, refine, in_sweep);
+}
+
+// One sweep of mode updates captured into a HIP graph and replayed: the sweep
+// issues ~20 small kernels per mode whose launch cost would otherwise show.
+// FP8 (host-side scale readback) and profiled runs launch eagerly.
+static hipGraphExec_t sweep_graph(tr_als_ctx* c, int prec, int refine) {
+  if (!c->graphs_ok || c->prof || prec == TR_FP8 || c->variant != TR_NE) return nullptr;
+  if (c->graphs[prec][refine]) return c->graphs[prec][refine];
+  if (ensure_shadow(c, prec) != TR_OK) return nullptr;
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+    (void)hipGetLastError();
+    c->graphs_ok = false;
+    return nullptr;
+  }
+  int rc = TR_OK;
+  for (int m = 0; m < c->N && rc == TR_OK; ++m) rc = update_mode(c, m, prec, refine, true);
+  hipError_t e = hipStreamEndCapture(c->stream, &g);
+  hipGraphExec_t ex = nullptr;
+  if (rc == TR_OK && e == hipSuccess && g) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (rc != TR_OK || e != hipSuccess || !ex) {
+    (void)hipGetLastError();
+    c->graphs_ok = false;
+    c->err.clear();
+    return nullptr;
+  }
+  c->graphs[prec][refine] = ex;
+  return ex;
 }
 
 int tr_als_sweep(tr_als_ctx* c, int nsweeps, int prec, int refine) {
@@ -552,11 +804,17 @@ int tr_als_sweep(tr_als_ctx* c, int nsweeps, int prec, int refine) {
   if (nsweeps < 0 || prec < TR_F64 || prec > TR_FP8 || refine < 0 || refine > 4)
     return fail(c, TR_EINVAL, "bad sweep arguments");
   c->err.clear();
-  for (int sw = 0; sw < nsweeps; ++sw)
+  hipGraphExec_t ex = nsweeps > 0 ? sweep_graph(c, prec, refine) : nullptr;
+  for (int sw = 0; sw < nsweeps; ++sw) {
+    if (ex) {
+      HIPCHK(c, hipGraphLaunch(ex, c->stream));
+      continue;
+    }
     for (int m = 0; m < c->N; ++m) {
-      int rc = update_mode(c, m, prec, refine);
+      int rc = update_mode(c, m, prec, refine, true);
       if (rc) return rc;
     }
+  }
   int rc = read_status(c);
   // cores written back in either case: on error they hold the last good update
   int rc2 = store_cores(c);
@@ -568,7 +826,7 @@ int tr_als_sweep(tr_als_ctx* c, int nsweeps, int prec, int refine) {
 int tr_als_update_mode(tr_als_ctx* c, int n, int prec, int refine) {
   if (!valid_ctx(c) || n < 1 || n > c->N || prec < TR_F64 || prec > TR_FP8 || refine < 0 || refine > 4)
     return c ? fail(c, TR_EINVAL, "bad arguments") : TR_EINVAL;
-  int rc = update_mode(c, n - 1, prec, refine);
+  int rc = update_mode(c, n - 1, prec, refine, false);
   if (rc) return rc;
   return read_status(c);
 }
@@ -591,7 +849,7 @@ int tr_als_mttsp(tr_als_ctx* c, int n, int prec, double* Mout) {
 
 int tr_als_coef(tr_als_ctx* c, int n, double* Sout) {
   if (!valid_ctx(c) || n < 1 || n > c->N || !Sout) return c ? fail(c, TR_EINVAL, "bad arguments") : TR_EINVAL;
-  int rc = compute_coef(c, n - 1, Sout);
+  int rc = compute_coef(c, n - 1, Sout, c->stream);
   if (rc) return rc;
   return read_status(c);
 }

@@ -59,11 +59,20 @@ def test_gram_and_coef(dims, ranks):
     ctx.close()
 
 
+@pytest.fixture
+def force_regime(request, monkeypatch):
+    """Pin the MTTSP kernel: 1 = two-stage GEMM wherever a group exists,
+    2 = fused single pass, 0 = the cost rule."""
+    monkeypatch.setenv("TR_ALS_FORCE_REGIME", str(request.param))
+    return request.param
+
+
+@pytest.mark.parametrize("force_regime", [0, 1, 2], indirect=True)
 @pytest.mark.parametrize("prec,xdt,tol", [("f64", np.float64, 1e-12), ("f32", np.float32, 1e-5),
                                           ("bf16", np.float32, 2e-2), ("fp8", np.float32, 1.5e-1)])
 @pytest.mark.parametrize("dims,ranks", SHAPES, ids=[str(s[0]) for s in SHAPES])
-def test_mttsp(dims, ranks, prec, xdt, tol):
-    say(f"[mttsp] dims={dims} ranks={ranks} prec={prec}")
+def test_mttsp(dims, ranks, prec, xdt, tol, force_regime):
+    say(f"[mttsp] dims={dims} ranks={ranks} prec={prec} regime={force_regime}")
     X, init = _data(dims, ranks, 2, xdt)
     ctx, _ = _ctx(to_dev_flat(X), init, dims, ranks)
     Xd = X.astype(np.float64)
@@ -169,6 +178,26 @@ def test_mixed_schedule_final_fit(prec):
     say(f"   fit gpu {f_gpu:.6e} oracle {f_ref:.6e}")
     assert abs(f_gpu - f_ref) <= 1e-3
     ctx.close()
+
+
+def test_graph_replays_match_eager(monkeypatch):
+    """Sweeps replayed from the captured graph equal eager sweeps bit for bit,
+    replay after replay, with host synchronisation in between."""
+    w = W.make_workload(2, dims=(20, 22, 18, 16), ranks=(4, 5, 3, 4))
+    monkeypatch.setenv("TR_ALS_NO_GRAPH", "1")
+    eager, de = _ctx(to_dev_flat(w.X), w.init_cores, w.dims, w.ranks)
+    monkeypatch.delenv("TR_ALS_NO_GRAPH")
+    graph, dg = _ctx(to_dev_flat(w.X), w.init_cores, w.dims, w.ranks)
+    for prec in ("f32", "bf16", "f32"):
+        for rep in range(3):
+            eager.sweep(1, prec, refine=1)
+            graph.sweep(1, prec, refine=1)
+            a = cores_from_dev(de, w.dims, w.ranks)
+            b = cores_from_dev(dg, w.dims, w.ranks)
+            for x, y in zip(a, b):
+                assert np.array_equal(x, y), (prec, rep)
+    eager.close()
+    graph.close()
 
 
 def test_singular_and_nonfinite_paths():
