@@ -90,7 +90,19 @@ hipError_t launch_chol(const double* S, int n, double* L, double* LT, double* wo
 bool solve_in_lds(int n);
 hipError_t launch_chol_lds(const double* S, int n, double* L, double* LT, double* rdiag, int* status, hipStream_t s);
 hipError_t launch_trsm_rhs(const double* L, const double* rdiag, int n, const double* Rhs, int64_t I, double* G,
-                           int accumulate, const int* status, hipStream_t s);
+                           int accumulate, const int* status, hipStream_t s, int mode = 0);
+// QR variant
+hipError_t launch_householder_qr(double* A, int64_t m, int n, double* V, double* tau, double* Q, double* R,
+                                 hipStream_t s);
+hipError_t launch_tall_atb(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t K, int P, int Q,
+                           int mode, int64_t L, int64_t Ip, int64_t T, double* part, int64_t part_elems, double* C,
+                           hipStream_t s);
+hipError_t launch_ttm(const void* in, int in_type, int64_t L, int64_t I, int64_t T, const double* Q, int R,
+                      double scale, double* out, hipStream_t s);
+hipError_t launch_transpose(const double* A, int64_t rows, int64_t cols, double* At, hipStream_t s);
+hipError_t launch_table_to_v2(const double* T, int64_t J, int Ra, int Rb, double* V2, hipStream_t s);
+hipError_t launch_shift_and_add(double* G, int n, int64_t m, double* sbuf, hipStream_t s);
+hipError_t launch_core_fold(const double* G2, int64_t I, int Ra, int Rb, double* core, hipStream_t s);
 hipError_t launch_chol_inv(const double* S, int n, double* L, double* LT, double* LinvT, double* work, int* status,
                            hipStream_t s);
 hipError_t launch_chol_solve(const double* L, const double* LT, int n, const double* Rhs, int64_t I,

@@ -1,0 +1,293 @@
+// Kernels of the QR-stabilised update (Alg. 3), all FP64 except the first TTM,
+// which reads X in the contraction precision:
+//   - Householder QR of a core's mode-2 unfolding (Definition of the mode-n QR):
+//     explicit Q (I x r) and R (r x RR), r = min(I, RR);
+//   - tall products C = A^T B over millions of rows (Gram of V_n[2] for the
+//     shifted Cholesky-QR, and W_n = Y_[n] Q_0) on FP64 MFMA with ordered split-K;
+//   - mode products (TTM, Sec. 2) for the Multi-TTM Y = X x_{j != n} Q_j^T.
+#include <algorithm>
+
+#include "common.h"
+#include "../../include/tr_als.h"
+
+namespace {
+
+__device__ __forceinline__ void mma64(f64x4& c, double a, double b) {
+  c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ double block_sum(double v, double* red) {
+  const int tid = threadIdx.x;
+  red[tid] = v;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// Householder QR of A (m x n, column-major, overwritten).  One workgroup of
+// 1024 threads; columns are processed in order, each trailing column updated
+// by one wave.  Writes Q (m x r) and R (r x n), r = min(m, n).  V (m x r)
+// keeps the reflectors, tau (r) their scales.
+__global__ __launch_bounds__(1024) void householder_qr_kernel(double* A, int64_t m, int n, double* V, double* tau,
+                                                              double* Q, double* R) {
+  __shared__ double red[1024];
+  __shared__ double sh_alpha, sh_beta;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = (int)min<int64_t>(m, n);
+  for (int k = 0; k < r; ++k) {
+    // norm of A[k:m, k]
+    double s = 0.0;
+    for (int64_t i = k + tid; i < m; i += 1024) s += A[i + m * k] * A[i + m * k];
+    const double nrm2 = block_sum(s, red);
+    if (tid == 0) {
+      const double x0 = A[k + m * k];
+      const double nrm = sqrt(nrm2);
+      const double alpha = (x0 >= 0.0) ? -nrm : nrm;
+      const double v0 = x0 - alpha;
+      const double vtv = nrm2 - x0 * x0 + v0 * v0;
+      sh_alpha = alpha;
+      sh_beta = vtv > 0.0 ? 2.0 / vtv : 0.0;
+      A[k + m * k] = v0;   // the reflector lives in A[k:m, k] for the moment
+    }
+    __syncthreads();
+    const double beta = sh_beta;
+    for (int64_t i = k + tid; i < m; i += 1024) V[i + m * k] = A[i + m * k];
+    for (int64_t i = tid; i < k; i += 1024) V[i + m * k] = 0.0;
+    if (tid == 0) tau[k] = beta;
+    __syncthreads();
+    // apply H = I - beta v v^T to the trailing columns, one wave per column
+    for (int j = k + 1 + wave; j < n; j += 16) {
+      double d = 0.0;
+      for (int64_t i = k + lane; i < m; i += 64) d += V[i + m * k] * A[i + m * j];
+      for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off);
+      const double f = beta * d;
+      for (int64_t i = k + lane; i < m; i += 64) A[i + m * j] -= f * V[i + m * k];
+    }
+    __syncthreads();
+    if (tid == 0) A[k + m * k] = sh_alpha;
+    for (int64_t i = k + 1 + tid; i < m; i += 1024) A[i + m * k] = 0.0;
+    __syncthreads();
+  }
+  // R = upper part of the first r rows
+  for (int64_t e = tid; e < (int64_t)r * n; e += 1024) {
+    const int i = (int)(e % r), j = (int)(e / r);
+    R[e] = (i <= j) ? A[i + m * j] : 0.0;
+  }
+  // Q = H_0 H_1 ... H_{r-1} [I_r; 0]: apply the reflectors from the last
+  for (int64_t e = tid; e < m * r; e += 1024) {
+    const int64_t i = e % m, j = e / m;
+    Q[e] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int k = r - 1; k >= 0; --k) {
+    const double beta = tau[k];
+    for (int j = wave; j < r; j += 16) {
+      double d = 0.0;
+      for (int64_t i = k + lane; i < m; i += 64) d += V[i + m * k] * Q[i + m * j];
+      for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off);
+      const double f = beta * d;
+      for (int64_t i = k + lane; i < m; i += 64) Q[i + m * j] -= f * V[i + m * k];
+    }
+    __syncthreads();
+  }
+}
+
+// C_part[chunk] = A^T B over rows [chunk*kc, ...): A is K x P, B is K x Q,
+// both column-major (lda, ldb).  Mode 1 reads A through the Multi-TTM layout:
+// A(k, p) = Y[l + L*(p + Ip*t)] with the cyclic row index k = t + T*l.
+struct TallArgs {
+  const double* A; int64_t lda;
+  const double* B; int64_t ldb;
+  int64_t K; int P, Q;
+  int64_t kc;            // rows per chunk
+  int mode;              // 0 plain, 1 Multi-TTM layout
+  int64_t L, Ip, T;      // mode 1 layout
+  double* part;          // [nchunk][P][Q] (column-major P x Q per chunk)
+};
+
+__global__ __launch_bounds__(256) void tall_atb_kernel(TallArgs g) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nbp = (g.P + 15) / 16, nbq = (g.Q + 15) / 16;
+  const int64_t k0 = (int64_t)blockIdx.x * g.kc;
+  const int64_t k1 = min(g.K, k0 + g.kc);
+  double* out = g.part + (size_t)blockIdx.x * g.P * g.Q;
+  for (int blk = wave; blk < nbp * nbq; blk += 4) {
+    const int bp = blk % nbp, bq = blk / nbp;
+    const int p = bp * 16 + (lane & 15), q = bq * 16 + (lane & 15);
+    f64x4 acc = {0, 0, 0, 0};
+    for (int64_t kb = k0; kb < k1; kb += 4) {
+      const int64_t k = kb + (lane >> 4);
+      double av = 0.0, bv = 0.0;
+      if (k < k1) {
+        if (p < g.P) {
+          if (g.mode == 0) av = g.A[k + g.lda * p];
+          else {
+            const int64_t t = k % g.T, l = k / g.T;
+            av = g.A[l + g.L * (p + g.Ip * t)];
+          }
+        }
+        if (q < g.Q) bv = g.B[k + g.ldb * q];
+      }
+      mma64(acc, av, bv);
+    }
+    for (int v = 0; v < 4; ++v) {
+      const int row = bp * 16 + (lane >> 4) + 4 * v, col = bq * 16 + (lane & 15);
+      if (row < g.P && col < g.Q) out[row + (int64_t)g.P * col] = acc[v];
+    }
+  }
+}
+
+__global__ void sum_chunks_kernel(const double* part, int nchunk, int64_t n, double* C) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += part[(size_t)c * n + e];
+  C[e] = s;
+}
+
+// Mode product: out(l, r, t) = scale * sum_i in(l + L*(i + I*t)) Q(i + I*r).
+template <typename Tin>
+__global__ void ttm_kernel(const Tin* in, int64_t L, int64_t I, int64_t T, const double* Q, int R, double scale,
+                           double* out) {
+  const int64_t n = L * R * T;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t l = e % L;
+    const int64_t r = (e / L) % R;
+    const int64_t t = e / (L * R);
+    const Tin* x = in + l + L * I * t;
+    const double* q = Q + I * r;
+    double s = 0.0;
+    for (int64_t i = 0; i < I; ++i) s += (double)x[L * i] * q[i];
+    out[e] = s * scale;
+  }
+}
+
+__global__ void ttm_fp8_kernel(const uint8_t* in, int64_t L, int64_t I, int64_t T, const double* Q, int R,
+                               double scale, double* out) {
+  const int64_t n = L * R * T;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t l = e % L;
+    const int64_t r = (e / L) % R;
+    const int64_t t = e / (L * R);
+    const uint8_t* x = in + l + L * I * t;
+    const double* q = Q + I * r;
+    double s = 0.0;
+    for (int64_t i = 0; i < I; ++i) {
+      const float v = __builtin_amdgcn_cvt_f32_fp8((int)x[L * i], 0);
+      s += (double)v * q[i];
+    }
+    out[e] = s * scale;
+  }
+}
+
+__global__ void transpose_kernel(const double* A, int64_t rows, int64_t cols, double* At) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * cols) return;
+  const int64_t i = e % rows, j = e / rows;
+  At[j + cols * i] = A[e];
+}
+
+// V2[k + J*(a + Ra*b)] = T[k*C + b + Rb*a] (bond order of the subchain table
+// turned into the column order a + R_n*b of G_n(2)).
+__global__ void table_to_v2_kernel(const double* T, int64_t J, int Ra, int Rb, double* V2) {
+  const int64_t C = (int64_t)Ra * Rb;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= J * C) return;
+  const int64_t k = e % J, col = e / J;
+  const int64_t a = col % Ra, b = col / Ra;
+  V2[e] = T[k * C + b + Rb * a];
+}
+
+// core[a + Ra*(i + I*b)] = G2[i + I*(a + Ra*b)]  (inverse of the mode-2 unfolding)
+__global__ void core_fold_kernel(const double* G2, int64_t I, int Ra, int Rb, double* core) {
+  const int64_t n = I * Ra * Rb;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int a = (int)(e % Ra);
+  const int64_t i = (e / Ra) % I;
+  const int b = (int)(e / ((int64_t)Ra * I));
+  core[e] = G2[i + I * (a + (int64_t)Ra * b)];
+}
+
+// A + s*I in place on the diagonal.
+__global__ void add_diag_kernel(double* A, int n, const double* s) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) A[i + (int64_t)n * i] += *s;
+}
+
+// shift for the shifted Cholesky QR: s = 11 (m n + n (n + 1)) u ||A||_F^2, with
+// ||A||_F^2 = trace(A^T A).
+__global__ void shift_kernel(const double* G, int n, int64_t m, double* s) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double tr = 0.0;
+    for (int i = 0; i < n; ++i) tr += G[i + (int64_t)n * i];
+    const double u = 1.1102230246251565e-16;
+    *s = 11.0 * ((double)m * n + (double)n * (n + 1)) * u * tr;
+  }
+}
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace
+
+hipError_t launch_householder_qr(double* A, int64_t m, int n, double* V, double* tau, double* Q, double* R,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(householder_qr_kernel, dim3(1), dim3(1024), 0, s, A, m, n, V, tau, Q, R);
+  return hipGetLastError();
+}
+
+// C (P x Q) = A^T B over K rows, ordered split-K; part must hold nchunk*P*Q.
+hipError_t launch_tall_atb(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t K, int P, int Q,
+                           int mode, int64_t L, int64_t Ip, int64_t T, double* part, int64_t part_elems, double* C,
+                           hipStream_t s) {
+  TallArgs g;
+  g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.K = K; g.P = P; g.Q = Q; g.mode = mode;
+  g.L = L; g.Ip = Ip; g.T = T; g.part = part;
+  int64_t nchunk = std::min<int64_t>(512, std::max<int64_t>(1, part_elems / ((int64_t)P * Q)));
+  nchunk = std::min<int64_t>(nchunk, cdiv(K, 64));
+  g.kc = cdiv(cdiv(K, nchunk), 4) * 4;
+  nchunk = cdiv(K, g.kc);
+  hipLaunchKernelGGL(tall_atb_kernel, dim3((unsigned)nchunk), dim3(256), 0, s, g);
+  const int64_t n = (int64_t)P * Q;
+  hipLaunchKernelGGL(sum_chunks_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, (const double*)part, (int)nchunk, n, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_ttm(const void* in, int in_type, int64_t L, int64_t I, int64_t T, const double* Q, int R,
+                      double scale, double* out, hipStream_t s) {
+  const int64_t n = L * R * T;
+  const int64_t grid = std::min<int64_t>(cdiv(n, 256), 65536);
+  switch (in_type) {
+    case TR_F64: hipLaunchKernelGGL(ttm_kernel<double>, dim3(grid), dim3(256), 0, s, (const double*)in, L, I, T, Q, R, scale, out); break;
+    case TR_F32: hipLaunchKernelGGL(ttm_kernel<float>, dim3(grid), dim3(256), 0, s, (const float*)in, L, I, T, Q, R, scale, out); break;
+    case TR_BF16: hipLaunchKernelGGL(ttm_kernel<__bf16>, dim3(grid), dim3(256), 0, s, (const __bf16*)in, L, I, T, Q, R, scale, out); break;
+    default: hipLaunchKernelGGL(ttm_fp8_kernel, dim3(grid), dim3(256), 0, s, (const uint8_t*)in, L, I, T, Q, R, scale, out); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose(const double* A, int64_t rows, int64_t cols, double* At, hipStream_t s) {
+  hipLaunchKernelGGL(transpose_kernel, dim3(cdiv(rows * cols, 256)), dim3(256), 0, s, A, rows, cols, At);
+  return hipGetLastError();
+}
+
+hipError_t launch_table_to_v2(const double* T, int64_t J, int Ra, int Rb, double* V2, hipStream_t s) {
+  hipLaunchKernelGGL(table_to_v2_kernel, dim3(cdiv(J * Ra * Rb, 256)), dim3(256), 0, s, T, J, Ra, Rb, V2);
+  return hipGetLastError();
+}
+
+hipError_t launch_core_fold(const double* G2, int64_t I, int Ra, int Rb, double* core, hipStream_t s) {
+  hipLaunchKernelGGL(core_fold_kernel, dim3(cdiv(I * Ra * Rb, 256)), dim3(256), 0, s, G2, I, Ra, Rb, core);
+  return hipGetLastError();
+}
+
+hipError_t launch_shift_and_add(double* G, int n, int64_t m, double* sbuf, hipStream_t s) {
+  hipLaunchKernelGGL(shift_kernel, dim3(1), dim3(64), 0, s, (const double*)G, n, m, sbuf);
+  hipLaunchKernelGGL(add_diag_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, G, n, (const double*)sbuf);
+  return hipGetLastError();
+}

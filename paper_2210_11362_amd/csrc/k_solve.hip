@@ -147,12 +147,15 @@ __global__ __launch_bounds__(256) void chol_lds_kernel(const double* S, int n, d
 // forward L z^T = rhs^T, then backward L^T g^T = z^T, both blocked by 16 on
 // an identity-padded copy of L (fixed trip counts in every inner loop).
 __global__ __launch_bounds__(256) void trsm_rhs_kernel(const double* Lg, const double* rdg, int n, const double* Rhs,
-                                                       int64_t I, double* G, int accumulate, const int* status) {
+                                                       int64_t I, double* G, int accumulate, const int* status,
+                                                       int mode) {
+  // mode 0: g S = rhs with S = L L^T; 1: g L^T = rhs (forward only);
+  // 2: g L = rhs (backward only).  rdg == nullptr: reciprocals taken from L.
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double rd[256];
   if (*status != 0) return;
   const int np = (n + NB - 1) / NB * NB;
-  for (int e = threadIdx.x; e < np; e += 256) rd[e] = rdg[e];
+  for (int e = threadIdx.x; e < np; e += 256) rd[e] = rdg ? rdg[e] : (e < n ? 1.0 / Lg[e + (int64_t)n * e] : 1.0);
   double* Ls = reinterpret_cast<double*>(smem_raw);   // np x np column-major
   double* B = Ls + (size_t)np * np;                   // NRHS x np, row r at B[r + NRHS*j]
   const int tid = threadIdx.x;
@@ -169,7 +172,7 @@ __global__ __launch_bounds__(256) void trsm_rhs_kernel(const double* Lg, const d
   }
   __syncthreads();
   // forward: z_j = (b_j - sum_{t<j} L[j,t] z_t) / L[j,j]
-  for (int J = 0; J < np; J += NB) {
+  for (int J = 0; J < np && mode != 2; J += NB) {
     if (tid < NRHS) {
       const int r = tid;
       double z[NB];
@@ -196,7 +199,7 @@ __global__ __launch_bounds__(256) void trsm_rhs_kernel(const double* Lg, const d
     __syncthreads();
   }
   // backward: g_j = (z_j - sum_{t>j} L[t,j] g_t) / L[j,j]
-  for (int J = np - NB; J >= 0; J -= NB) {
+  for (int J = np - NB; J >= 0 && mode != 1; J -= NB) {
     if (tid < NRHS) {
       const int r = tid;
       double g[NB];
@@ -247,11 +250,11 @@ hipError_t launch_chol_lds(const double* S, int n, double* L, double* LT, double
 }
 
 hipError_t launch_trsm_rhs(const double* L, const double* rdiag, int n, const double* Rhs, int64_t I, double* G,
-                           int accumulate, const int* status, hipStream_t s) {
+                           int accumulate, const int* status, hipStream_t s, int mode) {
   const int np = (n + NB - 1) / NB * NB;
   const size_t lds = ((size_t)np * np + (size_t)NRHS * np) * sizeof(double);
   if (lds > 64 * 1024) hipFuncSetAttribute((const void*)trsm_rhs_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(trsm_rhs_kernel, dim3((unsigned)((I + NRHS - 1) / NRHS)), dim3(256), lds, s, L, rdiag, n, Rhs,
-                     I, G, accumulate, status);
+                     I, G, accumulate, status, mode);
   return hipGetLastError();
 }

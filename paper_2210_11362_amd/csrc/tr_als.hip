@@ -48,6 +48,16 @@ struct tr_als_ctx {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   double* Sinv = nullptr;
   double* rdiag = nullptr;                   // reciprocal pivots of the Cholesky factor
+  // QR variant state (Alg. 3): per-core Q_j (I_j x r_j) and R-cores
+  // (R_j x r_j x R_{j+1}), r_j = min(I_j, R_j R_{j+1}); workspace
+  double* qQ[TR_MAXN] = {nullptr};
+  double* qR[TR_MAXN] = {nullptr};
+  int64_t qr_r[TR_MAXN] = {0};
+  double *qA = nullptr, *qV = nullptr, *qtau = nullptr, *qRt = nullptr;
+  double *qT = nullptr, *qV2 = nullptr, *qQa = nullptr, *qQb = nullptr, *qY0 = nullptr, *qY1 = nullptr, *qW = nullptr;
+  double *qG = nullptr, *qL[3] = {nullptr, nullptr, nullptr}, *qLT = nullptr, *qRi = nullptr, *qLp = nullptr,
+         *qLt = nullptr, *qshift = nullptr, *qpart = nullptr;
+  int64_t qpart_elems = 0;
   // captured sweeps, one per (precision, refinement steps)
   hipGraphExec_t graphs[4][5] = {{nullptr}};
   bool graphs_ok = true;
@@ -257,25 +267,32 @@ int64_t table_build_max(const tr_als_ctx* c, const std::vector<int>& cl) {
   return mx;
 }
 
-// Table of the partial subchain of cores `cl` (chain order, first index fastest).
-int build_table(tr_als_ctx* c, const std::vector<int>& cl, int Rid, double* out) {
+// Table of the partial subchain of cores `cl` (chain order, first index
+// fastest); `cores`/`dims` default to the context's TR-cores (the QR variant
+// passes its R-cores and their middle sizes).
+int build_table_ex(tr_als_ctx* c, const std::vector<int>& cl, int Rid, double* out, double* const* cores,
+                   const int64_t* dims, double* t0, double* t1) {
   hipStream_t s = c->stream;
   if (cl.empty()) {
     HIPCHK(c, launch_identity_table(Rid, out, s));
     return TR_OK;
   }
   const int Rl = c->R[cl.front()];
-  double* cur = (cl.size() == 1) ? out : c->T0;
-  HIPCHK(c, launch_core_to_table(c->cores[cl[0]], Rl, c->dims[cl[0]], c->R[cl[0] + 1], cur, s));
-  int64_t J = c->dims[cl[0]];
+  double* cur = (cl.size() == 1) ? out : t0;
+  HIPCHK(c, launch_core_to_table(cores[cl[0]], Rl, dims[cl[0]], c->R[cl[0] + 1], cur, s));
+  int64_t J = dims[cl[0]];
   for (size_t q = 1; q < cl.size(); ++q) {
     const int k = cl[q];
-    double* nxt = (q + 1 == cl.size()) ? out : (cur == c->T0 ? c->T1 : c->T0);
-    HIPCHK(c, launch_chain_step(cur, J, Rl, c->R[k], c->cores[k], c->dims[k], c->R[k + 1], nxt, s));
-    J *= c->dims[k];
+    double* nxt = (q + 1 == cl.size()) ? out : (cur == t0 ? t1 : t0);
+    HIPCHK(c, launch_chain_step(cur, J, Rl, c->R[k], cores[k], dims[k], c->R[k + 1], nxt, s));
+    J *= dims[k];
     cur = nxt;
   }
   return TR_OK;
+}
+
+int build_table(tr_als_ctx* c, const std::vector<int>& cl, int Rid, double* out) {
+  return build_table_ex(c, cl, Rid, out, c->cores, c->dims, c->T0, c->T1);
 }
 
 struct XsCfg {
@@ -562,6 +579,83 @@ int update_mode_ne(tr_als_ctx* c, int m, int prec, int refine, bool in_sweep) {
   return TR_OK;
 }
 
+// Mode-2 QR of core k (Definition of the mode-n QR): Q_k and the R-core.
+int qr_core(tr_als_ctx* c, int k) {
+  hipStream_t s = c->stream;
+  const int Ra = c->R[k], Rb = c->R[k + 1], n = Ra * Rb;
+  const int64_t I = c->dims[k], r = c->qr_r[k];
+  HIPCHK(c, launch_core_unfold(c->cores[k], Ra, I, Rb, c->qA, s));
+  HIPCHK(c, launch_householder_qr(c->qA, I, n, c->qV, c->qtau, c->qQ[k], c->qRt, s));
+  HIPCHK(c, launch_core_fold(c->qRt, r, Ra, Rb, c->qR[k], s));
+  return TR_OK;
+}
+
+// One QR-variant mode update (Alg. 3): V_n = subchain of the R-cores; QR of
+// V_n[2] = Q_0 R_[2] by shifted Cholesky-QR (three passes); Y = X x_{j!=n} Q_j^T
+// (most-compressing mode first); W_n = Y_[n] Q_0; G_n(2) R_[2]^T = W_n by
+// substitution; commit; re-factor core n.
+int update_mode_qr(tr_als_ctx* c, int m, int prec) {
+  hipStream_t s = c->stream;
+  const int N = c->N;
+  const int Ra = c->R[m], Rb = c->R[m + 1], n = Ra * Rb;
+  std::vector<int> chain;
+  for (int k = 1; k < N; ++k) chain.push_back((m + k) % N);
+  int64_t Jp = 1;
+  for (int j : chain) Jp *= c->qr_r[j];
+  // V_n[2] (J' x n)
+  int rc = build_table_ex(c, chain, Rb, c->qT, c->qR, c->qr_r, c->qY0, c->qY1);
+  if (rc) return rc;
+  HIPCHK(c, launch_table_to_v2(c->qT, Jp, Ra, Rb, c->qV2, s));
+  // shifted Cholesky-QR: three passes A <- A L^{-T}, R^T = L1 L2 L3
+  double* A = c->qV2;
+  double* bufs[2] = {c->qQa, c->qQb};
+  for (int it = 0; it < 3; ++it) {
+    HIPCHK(c, launch_tall_atb(A, Jp, A, Jp, Jp, n, n, 0, 1, 1, 1, c->qpart, c->qpart_elems, c->qG, s));
+    if (it == 0) HIPCHK(c, launch_shift_and_add(c->qG, n, Jp, c->qshift, s));
+    HIPCHK(c, launch_chol_lds(c->qG, n, c->qL[it], c->qLT, c->rdiag, c->status, s));
+    HIPCHK(c, launch_trsm_rhs(c->qL[it], c->rdiag, n, nullptr, n, c->qRi, 0, c->status, s, 1));
+    MatView Av{A, Jp, 0, 0, 0}, Ri{c->qRi, n, 0, 0, 0};
+    HIPCHK(c, launch_gemm64(Jp, n, n, 1.0, Av, Ri, 0.0, nullptr, 0, bufs[it & 1], Jp, s));
+    A = bufs[it & 1];
+  }
+  {
+    MatView L1{c->qL[0], n, 0, 0, 0}, L2{c->qL[1], n, 0, 0, 0}, L3{c->qL[2], n, 0, 0, 0}, Lp{c->qLp, n, 0, 0, 0};
+    HIPCHK(c, launch_gemm64(n, n, n, 1.0, L1, L2, 0.0, nullptr, 0, c->qLp, n, s));
+    HIPCHK(c, launch_gemm64(n, n, n, 1.0, Lp, L3, 0.0, nullptr, 0, c->qLt, n, s));
+  }
+  const double* Q0 = A;
+  // Multi-TTM, most-compressing mode first
+  std::vector<int> order = chain;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return (double)c->qr_r[a] / c->dims[a] < (double)c->qr_r[b] / c->dims[b];
+  });
+  int64_t cd[TR_MAXN];
+  for (int j = 0; j < N; ++j) cd[j] = c->dims[j];
+  rc = ensure_shadow(c, prec);
+  if (rc) return rc;
+  const void* cur = prec == TR_BF16 ? c->xbf16 : prec == TR_FP8 ? c->xfp8 : c->X;
+  int ctype = (prec == TR_BF16 || prec == TR_FP8) ? prec : c->xdt;
+  double scale = prec == TR_FP8 ? 1.0 / (double)c->fp8_scale : 1.0;
+  double* ybuf[2] = {c->qY0, c->qY1};
+  int yi = 0;
+  for (int j : order) {
+    const int64_t L = prod(cd, 0, j), T = prod(cd, j + 1, N);
+    HIPCHK(c, launch_ttm(cur, ctype, L, c->dims[j], T, c->qQ[j], (int)c->qr_r[j], scale, ybuf[yi], s));
+    cd[j] = c->qr_r[j];
+    cur = ybuf[yi];
+    yi ^= 1;
+    ctype = TR_F64;
+    scale = 1.0;
+  }
+  // W_n = Y_[n] Q_0 (I_n x n)
+  HIPCHK(c, launch_tall_atb((const double*)cur, 0, Q0, Jp, Jp, (int)c->dims[m], n, 1, prod(cd, 0, m), c->dims[m],
+                            prod(cd, m + 1, N), c->qpart, c->qpart_elems, c->qW, s));
+  // G_n(2) = W_n R^{-T}: backward substitution with L = R^T
+  HIPCHK(c, launch_trsm_rhs(c->qLt, nullptr, n, c->qW, c->dims[m], c->Gn, 0, c->status, s, 2));
+  HIPCHK(c, launch_commit_core(c->Gn, c->dims[m], Ra, Rb, c->cores[m], c->status, s));
+  return qr_core(c, m);
+}
+
 int read_status(tr_als_ctx* c) {
   int st = 0;
   HIPCHK(c, hipMemcpyAsync(&st, c->status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -732,6 +826,48 @@ int tr_als_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ran
   c->partial_bytes = pbytes;
   A(&c->Bt, btb);
   c->bt_bytes = btb;
+  if (variant == TR_QR) {
+    int64_t maxJ = 1, maxTT = 1, maxHn = 1;
+    for (int k = 0; k < N; ++k) c->qr_r[k] = std::min<int64_t>(dims[k], (int64_t)c->R[k] * c->R[k + 1]);
+    for (int m = 0; m < N; ++m) {
+      int64_t Jp = 1, tb = 1;
+      for (int k = 1; k < N; ++k) {
+        const int j = (m + k) % N;
+        Jp *= c->qr_r[j];
+        tb = std::max(tb, Jp * c->R[(m + 1) % N] * c->R[j + 1]);
+      }
+      maxJ = std::max(maxJ, Jp * c->R[m] * c->R[m + 1]);
+      maxTT = std::max(maxTT, tb);
+      maxHn = std::max(maxHn, (int64_t)dims[m] * c->R[m] * c->R[m + 1]);
+      if (c->R[m] * c->R[m + 1] > 128) rc = fail(c, TR_EINVAL, "QR variant needs R_n R_{n+1} <= 128");
+    }
+    maxTT = std::max(maxTT, maxJ);
+    for (int k = 0; k < N; ++k) {
+      A((void**)&c->qQ[k], (size_t)dims[k] * c->qr_r[k] * 8);
+      A((void**)&c->qR[k], (size_t)c->R[k] * c->qr_r[k] * c->R[k + 1] * 8);
+    }
+    A((void**)&c->qA, (size_t)maxHn * 8);
+    A((void**)&c->qV, (size_t)maxHn * 8);
+    A((void**)&c->qtau, 1024 * 8);
+    A((void**)&c->qRt, (size_t)maxHn * 8);
+    A((void**)&c->qT, (size_t)maxTT * 8);
+    A((void**)&c->qV2, (size_t)maxJ * 8);
+    A((void**)&c->qQa, (size_t)maxJ * 8);
+    A((void**)&c->qQb, (size_t)maxJ * 8);
+    A((void**)&c->qY0, (size_t)std::max(numel, maxTT) * 8);
+    A((void**)&c->qY1, (size_t)std::max(numel, maxTT) * 8);
+    A((void**)&c->qW, (size_t)maxI * 128 * 8);
+    for (int it = 0; it < 3; ++it) A((void**)&c->qL[it], 128 * 128 * 8);
+    A((void**)&c->qG, 128 * 128 * 8);
+    A((void**)&c->qLT, 128 * 128 * 8);
+    A((void**)&c->qRi, 128 * 128 * 8);
+    A((void**)&c->qLp, 128 * 128 * 8);
+    A((void**)&c->qLt, 128 * 128 * 8);
+    A((void**)&c->qshift, 64);
+    c->qpart_elems = (int64_t)512 * 128 * 128;
+    A((void**)&c->qpart, (size_t)c->qpart_elems * 8);
+    if (rc) { tr_als_destroy(c); return rc; }
+  }
   if (rc) { tr_als_destroy(c); return rc; }
 
   hipStream_t s = c->stream;
@@ -755,6 +891,10 @@ int tr_als_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ran
       return TR_EHIP;
     }
   }
+  if (variant == TR_QR) {
+    for (int k = 0; k < N && rc == TR_OK; ++k) rc = qr_core(c, k);
+    if (rc) { tr_als_destroy(c); return rc; }
+  }
   if (hipfail(launch_sumsq(X, x_dtype, numel, c->dpart, c->nred, c->dscal, s), "sumsq") ||
       hipfail(hipMemcpyAsync(&c->xnorm2, c->dscal, 8, hipMemcpyDeviceToHost, s), "copy norm") ||
       hipfail(hipStreamSynchronize(s), "sync")) {
@@ -766,7 +906,7 @@ int tr_als_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ran
 }
 
 static int update_mode(tr_als_ctx* c, int m, int prec, int refine, bool in_sweep) {
-  if (c->variant == TR_QR) return fail(c, TR_EINVAL, "QR variant not available in this build");
+  if (c->variant == TR_QR) return update_mode_qr(c, m, prec);
   return update_mode_ne(c, m, prec, refine, in_sweep);
 }
 

@@ -1,0 +1,90 @@
+"""The QR-stabilised update (Alg. 3) on the GPU against the oracle's regular ALS
+from the same initial cores (the variants are mathematically equivalent)."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from tests.gpu_util import cores_from_dev, cores_to_dev, rel, say, to_dev_flat
+
+pytestmark = pytest.mark.gpu
+
+QR_SHAPES = [
+    ((30, 40), (3, 4)),
+    ((17, 20, 13, 11), (2, 3, 4, 3)),
+    ((3, 8, 9, 7), (2, 2, 3, 2)),          # core 1: I = 3 < R_1 R_2 = 4 (square Q, trapezoidal R)
+    ((6, 7, 5, 8, 6), (2, 3, 2, 2, 3)),
+    ((40, 36, 30), (5, 6, 4)),
+]
+
+
+def _ctx(X, cores, dims, ranks, variant):
+    from paper_2210_11362_amd import TRContext
+    dev = cores_to_dev(cores)
+    return TRContext(X, dims, ranks, dev, variant=variant), dev
+
+
+def _data(dims, ranks, seed, dtype=np.float64):
+    g = np.random.default_rng(seed)
+    true = W.gaussian_cores(dims, ranks, g)
+    X = W.add_noise(W.planted_tensor(true), 0.05, g)
+    init = W.gaussian_cores(dims, ranks, g)
+    return np.asfortranarray(X.astype(dtype)), init
+
+
+@pytest.mark.parametrize("dims,ranks", QR_SHAPES, ids=[str(s[0]) for s in QR_SHAPES])
+def test_qr_variant_per_sweep_f64(dims, ranks):
+    say(f"[qr f64] dims={dims} ranks={ranks}")
+    X, init = _data(dims, ranks, 11)
+    ctx, dev = _ctx(to_dev_flat(X), init, dims, ranks, "qr")
+    ref = [np.array(c) for c in init]
+    for s in range(3):
+        ref, _ = O.tr_als(X, ref, 1)
+        ctx.sweep(1, "f64")
+        got = cores_from_dev(dev, dims, ranks)
+        errs = [rel(a, b) for a, b in zip(got, ref)]
+        say(f"   sweep {s + 1}: max core rel err {max(errs):.2e}")
+        assert max(errs) <= 1e-10
+    ctx.close()
+
+
+def test_qr_matches_literal_alg3_on_conditioned_cores():
+    """Config 3's recipe (cores with condition number 1e4, ranks (6,8,10,8,6) scaled
+    to (2,3,4,3,2)) at 9^5: GPU QR sweeps track the oracle's literal Alg. 3."""
+    w = W.make_workload(3, dims=(9, 9, 9, 9, 9), ranks=(2, 3, 4, 3, 2))
+    X = w.X.astype(np.float64)
+    ctx, dev = _ctx(to_dev_flat(w.X), w.init_cores, w.dims, w.ranks, "qr")
+    ctx.sweep(2, "f64")
+    got = cores_from_dev(dev, w.dims, w.ranks)
+    ref = O.tr_als_qr_literal(X, w.init_cores, 2)
+    errs = [rel(a, b) for a, b in zip(got, ref)]
+    say(f"   core rel errs {[f'{e:.1e}' for e in errs]}")
+    assert max(errs) <= 1e-8
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_qr_variant_fit_mixed(prec):
+    w = W.make_workload(2, dims=(18, 20, 16, 14), ranks=(4, 4, 4, 4))
+    ctx, dev = _ctx(to_dev_flat(w.X), w.init_cores, w.dims, w.ranks, "qr")
+    ctx.sweep(6, prec)
+    ctx.sweep(2, "f32")
+    f_gpu = ctx.fit()
+    ref, _ = O.tr_als(w.X.astype(np.float64), w.init_cores, 8)
+    f_ref = O.rel_error(w.X.astype(np.float64), ref)
+    say(f"   [{prec}] fit gpu {f_gpu:.6e} oracle {f_ref:.6e}")
+    assert abs(f_gpu - f_ref) <= 1e-3
+    ctx.close()
+
+
+def test_qr_and_ne_agree():
+    dims, ranks = (20, 18, 16, 14), (3, 4, 3, 4)
+    X, init = _data(dims, ranks, 12)
+    a, da = _ctx(to_dev_flat(X), init, dims, ranks, "ne")
+    b, db = _ctx(to_dev_flat(X), init, dims, ranks, "qr")
+    a.sweep(4, "f64")
+    b.sweep(4, "f64")
+    for x, y in zip(cores_from_dev(da, dims, ranks), cores_from_dev(db, dims, ranks)):
+        assert rel(x, y) <= 1e-9
+    a.close()
+    b.close()
