@@ -142,6 +142,131 @@ int tr_als_profile_enable(tr_als_ctx* ctx, int enable);
 int tr_als_profile_read(tr_als_ctx* ctx, double* xstream_ms /*host*/, int64_t* launches /*host*/,
                         double* bytes_per_launch /*host, algorithmic X bytes*/);
 
+/* ------------------------------------------------------------------------ *
+ * Planted test tensors generated on the device.
+ *
+ * The paper's synthetic recipe (Sec. 4): TR-cores with N(0,1) entries, the
+ * full tensor X_true = TR(G_1..G_N), then X = X_true + eta (||X_true|| / ||E||) E
+ * with E i.i.d. N(0,1).  Every normal number comes from the counter-based
+ * Philox4x32-10 generator (Salmon et al., SC'11; 10 rounds, key = seed) with the
+ * Box-Muller transform: normal e of stream sid is taken from pair p = e/2 drawn
+ * at counter (p mod 2^32, p / 2^32, sid, 0); words (0,1) and (2,3) give 53-bit
+ * uniforms u, v = (m + 0.5) 2^-53; element 2p is sqrt(-2 ln u) cos(2 pi v),
+ * element 2p+1 uses sin.  Streams: 0 the noise E (element = linear index of
+ * X), 0x100 + k true core k, 0x200 + k initial core k (k = 0..N-1, element =
+ * offset in the core layout above).  X_true is rounded to x_dtype, then the
+ * scaled noise is added in FP64 and rounded again.
+ * ------------------------------------------------------------------------ */
+
+/*
+ * tr_gen_planted -- write the planted tensor into X (prod(I_n) elements of
+ * x_dtype, TR_F32 or TR_F64).  true_cores: host array of N device pointers that
+ * receive the true cores, or NULL (kept in internal workspace).  init_cores:
+ * host array of N device pointers that receive N(0,1) initial cores, or NULL.
+ * eta >= 0 (0: no noise).  Allocates and frees its workspace; synchronises the
+ * stream.  Limits as tr_als_init.
+ */
+int tr_gen_planted(int N, const int64_t* dims, const int64_t* ranks, uint64_t seed, double eta, void* X,
+                   int x_dtype, double* const* true_cores, double* const* init_cores, void* hip_stream);
+
+/* ------------------------------------------------------------------------ *
+ * Serving: a request loop that runs many decomposition jobs on one GPU.
+ *
+ * Jobs are submitted without blocking, each with an arrival time.  A scheduler
+ * thread admits arrived jobs in arrival order when a slot is free and the
+ * job's whole HBM footprint (X, its BF16/FP8 shadow, cores, Grams and all
+ * workspace, computed exactly before admission) fits in the server's arena;
+ * a job that does not fit holds the queue for larger jobs while small jobs
+ * (footprint <= arena / 64) may pass it, until it has waited 0.5 s.  Admitted
+ * jobs run concurrently on their slots' streams; each keeps its cores and Gram
+ * matrices resident in its arena region until it finishes.  A job runs the
+ * planted-tensor generator above (or borrows the caller's X), nsweeps_mixed
+ * sweeps in prec_mixed, nsweeps_fin sweeps in prec_fin, and the fit; its final
+ * cores are kept on the host for tr_srv_result.  All kernels are
+ * deterministic, so a job's result does not depend on what else runs.
+ * Small same-shape-class jobs are batched (see TR_SRV_BATCH below).
+ * All times are seconds since tr_srv_create (steady clock).
+ * ------------------------------------------------------------------------ */
+
+typedef struct tr_srv tr_srv;
+
+enum { TR_JOB_QUEUED = 0, TR_JOB_RUNNING = 1, TR_JOB_DONE = 2, TR_JOB_FAILED = 3 };
+
+typedef struct {
+  int N;                      /* order, 2..8 */
+  int64_t dims[8];            /* I_1..I_N */
+  int64_t ranks[8];           /* R_1..R_N, 1..24 */
+  int variant;                /* TR_NE or TR_QR */
+  int prec_mixed;             /* contraction precision of the first sweeps */
+  int nsweeps_mixed;
+  int prec_fin;               /* contraction precision of the finishing sweeps */
+  int nsweeps_fin;
+  int refine;                 /* refinement steps of the NE solve, 0..4 */
+  uint64_t seed;              /* generator key (X, true and initial cores) */
+  double eta;                 /* relative noise of the generated X, >= 0 */
+  const void* X;              /* NULL: generate; else the caller's tensor (device,
+                                 borrowed read-only until the job is done) */
+  int x_dtype;                /* TR_F32 or TR_F64: storage type of X */
+  const double* const* init_cores; /* NULL: N(0,1) from seed; else host array of N
+                                 device pointers, copied when the job starts */
+  double t_arrival;           /* arrival time; earlier than the submit time = on submit */
+} tr_job_desc;
+
+typedef struct {
+  int state;                  /* TR_JOB_* */
+  int status;                 /* TR_OK or the failing step's code */
+  double rel_err;             /* final ||X - TR(G)|| / ||X|| (NaN until done) */
+  double t_arrival, t_admit, t_done;   /* t_admit/t_done < 0 until reached */
+  size_t footprint;           /* HBM bytes reserved for the job */
+  int slot;                   /* slot that ran it (-1 before admission) */
+  int batched;                /* 1 if it ran in a batched group */
+} tr_job_info;
+
+typedef struct {
+  uint64_t submitted, done, failed;
+  size_t arena_bytes;         /* HBM budget */
+  size_t peak_in_use;         /* largest sum of admitted footprints */
+  int slots;
+  int max_running;            /* most jobs admitted at once */
+} tr_srv_stats;
+
+/*
+ * tr_srv_create -- start a server on the current device.
+ *   hbm_budget_bytes  size of the device arena all jobs are carved from
+ *                     (0: 90% of the free device memory); allocated here.
+ *   max_slots         concurrent jobs, 1..64; each slot owns a thread and
+ *                     two streams (default priority).
+ *   flags             TR_SRV_BATCH: allow batching of small jobs.
+ * Returns TR_EINVAL, TR_ENOMEM (arena allocation) or TR_EHIP on failure.
+ */
+enum { TR_SRV_BATCH = 1 };
+int tr_srv_create(tr_srv** srv, size_t hbm_budget_bytes, int max_slots, int flags);
+
+/* Queue a job (host descriptor, copied).  Never blocks.  TR_EINVAL for an
+ * invalid descriptor, TR_ENOMEM if its footprint exceeds the whole arena. */
+int tr_srv_submit(tr_srv* srv, const tr_job_desc* desc, uint64_t* job_id /*host out*/);
+
+/* Current state of a job (host out). */
+int tr_srv_poll(tr_srv* srv, uint64_t job_id, tr_job_info* info);
+
+/* Block until the job is done or failed; then as tr_srv_poll. */
+int tr_srv_wait(tr_srv* srv, uint64_t job_id, tr_job_info* info);
+
+/* Copy a finished job's final cores into N host arrays (layout above). */
+int tr_srv_result(tr_srv* srv, uint64_t job_id, double* const* cores_host);
+
+/* Block until every submitted job is done or failed. */
+int tr_srv_drain(tr_srv* srv);
+
+int tr_srv_stats_read(tr_srv* srv, tr_srv_stats* out /*host*/);
+
+/* Drop queued jobs, finish running ones, free the arena and streams.  NULL is
+ * accepted. */
+int tr_srv_destroy(tr_srv* srv);
+
+/* Text of the failure of a job ("" if none); valid until tr_srv_destroy. */
+const char* tr_srv_job_error(tr_srv* srv, uint64_t job_id);
+
 #ifdef __cplusplus
 }
 #endif

@@ -6,4 +6,4 @@ and the stream.
 """
 from ._lib import (PREC, TR_BF16, TR_F32, TR_F64, TR_FP8, TR_NE, TR_QR, VARIANT, TRError,  # noqa: F401
                    header_symbols, lib)
-from .api import TRContext  # noqa: F401
+from .api import TRContext, TRServer, gen_planted  # noqa: F401

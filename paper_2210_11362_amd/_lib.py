@@ -40,6 +40,47 @@ _SIGS = {
     "tr_als_profile_read": (ctypes.c_int, [_vp, _dp, _i64p, _dp]),
 }
 
+
+class JobDesc(ctypes.Structure):
+    """tr_job_desc."""
+    _fields_ = [("N", ctypes.c_int), ("dims", ctypes.c_int64 * 8), ("ranks", ctypes.c_int64 * 8),
+                ("variant", ctypes.c_int), ("prec_mixed", ctypes.c_int), ("nsweeps_mixed", ctypes.c_int),
+                ("prec_fin", ctypes.c_int), ("nsweeps_fin", ctypes.c_int), ("refine", ctypes.c_int),
+                ("seed", ctypes.c_uint64), ("eta", ctypes.c_double), ("X", _vp), ("x_dtype", ctypes.c_int),
+                ("init_cores", ctypes.POINTER(_vp)), ("t_arrival", ctypes.c_double)]
+
+
+class JobInfo(ctypes.Structure):
+    """tr_job_info."""
+    _fields_ = [("state", ctypes.c_int), ("status", ctypes.c_int), ("rel_err", ctypes.c_double),
+                ("t_arrival", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("footprint", ctypes.c_size_t), ("slot", ctypes.c_int), ("batched", ctypes.c_int)]
+
+
+class SrvStats(ctypes.Structure):
+    """tr_srv_stats."""
+    _fields_ = [("submitted", ctypes.c_uint64), ("done", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+                ("arena_bytes", ctypes.c_size_t), ("peak_in_use", ctypes.c_size_t), ("slots", ctypes.c_int),
+                ("max_running", ctypes.c_int)]
+
+
+TR_JOB_QUEUED, TR_JOB_RUNNING, TR_JOB_DONE, TR_JOB_FAILED = 0, 1, 2, 3
+TR_SRV_BATCH = 1
+
+_SIGS.update({
+    "tr_gen_planted": (ctypes.c_int, [ctypes.c_int, _i64p, _i64p, ctypes.c_uint64, ctypes.c_double, _vp,
+                                      ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp]),
+    "tr_srv_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_size_t, ctypes.c_int, ctypes.c_int]),
+    "tr_srv_submit": (ctypes.c_int, [_vp, ctypes.POINTER(JobDesc), ctypes.POINTER(ctypes.c_uint64)]),
+    "tr_srv_poll": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(JobInfo)]),
+    "tr_srv_wait": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(JobInfo)]),
+    "tr_srv_result": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(_vp)]),
+    "tr_srv_drain": (ctypes.c_int, [_vp]),
+    "tr_srv_stats_read": (ctypes.c_int, [_vp, ctypes.POINTER(SrvStats)]),
+    "tr_srv_destroy": (ctypes.c_int, [_vp]),
+    "tr_srv_job_error": (ctypes.c_char_p, [_vp, ctypes.c_uint64]),
+})
+
 _lib = None
 
 

@@ -118,3 +118,144 @@ class TRContext:
 
     def __exit__(self, *a):
         self.close()
+
+
+def gen_planted(dims, ranks, seed: int, eta: float, dtype=None, want_true: bool = False, want_init: bool = True,
+                stream=None):
+    """Planted TR tensor generated on the device (``tr_gen_planted``): returns
+    (X flat CUDA tensor, true cores or None, initial cores or None); cores are
+    flat CUDA float64 tensors in the core layout."""
+    import torch
+    dtype = dtype or torch.float32
+    xdt = {torch.float64: C.TR_F64, torch.float32: C.TR_F32}[dtype]
+    dims = tuple(int(d) for d in dims)
+    ranks = tuple(int(r) for r in ranks)
+    N = len(dims)
+    numel = 1
+    for d in dims:
+        numel *= d
+    X = torch.empty(numel, dtype=dtype, device="cuda")
+
+    def cores():
+        return [torch.empty(ranks[k] * dims[k] * ranks[(k + 1) % N], dtype=torch.float64, device="cuda")
+                for k in range(N)]
+
+    true = cores() if want_true else None
+    init = cores() if want_init else None
+    ptrs = lambda cs: (ctypes.c_void_p * N)(*[c.data_ptr() for c in cs]) if cs is not None else None
+    rc = C.lib().tr_gen_planted(N, (ctypes.c_int64 * N)(*dims), (ctypes.c_int64 * N)(*ranks),
+                                ctypes.c_uint64(int(seed) & (2**64 - 1)), float(eta), ctypes.c_void_p(X.data_ptr()),
+                                xdt, ptrs(true), ptrs(init), _stream_handle(stream))
+    C.check(rc, None, "tr_gen_planted")
+    return X, true, init
+
+
+class TRServer:
+    """Request loop over the serving C ABI (``tr_srv_*``): jobs are submitted
+    with an arrival time, admitted by HBM footprint into the server's arena and
+    run concurrently on its slots."""
+
+    def __init__(self, hbm_budget_bytes: int = 0, slots: int = 8, batch: bool = False):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("TRServer needs a GPU")
+        h = ctypes.c_void_p()
+        rc = C.lib().tr_srv_create(ctypes.byref(h), ctypes.c_size_t(int(hbm_budget_bytes)), int(slots),
+                                   C.TR_SRV_BATCH if batch else 0)
+        C.check(rc, None, "tr_srv_create")
+        self._h = h
+        self._keep = {}
+
+    def submit(self, dims, ranks, seed: int = 0, eta: float = 0.01, prec_mixed: str = "bf16",
+               nsweeps_mixed: int = 8, prec_fin: str = "f32", nsweeps_fin: int = 2, refine: int = 1,
+               variant: str = "ne", t_arrival: float = 0.0, X=None, init_cores=None, x_dtype: str = "f32") -> int:
+        import torch
+        d = C.JobDesc()
+        N = len(dims)
+        d.N = N
+        for k in range(N):
+            d.dims[k] = int(dims[k])
+            d.ranks[k] = int(ranks[k])
+        d.variant = C.VARIANT[variant]
+        d.prec_mixed, d.nsweeps_mixed = C.PREC[prec_mixed], int(nsweeps_mixed)
+        d.prec_fin, d.nsweeps_fin = C.PREC[prec_fin], int(nsweeps_fin)
+        d.refine = int(refine)
+        d.seed = int(seed) & (2**64 - 1)
+        d.eta = float(eta)
+        keep = []
+        if X is not None:
+            if not X.is_cuda or not X.is_contiguous():
+                raise ValueError("X must be a contiguous CUDA tensor")
+            d.X = ctypes.c_void_p(X.data_ptr())
+            d.x_dtype = {torch.float64: C.TR_F64, torch.float32: C.TR_F32}[X.dtype]
+            keep.append(X)
+        else:
+            d.x_dtype = C.PREC[x_dtype]
+        if init_cores is not None:
+            arr = (ctypes.c_void_p * N)(*[c.data_ptr() for c in init_cores])
+            d.init_cores = ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p))
+            keep += [arr, *init_cores]
+        d.t_arrival = float(t_arrival)
+        jid = ctypes.c_uint64()
+        C.check(C.lib().tr_srv_submit(self._h, ctypes.byref(d), ctypes.byref(jid)), None, "tr_srv_submit")
+        if keep:
+            self._keep[jid.value] = keep
+        return jid.value
+
+    @staticmethod
+    def _info(i):
+        return {"state": i.state, "status": i.status, "rel_err": i.rel_err, "t_arrival": i.t_arrival,
+                "t_admit": i.t_admit, "t_done": i.t_done, "footprint": i.footprint, "slot": i.slot,
+                "batched": bool(i.batched)}
+
+    def poll(self, jid: int) -> dict:
+        i = C.JobInfo()
+        C.check(C.lib().tr_srv_poll(self._h, ctypes.c_uint64(jid), ctypes.byref(i)), None, "tr_srv_poll")
+        return self._info(i)
+
+    def wait(self, jid: int) -> dict:
+        i = C.JobInfo()
+        C.check(C.lib().tr_srv_wait(self._h, ctypes.c_uint64(jid), ctypes.byref(i)), None, "tr_srv_wait")
+        self._keep.pop(jid, None)
+        return self._info(i)
+
+    def error(self, jid: int) -> str:
+        return C.lib().tr_srv_job_error(self._h, ctypes.c_uint64(jid)).decode()
+
+    def result(self, jid: int, dims, ranks):
+        """Final cores of a finished job as Fortran-ordered numpy arrays."""
+        import numpy as np
+        N = len(dims)
+        outs = [np.zeros(int(ranks[k]) * int(dims[k]) * int(ranks[(k + 1) % N]), dtype=np.float64)
+                for k in range(N)]
+        arr = (ctypes.c_void_p * N)(*[o.ctypes.data for o in outs])
+        C.check(C.lib().tr_srv_result(self._h, ctypes.c_uint64(jid), arr), None, "tr_srv_result")
+        return [np.asfortranarray(o.reshape((int(ranks[k]), int(dims[k]), int(ranks[(k + 1) % N])), order="F"))
+                for k, o in enumerate(outs)]
+
+    def drain(self):
+        C.check(C.lib().tr_srv_drain(self._h), None, "tr_srv_drain")
+        self._keep.clear()
+
+    def stats(self) -> dict:
+        s = C.SrvStats()
+        C.check(C.lib().tr_srv_stats_read(self._h, ctypes.byref(s)), None, "tr_srv_stats_read")
+        return {k: getattr(s, k) for k, _ in C.SrvStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            C.lib().tr_srv_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -118,3 +118,11 @@ hipError_t launch_fit(const void* X, int xdt, int64_t I, int64_t K, const double
                       const double* F2, int64_t d1, int64_t m1, int64_t d2, int64_t m2, int Rb, int Rmid, int Ra,
                       double* partials, int nblk, double* out, hipStream_t s);
 hipError_t launch_table_absmax(const double* T, int64_t n, double* out, hipStream_t s);
+// planted-tensor generator (serving)
+hipError_t launch_philox_normal(double* out, int64_t n, uint64_t seed, uint32_t sid, hipStream_t s);
+hipError_t launch_gen_planted(void* X, int xdt, int64_t I, int64_t K, const double* G0, const double* F1,
+                              const double* F2, int64_t d1, int64_t m1, int64_t d2, int64_t m2, int Rb, int Rmid,
+                              int Ra, uint64_t seed, double eta, double* partials, int nblk, double* scal,
+                              hipStream_t s);
+// Philox stream ids of the generator's normal numbers
+enum { GEN_SID_NOISE = 0, GEN_SID_TRUE = 0x100, GEN_SID_INIT = 0x200 };

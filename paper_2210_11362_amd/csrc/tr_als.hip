@@ -9,7 +9,7 @@
 #include <vector>
 
 #include "common.h"
-#include "../../include/tr_als.h"
+#include "runtime.h"
 
 namespace {
 
@@ -66,6 +66,12 @@ struct tr_als_ctx {
   Plan plan[TR_MAXN];
   // workspace
   std::vector<void*> allocs;
+  // workspace carved from a caller-supplied region (serving) or only sized
+  char* region = nullptr;
+  size_t region_cap = 0, region_off = 0;
+  bool measure = false;
+  bool own_stream2 = true;
+  bool bf16_ready = false, fp8_ready = false;
   double *F1 = nullptr, *F2 = nullptr, *T0 = nullptr, *T1 = nullptr;
   double *M = nullptr, *S = nullptr, *W0 = nullptr, *W1 = nullptr, *Lf = nullptr, *LTf = nullptr, *cholw = nullptr;
   double *Gn = nullptr, *Res = nullptr, *G0u = nullptr, *LinvT = nullptr, *Tsol = nullptr;
@@ -109,6 +115,17 @@ int fail(tr_als_ctx* c, int code, const std::string& msg) {
 
 int alloc(tr_als_ctx* c, void** p, size_t bytes) {
   if (bytes == 0) bytes = 16;
+  if (c->measure || c->region) {
+    const size_t b = trx_round(bytes);
+    if (c->region && c->region_off + b > c->region_cap) {
+      *p = nullptr;
+      return fail(c, TR_ENOMEM, "workspace region of " + std::to_string(c->region_cap) + " bytes exhausted");
+    }
+    // sizing only: a distinct, never dereferenced, aligned placeholder
+    *p = c->region ? (void*)(c->region + c->region_off) : (void*)(TRX_ALIGN + c->region_off);
+    c->region_off += b;
+    return TR_OK;
+  }
   hipError_t e = hipMalloc(p, bytes);
   if (e != hipSuccess) {
     *p = nullptr;
@@ -391,14 +408,20 @@ size_t partial_bytes_needed(const XsCfg& x, int prec) {
 
 int ensure_shadow(tr_als_ctx* c, int prec) {
   hipStream_t s = c->stream;
-  if (prec == TR_BF16 && !c->xbf16) {
-    int rc = alloc(c, &c->xbf16, (size_t)c->numel * 2);
-    if (rc) return rc;
+  if (prec == TR_BF16 && !c->bf16_ready) {
+    if (!c->xbf16) {
+      int rc = alloc(c, &c->xbf16, (size_t)c->numel * 2);
+      if (rc) return rc;
+    }
     HIPCHK(c, launch_to_bf16(c->X, c->xdt, c->numel, c->xbf16, s));
+    c->bf16_ready = true;
   }
-  if (prec == TR_FP8 && !c->xfp8) {
-    int rc = alloc(c, &c->xfp8, (size_t)c->numel);
-    if (rc) return rc;
+  if (prec == TR_FP8 && !c->fp8_ready) {
+    if (!c->xfp8) {
+      int rc = alloc(c, &c->xfp8, (size_t)c->numel);
+      if (rc) return rc;
+    }
+    c->fp8_ready = true;
     HIPCHK(c, launch_absmax(c->X, c->xdt, c->numel, c->fpart, c->nred, c->fscal, s));
     HIPCHK(c, launch_to_fp8(c->X, c->xdt, c->numel, c->fscal, c->fscal + 1, c->xfp8, s));
     HIPCHK(c, hipMemcpyAsync(&c->fp8_scale, c->fscal + 1, sizeof(float), hipMemcpyDeviceToHost, s));
@@ -710,12 +733,19 @@ const char* tr_als_last_error(const tr_als_ctx* ctx) { return ctx ? ctx->err.c_s
 
 int tr_als_destroy(tr_als_ctx* ctx) {
   if (!ctx) return TR_OK;
+  if (ctx->measure) {
+    delete ctx;
+    return TR_OK;
+  }
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   for (auto& e : ctx->evs) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
   for (auto& row : ctx->graphs)
     for (auto& g : row)
       if (g) (void)hipGraphExecDestroy(g);
-  if (ctx->stream2) { (void)hipStreamSynchronize(ctx->stream2); (void)hipStreamDestroy(ctx->stream2); }
+  if (ctx->stream2) {
+    (void)hipStreamSynchronize(ctx->stream2);
+    if (ctx->own_stream2) (void)hipStreamDestroy(ctx->stream2);
+  }
   if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
   if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
   for (void* p : ctx->allocs) (void)hipFree(p);
@@ -725,9 +755,20 @@ int tr_als_destroy(tr_als_ctx* ctx) {
 
 int tr_als_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ranks, const void* X, int x_dtype,
                 double* const* cores, int variant, void* hip_stream) {
+  return trx_init(out, N, dims, ranks, X, x_dtype, cores, variant, (hipStream_t)hip_stream, TrxOpts());
+}
+
+}  // extern "C"
+
+int trx_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ranks, const void* X, int x_dtype,
+             double* const* cores, int variant, hipStream_t hip_stream, const TrxOpts& o) {
   if (!out) return TR_EINVAL;
   *out = nullptr;
-  if (N < 2 || N > TR_MAXN || !dims || !ranks || !X || !cores) return TR_EINVAL;
+  if (o.measure) {
+    if (!o.measured) return TR_EINVAL;
+    *o.measured = 0;
+  }
+  if (N < 2 || N > TR_MAXN || !dims || !ranks || (!o.measure && (!X || !cores))) return TR_EINVAL;
   if (x_dtype != TR_F64 && x_dtype != TR_F32) return TR_EINVAL;
   if (variant != TR_NE && variant != TR_QR) return TR_EINVAL;
   int64_t numel = 1;
@@ -735,9 +776,12 @@ int tr_als_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ran
     if (dims[k] < 1 || ranks[k] < 1 || ranks[k] > TR_MAXR) return TR_EINVAL;
     if (numel > (int64_t(1) << 62) / dims[k]) return TR_EINVAL;
     numel *= dims[k];
-    if (!cores[k]) return TR_EINVAL;
+    if (!o.measure && !cores[k]) return TR_EINVAL;
   }
   tr_als_ctx* c = new tr_als_ctx();
+  c->measure = o.measure;
+  c->region = o.region;
+  c->region_cap = o.region_bytes;
   c->N = N;
   for (int k = 0; k < N; ++k) { c->dims[k] = dims[k]; c->R[k] = (int)ranks[k]; }
   c->R[N] = c->R[0];
@@ -745,9 +789,10 @@ int tr_als_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ran
   c->xdt = x_dtype;
   c->X = X;
   c->numel = numel;
-  c->stream = (hipStream_t)hip_stream;
-  c->user_cores.assign(cores, cores + N);
+  c->stream = hip_stream;
+  if (!o.measure) c->user_cores.assign(cores, cores + N);
   if (const char* ev = getenv("TR_ALS_NO_GRAPH")) c->graphs_ok = (ev[0] == '0');
+  if (o.graphs >= 0) c->graphs_ok = o.graphs == 1;
   for (int m = 0; m < N; ++m) c->plan[m] = make_plan(c, m);
   // within a sweep, mode m can reuse mode m-1's group table when the groups
   // match and the core updated by mode m-1 is not part of it
@@ -868,7 +913,14 @@ int tr_als_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ran
     A((void**)&c->qpart, (size_t)c->qpart_elems * 8);
     if (rc) { tr_als_destroy(c); return rc; }
   }
+  if (o.shadow_mask & (1u << TR_BF16)) A(&c->xbf16, (size_t)numel * 2);
+  if (o.shadow_mask & (1u << TR_FP8)) A(&c->xfp8, (size_t)numel);
   if (rc) { tr_als_destroy(c); return rc; }
+  if (c->measure) {
+    *o.measured = c->region_off;
+    tr_als_destroy(c);
+    return TR_OK;
+  }
 
   hipStream_t s = c->stream;
   auto hipfail = [&](hipError_t e, const char* what) {
@@ -877,7 +929,8 @@ int tr_als_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ran
     return true;
   };
   if (hipfail(hipMemsetAsync(c->status, 0, 16, s), "memset") ||
-      hipfail(hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking), "stream") ||
+      (o.stream2 ? ((c->stream2 = o.stream2), (c->own_stream2 = false)) :
+                   hipfail(hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking), "stream")) ||
       hipfail(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming), "event") ||
       hipfail(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming), "event")) {
     tr_als_destroy(c);
@@ -904,6 +957,131 @@ int tr_als_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ran
   *out = c;
   return TR_OK;
 }
+
+size_t trx_footprint(int N, const int64_t* dims, const int64_t* ranks, int x_dtype, int variant,
+                     unsigned shadow_mask) {
+  TrxOpts o;
+  size_t bytes = 0;
+  o.measure = true;
+  o.measured = &bytes;
+  o.shadow_mask = shadow_mask;
+  tr_als_ctx* c = nullptr;
+  if (trx_init(&c, N, dims, ranks, nullptr, x_dtype, nullptr, variant, nullptr, o) != TR_OK) return 0;
+  return bytes;
+}
+
+// ---------------------------------------------------------------------------
+// Planted-tensor generator: true cores (Philox normals), the split of mode 1's
+// subchain into two partial-subchain tables (as for the fit), X_true tiles,
+// relative noise; optionally N(0,1) initial cores from the same key.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct GenLayout {
+  Plan p;
+  size_t cores[TR_MAXN] = {0};
+  size_t F1 = 0, F2 = 0, T0 = 0, T1 = 0, G0 = 0, part = 0, scal = 0, total = 0;
+  int nblk = 1024;
+};
+
+bool gen_shape(tr_als_ctx& g, int N, const int64_t* dims, const int64_t* ranks) {
+  if (N < 2 || N > TR_MAXN || !dims || !ranks) return false;
+  g.N = N;
+  g.numel = 1;
+  for (int k = 0; k < N; ++k) {
+    if (dims[k] < 1 || ranks[k] < 1 || ranks[k] > TR_MAXR) return false;
+    if (g.numel > (int64_t(1) << 62) / dims[k]) return false;
+    g.dims[k] = dims[k];
+    g.R[k] = (int)ranks[k];
+    g.numel *= dims[k];
+  }
+  g.R[N] = g.R[0];
+  return true;
+}
+
+GenLayout gen_layout(tr_als_ctx& g, bool need_true) {
+  GenLayout L;
+  L.p = make_plan(&g, 0);
+  size_t off = 0;
+  auto take = [&](size_t bytes) { const size_t o = off; off += trx_round(bytes ? bytes : 16); return o; };
+  for (int k = 0; k < g.N; ++k)
+    L.cores[k] = need_true ? take((size_t)g.R[k] * g.dims[k] * g.R[k + 1] * 8) : 0;
+  L.F1 = take((size_t)table_elems(&g, L.p.f1c, L.p.Rmid) * 8);
+  L.F2 = take((size_t)table_elems(&g, L.p.f2c, L.p.Rmid) * 8);
+  const int64_t tb = std::max<int64_t>(1, std::max(table_build_max(&g, L.p.f1c), table_build_max(&g, L.p.f2c)));
+  L.T0 = take((size_t)tb * 8);
+  L.T1 = take((size_t)tb * 8);
+  L.G0 = take((size_t)L.p.I * L.p.Ra * L.p.Rb * 8);
+  L.part = take((size_t)2 * L.nblk * 8);
+  L.scal = take(8 * 8);
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+size_t trx_gen_workspace(int N, const int64_t* dims, const int64_t* ranks, bool need_true_cores) {
+  tr_als_ctx g;
+  if (!gen_shape(g, N, dims, ranks)) return 0;
+  return gen_layout(g, need_true_cores).total;
+}
+
+int trx_gen(int N, const int64_t* dims, const int64_t* ranks, uint64_t seed, double eta, void* X, int x_dtype,
+            double* const* true_cores, double* const* init_cores, char* ws, size_t ws_bytes, hipStream_t s,
+            std::string* err) {
+  tr_als_ctx g;
+  auto bad = [&](int code, const char* msg) { if (err) *err = msg; return code; };
+  if (!gen_shape(g, N, dims, ranks) || !X || !ws || (x_dtype != TR_F64 && x_dtype != TR_F32) || !(eta >= 0.0))
+    return bad(TR_EINVAL, "invalid generator arguments");
+  const GenLayout L = gen_layout(g, true_cores == nullptr);
+  if (ws_bytes < L.total) return bad(TR_EINVAL, "generator workspace too small");
+  g.stream = s;
+  for (int k = 0; k < N; ++k) {
+    g.cores[k] = true_cores ? true_cores[k] : (double*)(ws + L.cores[k]);
+    const int64_t n = (int64_t)g.R[k] * g.dims[k] * g.R[k + 1];
+    if (launch_philox_normal(g.cores[k], n, seed, GEN_SID_TRUE + k, s) != hipSuccess)
+      return bad(TR_EHIP, "generator launch failed");
+    if (init_cores && launch_philox_normal(init_cores[k], n, seed, GEN_SID_INIT + k, s) != hipSuccess)
+      return bad(TR_EHIP, "generator launch failed");
+  }
+  double* F1 = (double*)(ws + L.F1);
+  double* F2 = (double*)(ws + L.F2);
+  double* G0 = (double*)(ws + L.G0);
+  const Plan& p = L.p;
+  int rc = build_table_ex(&g, p.f1c, p.Rmid, F1, g.cores, g.dims, (double*)(ws + L.T0), (double*)(ws + L.T1));
+  if (rc == TR_OK)
+    rc = build_table_ex(&g, p.f2c, p.Rmid, F2, g.cores, g.dims, (double*)(ws + L.T0), (double*)(ws + L.T1));
+  if (rc) return bad(rc, g.err.c_str());
+  if (launch_core_unfold(g.cores[0], p.Ra, p.I, p.Rb, G0, s) != hipSuccess ||
+      launch_gen_planted(X, x_dtype, p.I, p.K, G0, F1, F2, p.d1, p.m1, p.d2, p.m2, p.Rb, p.Rmid, p.Ra, seed, eta,
+                         (double*)(ws + L.part), L.nblk, (double*)(ws + L.scal), s) != hipSuccess)
+    return bad(TR_EHIP, "generator launch failed");
+  return TR_OK;
+}
+
+extern "C" {
+
+int tr_gen_planted(int N, const int64_t* dims, const int64_t* ranks, uint64_t seed, double eta, void* X,
+                   int x_dtype, double* const* true_cores, double* const* init_cores, void* hip_stream) {
+  if (N < 2 || N > TR_MAXN || !dims || !ranks || !X) return TR_EINVAL;
+  const size_t ws = trx_gen_workspace(N, dims, ranks, true_cores == nullptr);
+  if (ws == 0) return TR_EINVAL;
+  hipStream_t s = (hipStream_t)hip_stream;
+  void* buf = nullptr;
+  if (hipMalloc(&buf, ws) != hipSuccess) {
+    (void)hipGetLastError();
+    return TR_ENOMEM;
+  }
+  int rc = trx_gen(N, dims, ranks, seed, eta, X, x_dtype, true_cores, init_cores, (char*)buf, ws, s, nullptr);
+  const hipError_t e = hipStreamSynchronize(s);
+  (void)hipFree(buf);
+  if (rc == TR_OK && e != hipSuccess) rc = TR_EHIP;
+  return rc;
+}
+
+}  // extern "C"
+
+extern "C" {
 
 static int update_mode(tr_als_ctx* c, int m, int prec, int refine, bool in_sweep) {
   if (c->variant == TR_QR) return update_mode_qr(c, m, prec);
