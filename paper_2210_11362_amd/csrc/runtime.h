@@ -22,6 +22,7 @@ struct TrxOpts {
   hipStream_t stream2 = nullptr; // borrowed stream for the coefficient branch (else one is created)
   unsigned shadow_mask = 0;      // bit p set: the X shadow of precision p is reserved at init
   int graphs = -1;               // -1: environment default, 0: never capture sweeps, 1: capture
+  bool no_sync = false;          // leave ||X||^2 on the device; creation never waits on the stream
 };
 
 int trx_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ranks, const void* X, int x_dtype,
@@ -38,3 +39,13 @@ size_t trx_gen_workspace(int N, const int64_t* dims, const int64_t* ranks, bool 
 int trx_gen(int N, const int64_t* dims, const int64_t* ranks, uint64_t seed, double eta, void* X, int x_dtype,
             double* const* true_cores, double* const* init_cores, char* ws, size_t ws_bytes, hipStream_t s,
             std::string* err);
+
+// Asynchronous job body for the serving executor: nmixed sweeps in prec_mixed,
+// nfin in prec_fin, cores written back, fit, then the latched status word and
+// (||X||^2, fit residual^2) copied to the given pinned host memory, all
+// enqueued on the context's stream without waiting (FP8 still reads its scale
+// back).  A solve failure latches the status word; later updates then leave
+// the cores unchanged.
+int trx_run_async(tr_als_ctx* c, int nmixed, int prec_mixed, int nfin, int prec_fin, int refine, int* status_host,
+                  double* scal_host);
+const char* trx_status_text(int status_word);

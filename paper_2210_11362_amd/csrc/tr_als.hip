@@ -948,9 +948,13 @@ int trx_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ranks,
     for (int k = 0; k < N && rc == TR_OK; ++k) rc = qr_core(c, k);
     if (rc) { tr_als_destroy(c); return rc; }
   }
-  if (hipfail(launch_sumsq(X, x_dtype, numel, c->dpart, c->nred, c->dscal, s), "sumsq") ||
-      hipfail(hipMemcpyAsync(&c->xnorm2, c->dscal, 8, hipMemcpyDeviceToHost, s), "copy norm") ||
-      hipfail(hipStreamSynchronize(s), "sync")) {
+  if (hipfail(launch_sumsq(X, x_dtype, numel, c->dpart, c->nred, c->dscal, s), "sumsq")) {
+    tr_als_destroy(c);
+    return TR_EHIP;
+  }
+  // asynchronous creation leaves ||X||^2 on the device (dscal[0])
+  if (!o.no_sync && (hipfail(hipMemcpyAsync(&c->xnorm2, c->dscal, 8, hipMemcpyDeviceToHost, s), "copy norm") ||
+                     hipfail(hipStreamSynchronize(s), "sync"))) {
     tr_als_destroy(c);
     return TR_EHIP;
   }
@@ -1117,11 +1121,7 @@ static hipGraphExec_t sweep_graph(tr_als_ctx* c, int prec, int refine) {
   return ex;
 }
 
-int tr_als_sweep(tr_als_ctx* c, int nsweeps, int prec, int refine) {
-  if (!valid_ctx(c)) return TR_EINVAL;
-  if (nsweeps < 0 || prec < TR_F64 || prec > TR_FP8 || refine < 0 || refine > 4)
-    return fail(c, TR_EINVAL, "bad sweep arguments");
-  c->err.clear();
+static int enqueue_sweeps(tr_als_ctx* c, int nsweeps, int prec, int refine) {
   hipGraphExec_t ex = nsweeps > 0 ? sweep_graph(c, prec, refine) : nullptr;
   for (int sw = 0; sw < nsweeps; ++sw) {
     if (ex) {
@@ -1133,7 +1133,30 @@ int tr_als_sweep(tr_als_ctx* c, int nsweeps, int prec, int refine) {
       if (rc) return rc;
     }
   }
-  int rc = read_status(c);
+  return TR_OK;
+}
+
+static int enqueue_fit(tr_als_ctx* c) {
+  hipStream_t s = c->stream;
+  const Plan& p = c->plan[0];
+  int rc = build_table(c, p.f1c, p.Rmid, c->F1);
+  if (rc) return rc;
+  rc = build_table(c, p.f2c, p.Rmid, c->F2);
+  if (rc) return rc;
+  HIPCHK(c, launch_core_unfold(c->cores[0], p.Ra, p.I, p.Rb, c->G0u, s));
+  HIPCHK(c, launch_fit(c->X, c->xdt, p.I, p.K, c->G0u, c->F1, c->F2, p.d1, p.m1, p.d2, p.m2, p.Rb, p.Rmid, p.Ra,
+                       c->dpart, c->nred, c->dscal + 1, s));
+  return TR_OK;
+}
+
+int tr_als_sweep(tr_als_ctx* c, int nsweeps, int prec, int refine) {
+  if (!valid_ctx(c)) return TR_EINVAL;
+  if (nsweeps < 0 || prec < TR_F64 || prec > TR_FP8 || refine < 0 || refine > 4)
+    return fail(c, TR_EINVAL, "bad sweep arguments");
+  c->err.clear();
+  int rc = enqueue_sweeps(c, nsweeps, prec, refine);
+  if (rc) return rc;
+  rc = read_status(c);
   // cores written back in either case: on error they hold the last good update
   int rc2 = store_cores(c);
   if (rc2) return rc2;
@@ -1189,20 +1212,37 @@ int tr_als_xnorm2(const tr_als_ctx* c, double* out) {
 int tr_als_fit(tr_als_ctx* c, double* rel_err) {
   if (!valid_ctx(c) || !rel_err) return c ? fail(c, TR_EINVAL, "bad arguments") : TR_EINVAL;
   hipStream_t s = c->stream;
-  const Plan& p = c->plan[0];
-  int rc = build_table(c, p.f1c, p.Rmid, c->F1);
+  int rc = enqueue_fit(c);
   if (rc) return rc;
-  rc = build_table(c, p.f2c, p.Rmid, c->F2);
-  if (rc) return rc;
-  HIPCHK(c, launch_core_unfold(c->cores[0], p.Ra, p.I, p.Rb, c->G0u, s));
-  HIPCHK(c, launch_fit(c->X, c->xdt, p.I, p.K, c->G0u, c->F1, c->F2, p.d1, p.m1, p.d2, p.m2, p.Rb, p.Rmid, p.Ra,
-                       c->dpart, c->nred, c->dscal + 1, s));
   double ss = 0.0;
   HIPCHK(c, hipMemcpyAsync(&ss, c->dscal + 1, sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
   *rel_err = c->xnorm2 > 0 ? std::sqrt(std::max(0.0, ss)) / std::sqrt(c->xnorm2) : 0.0;
   return read_status(c);
 }
+
+}  // extern "C"
+
+int trx_run_async(tr_als_ctx* c, int nmixed, int prec_mixed, int nfin, int prec_fin, int refine, int* status_host,
+                  double* scal_host) {
+  if (!valid_ctx(c)) return TR_EINVAL;
+  int rc = enqueue_sweeps(c, nmixed, prec_mixed, refine);
+  if (rc == TR_OK) rc = enqueue_sweeps(c, nfin, prec_fin, refine);
+  if (rc == TR_OK) rc = store_cores(c);
+  if (rc == TR_OK) rc = enqueue_fit(c);
+  if (rc) return rc;
+  HIPCHK(c, hipMemcpyAsync(status_host, c->status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(scal_host, c->dscal, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  return TR_OK;
+}
+
+const char* trx_status_text(int st) {
+  if (st & ST_SINGULAR) return "coefficient matrix not positive definite (or zero pivot)";
+  if (st & ST_NONFINITE) return "non-finite value in M_n or in an updated core";
+  return "";
+}
+
+extern "C" {
 
 int tr_als_profile_enable(tr_als_ctx* c, int enable) {
   if (!valid_ctx(c)) return TR_EINVAL;

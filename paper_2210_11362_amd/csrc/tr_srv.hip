@@ -1,10 +1,11 @@
 // Serving runtime: a request loop that runs many TR-ALS jobs on one GPU with
-// continuous admission.  One scheduler thread admits arrived jobs (arrival
-// order, HBM-footprint admission into a device arena, bounded backfill of
-// small jobs); every slot is a worker thread with two streams that runs its
-// job from generation to fit, so admitted jobs overlap on the device.  Device
-// memory comes from one arena allocated at creation: no hipMalloc/hipFree (and
-// their device-wide synchronisation) while jobs run.
+// continuous admission.  One executor thread is the only caller of HIP: it
+// admits arrived jobs (arrival order, HBM-footprint admission into a device
+// arena, bounded backfill of small jobs), enqueues each admitted job's whole
+// work (generation, sweeps, fit, result copies) on its slot's streams without
+// waiting, and polls the slots' completion events, so admitted jobs overlap on
+// the device.  Device memory comes from one arena allocated at creation: no
+// hipMalloc/hipFree (and their device-wide synchronisation) while jobs run.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -91,13 +92,27 @@ struct Job {
   std::string err;
 };
 
+// A slot runs one job at a time: its streams, the completion event of the job
+// and pinned host memory for the job's results (status word, norms, cores).
 struct Slot {
-  std::thread th;
   hipStream_t s = nullptr, s2 = nullptr;
+  hipEvent_t done = nullptr;
   Job* job = nullptr;
+  tr_als_ctx* ctx = nullptr;
+  char* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  int rc = TR_OK;             // enqueue failure of the running job
+  std::string err;
 };
 
 inline size_t esize(int dt) { return dt == TR_F64 ? 8 : 4; }
+
+inline size_t core_elems(const tr_job_desc& d, int k) {
+  return (size_t)d.ranks[k] * d.dims[k] * d.ranks[(k + 1) % d.N];
+}
+
+constexpr size_t PIN_HEAD = 64;              // status word, ||X||^2, residual^2
+constexpr size_t PIN_DEFAULT = 8u << 20;     // per slot; grown on demand
 
 }  // namespace
 
@@ -105,9 +120,10 @@ struct tr_srv {
   int device = 0;
   Arena arena;
   std::vector<Slot> slots;
-  std::thread sched;
+  std::vector<char*> old_pinned;   // outgrown pinned buffers, freed at destroy
+  std::thread exec;
   std::mutex mu;
-  std::condition_variable cv_sched, cv_slot, cv_done;
+  std::condition_variable cv_exec, cv_done;
   std::vector<Job*> pending;  // ordered by (arrival, id)
   std::unordered_map<uint64_t, std::unique_ptr<Job>> jobs;
   uint64_t next_id = 1;
@@ -125,18 +141,15 @@ struct tr_srv {
 namespace {
 
 constexpr double HEAD_MAX_WAIT_S = 0.5;
+constexpr auto POLL = std::chrono::microseconds(50);
 
-// What a finished job hands back (committed to the Job under the lock).
-struct JobOut {
-  double rel_err = NAN;
-  std::vector<std::vector<double>> cores;
-  std::string err;
-};
-
-// One job on one slot: generate (or borrow) X and the initial cores, create a
-// context in the job's arena region, run the mixed and finishing sweeps, fit,
-// copy the final cores to the host.
-int run_job(tr_srv* srv, const Job* j, hipStream_t s, hipStream_t s2, JobOut* out) {
+// Enqueue a whole job on its slot: generate (or borrow) X and the initial
+// cores, create a context in the job's arena region, the mixed and finishing
+// sweeps, the fit, the copies of the results to pinned memory and the
+// completion event.  Nothing here waits on the device (FP8 contractions read
+// their scale back).
+int start_job(tr_srv* srv, Slot& sl) {
+  const Job* j = sl.job;
   const tr_job_desc& d = j->d;
   char* base = srv->arena.base + j->off;
   size_t off = 0;
@@ -147,142 +160,236 @@ int run_job(tr_srv* srv, const Job* j, hipStream_t s, hipStream_t s2, JobOut* ou
   };
   void* X = d.X ? const_cast<void*>(d.X) : (void*)carve(j->numel * esize(d.x_dtype));
   double* cores[TR_MAXN] = {nullptr};
-  for (int k = 0; k < d.N; ++k)
-    cores[k] = (double*)carve((size_t)d.ranks[k] * d.dims[k] * d.ranks[(k + 1) % d.N] * 8);
+  size_t core_bytes = 0;
+  for (int k = 0; k < d.N; ++k) {
+    cores[k] = (double*)carve(core_elems(d, k) * 8);
+    core_bytes += core_elems(d, k) * 8;
+  }
+  if (PIN_HEAD + core_bytes > sl.pinned_bytes) {
+    void* p = nullptr;
+    const size_t want = std::max(PIN_HEAD + core_bytes, 2 * sl.pinned_bytes);
+    if (hipHostMalloc(&p, want, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      sl.err = "pinned host allocation failed";
+      return TR_ENOMEM;
+    }
+    if (sl.pinned) srv->old_pinned.push_back(sl.pinned);
+    sl.pinned = (char*)p;
+    sl.pinned_bytes = want;
+  }
   // the generator's workspace and, after it in stream order, the context's
   char* shared = base + off;
+  hipStream_t s = sl.s;
   int rc = TR_OK;
   if (!d.X) {
     rc = trx_gen(d.N, d.dims, d.ranks, d.seed, d.eta, X, d.x_dtype, nullptr, d.init_cores ? nullptr : cores,
-                 shared, j->bytes_gen, s, &out->err);
+                 shared, j->bytes_gen, s, &sl.err);
     if (rc) return rc;
   } else if (!d.init_cores) {
     for (int k = 0; k < d.N; ++k)
-      if (launch_philox_normal(cores[k], (int64_t)d.ranks[k] * d.dims[k] * d.ranks[(k + 1) % d.N], d.seed,
-                               GEN_SID_INIT + k, s) != hipSuccess) {
-        out->err = "initial-core generation failed";
+      if (launch_philox_normal(cores[k], (int64_t)core_elems(d, k), d.seed, GEN_SID_INIT + k, s) != hipSuccess) {
+        sl.err = "initial-core generation failed";
         return TR_EHIP;
       }
   }
   if (d.init_cores)
     for (int k = 0; k < d.N; ++k)
-      if (hipMemcpyAsync(cores[k], j->init_ptrs[k], (size_t)d.ranks[k] * d.dims[k] * d.ranks[(k + 1) % d.N] * 8,
-                         hipMemcpyDeviceToDevice, s) != hipSuccess) {
-        out->err = "copy of the initial cores failed";
+      if (hipMemcpyAsync(cores[k], j->init_ptrs[k], core_elems(d, k) * 8, hipMemcpyDeviceToDevice, s) !=
+          hipSuccess) {
+        sl.err = "copy of the initial cores failed";
         return TR_EHIP;
       }
   TrxOpts o;
   o.region = shared;
   o.region_bytes = j->bytes_ctx;
-  o.stream2 = s2;
+  o.stream2 = sl.s2;
   o.shadow_mask = j->shadow_mask;
-  tr_als_ctx* ctx = nullptr;
-  rc = trx_init(&ctx, d.N, d.dims, d.ranks, X, d.x_dtype, cores, d.variant, s, o);
+  o.no_sync = true;
+  rc = trx_init(&sl.ctx, d.N, d.dims, d.ranks, X, d.x_dtype, cores, d.variant, s, o);
   if (rc) {
-    out->err = "context creation failed: " + std::string(tr_als_strerror(rc));
+    sl.err = "context creation failed: " + std::string(tr_als_strerror(rc));
     return rc;
   }
-  if (d.nsweeps_mixed > 0) rc = tr_als_sweep(ctx, d.nsweeps_mixed, d.prec_mixed, d.refine);
-  if (rc == TR_OK && d.nsweeps_fin > 0) rc = tr_als_sweep(ctx, d.nsweeps_fin, d.prec_fin, d.refine);
-  double fit = NAN;
-  if (rc == TR_OK) rc = tr_als_fit(ctx, &fit);
-  if (rc) out->err = tr_als_last_error(ctx);
-  out->rel_err = fit;
-  // final cores (the last good ones on a solve failure) to the host
-  out->cores.resize(d.N);
+  rc = trx_run_async(sl.ctx, d.nsweeps_mixed, d.prec_mixed, d.nsweeps_fin, d.prec_fin, d.refine, (int*)sl.pinned,
+                     (double*)(sl.pinned + 16));
+  if (rc) {
+    sl.err = tr_als_last_error(sl.ctx);
+    return rc;
+  }
+  size_t po = PIN_HEAD;
   for (int k = 0; k < d.N; ++k) {
-    const size_t n = (size_t)d.ranks[k] * d.dims[k] * d.ranks[(k + 1) % d.N];
-    out->cores[k].resize(n);
-    if (hipMemcpyAsync(out->cores[k].data(), cores[k], n * 8, hipMemcpyDeviceToHost, s) != hipSuccess && !rc) {
-      out->err = "copy of the final cores failed";
-      rc = TR_EHIP;
+    if (hipMemcpyAsync(sl.pinned + po, cores[k], core_elems(d, k) * 8, hipMemcpyDeviceToHost, s) != hipSuccess) {
+      sl.err = "copy of the final cores failed";
+      return TR_EHIP;
     }
+    po += core_elems(d, k) * 8;
   }
-  if (hipStreamSynchronize(s) != hipSuccess && !rc) {
-    out->err = "stream synchronisation failed";
-    rc = TR_EHIP;
+  if (hipEventRecord(sl.done, s) != hipSuccess) {
+    sl.err = "event record failed";
+    return TR_EHIP;
   }
-  tr_als_destroy(ctx);
-  return rc;
+  return TR_OK;
 }
 
-void slot_main(tr_srv* srv, int k) {
-  (void)hipSetDevice(srv->device);
-  Slot& sl = srv->slots[k];
-  std::unique_lock<std::mutex> lk(srv->mu);
-  for (;;) {
-    srv->cv_slot.wait(lk, [&] { return srv->stop || sl.job != nullptr; });
-    if (!sl.job) return;
-    Job* j = sl.job;
-    lk.unlock();
-    JobOut res;
-    const int rc = run_job(srv, j, sl.s, sl.s2, &res);
-    // nothing of the job may still run when its region is handed out again
-    (void)hipStreamSynchronize(sl.s2);
-    (void)hipStreamSynchronize(sl.s);
-    lk.lock();
-    srv->arena.release(j->off, j->footprint);
-    j->rel_err = res.rel_err;
-    j->cores = std::move(res.cores);
-    j->err = std::move(res.err);
-    j->status = rc;
-    j->state = rc == TR_OK ? TR_JOB_DONE : TR_JOB_FAILED;
-    j->t_done = srv->now();
-    if (rc == TR_OK) srv->n_done++;
-    else srv->n_failed++;
-    srv->running--;
-    sl.job = nullptr;
-    srv->cv_sched.notify_one();
-    srv->cv_done.notify_all();
+// Results of a finished (or failed-to-enqueue) job, read from the slot.
+struct JobOut {
+  int rc = TR_OK;
+  double rel_err = NAN;
+  std::vector<std::vector<double>> cores;
+  std::string err;
+};
+
+JobOut finish_job(Slot& sl) {
+  JobOut r;
+  const tr_job_desc& d = sl.job->d;
+  r.rc = sl.rc;
+  r.err = sl.err;
+  // nothing of the job may still run when its region is handed out again
+  if (hipStreamSynchronize(sl.s2) != hipSuccess || hipStreamSynchronize(sl.s) != hipSuccess) {
+    (void)hipGetLastError();
+    if (r.rc == TR_OK) { r.rc = TR_EHIP; r.err = "stream synchronisation failed"; }
   }
+  if (r.rc == TR_OK) {
+    const int st = *(const int*)sl.pinned;
+    const double* sc = (const double*)(sl.pinned + 16);
+    if (st) {
+      r.rc = (st & ST_SINGULAR) ? TR_ESINGULAR : TR_ENONFINITE;
+      r.err = trx_status_text(st);
+    } else {
+      r.rel_err = sc[0] > 0 ? std::sqrt(std::max(0.0, sc[1])) / std::sqrt(sc[0]) : 0.0;
+    }
+    // final cores (the last good ones after a solve failure)
+    r.cores.resize(d.N);
+    size_t po = PIN_HEAD;
+    for (int k = 0; k < d.N; ++k) {
+      const double* src = (const double*)(sl.pinned + po);
+      r.cores[k].assign(src, src + core_elems(d, k));
+      po += core_elems(d, k) * 8;
+    }
+  }
+  if (sl.ctx) tr_als_destroy(sl.ctx);
+  sl.ctx = nullptr;
+  sl.rc = TR_OK;
+  sl.err.clear();
+  return r;
 }
 
 // Admission: arrived jobs in arrival order, each needing a free slot and one
 // contiguous arena region of its footprint.  When the oldest arrived job does
 // not fit, later jobs with footprint <= arena/64 may go first, for at most
-// HEAD_MAX_WAIT_S seconds of the head's waiting.
-void sched_main(tr_srv* srv) {
-  std::unique_lock<std::mutex> lk(srv->mu);
-  while (!srv->stop) {
-    const double now = srv->now();
-    double next_arrival = -1;
-    bool head = true, backfill_ok = true, assigned = false;
-    for (size_t q = 0; q < srv->pending.size();) {
-      Job* j = srv->pending[q];
-      if (j->t_arrival > now) { next_arrival = j->t_arrival; break; }
-      int free_slot = -1;
-      for (size_t k = 0; k < srv->slots.size(); ++k)
-        if (!srv->slots[k].job) { free_slot = (int)k; break; }
-      if (free_slot < 0) break;
-      const bool small = j->footprint <= srv->arena.cap / 64;
-      size_t off = 0;
-      if ((!head && !(backfill_ok && small)) || !srv->arena.alloc(j->footprint, &off)) {
-        if (head) {
-          if (srv->head_block_id != j->id) { srv->head_block_id = j->id; srv->head_block_since = now; }
-          backfill_ok = now - srv->head_block_since < HEAD_MAX_WAIT_S;
-        }
-        head = false;
-        ++q;
-        continue;
+// HEAD_MAX_WAIT_S seconds of the head's waiting.  Called with the lock held;
+// returns the slots that received a job and the next future arrival (or -1).
+void admit(tr_srv* srv, std::vector<int>* started, double* next_arrival) {
+  const double now = srv->now();
+  *next_arrival = -1;
+  bool head = true, backfill_ok = true;
+  for (size_t q = 0; q < srv->pending.size();) {
+    Job* j = srv->pending[q];
+    if (j->t_arrival > now) { *next_arrival = j->t_arrival; break; }
+    int free_slot = -1;
+    for (size_t k = 0; k < srv->slots.size(); ++k)
+      if (!srv->slots[k].job) { free_slot = (int)k; break; }
+    if (free_slot < 0) break;
+    const bool small = j->footprint <= srv->arena.cap / 64;
+    size_t off = 0;
+    if ((!head && !(backfill_ok && small)) || !srv->arena.alloc(j->footprint, &off)) {
+      if (head) {
+        if (srv->head_block_id != j->id) { srv->head_block_id = j->id; srv->head_block_since = now; }
+        backfill_ok = now - srv->head_block_since < HEAD_MAX_WAIT_S;
       }
-      if (head) srv->head_block_id = 0;
-      j->off = off;
-      j->slot = free_slot;
-      j->state = TR_JOB_RUNNING;
-      j->t_admit = now;
-      srv->slots[free_slot].job = j;
-      srv->running++;
-      srv->max_running = std::max(srv->max_running, srv->running);
-      srv->pending.erase(srv->pending.begin() + q);
-      assigned = true;
+      head = false;
+      ++q;
+      continue;
     }
-    if (assigned) srv->cv_slot.notify_all();
-    if (next_arrival >= 0)
-      srv->cv_sched.wait_until(lk, srv->t0 + std::chrono::duration_cast<Clock::duration>(
-                                                  std::chrono::duration<double>(next_arrival)));
-    else if (!srv->stop)
-      srv->cv_sched.wait(lk);
+    if (head) srv->head_block_id = 0;
+    j->off = off;
+    j->slot = free_slot;
+    j->state = TR_JOB_RUNNING;
+    j->t_admit = now;
+    srv->slots[free_slot].job = j;
+    srv->running++;
+    srv->max_running = std::max(srv->max_running, srv->running);
+    srv->pending.erase(srv->pending.begin() + q);
+    started->push_back(free_slot);
   }
+}
+
+// The executor: the only thread that calls HIP.  It admits jobs, enqueues each
+// admitted job's whole work on its slot, and polls the slots' completion
+// events; queued jobs are dropped and running ones finished when stopping.
+void exec_main(tr_srv* srv) {
+  (void)hipSetDevice(srv->device);
+  std::unique_lock<std::mutex> lk(srv->mu);
+  for (;;) {
+    if (srv->stop && srv->running == 0) break;
+    std::vector<int> started;
+    double next_arrival = -1;
+    if (!srv->stop) admit(srv, &started, &next_arrival);
+    lk.unlock();
+    for (int k : started) {
+      Slot& sl = srv->slots[k];
+      sl.rc = start_job(srv, sl);
+      if (sl.rc != TR_OK) (void)hipGetLastError();
+    }
+    // completions
+    std::vector<std::pair<int, JobOut>> finished;
+    for (size_t k = 0; k < srv->slots.size(); ++k) {
+      Slot& sl = srv->slots[k];
+      if (!sl.job) continue;
+      bool ready = sl.rc != TR_OK;
+      if (!ready) {
+        const hipError_t q = hipEventQuery(sl.done);
+        if (q == hipSuccess) ready = true;
+        else if (q != hipErrorNotReady) {
+          (void)hipGetLastError();
+          sl.rc = TR_EHIP;
+          sl.err = "completion event failed";
+          ready = true;
+        }
+      }
+      if (ready) finished.emplace_back((int)k, finish_job(sl));
+    }
+    lk.lock();
+    for (auto& f : finished) {
+      Slot& sl = srv->slots[f.first];
+      Job* j = sl.job;
+      JobOut& r = f.second;
+      srv->arena.release(j->off, j->footprint);
+      j->rel_err = r.rel_err;
+      j->cores = std::move(r.cores);
+      j->err = std::move(r.err);
+      j->status = r.rc;
+      j->state = r.rc == TR_OK ? TR_JOB_DONE : TR_JOB_FAILED;
+      j->t_done = srv->now();
+      if (r.rc == TR_OK) srv->n_done++;
+      else srv->n_failed++;
+      srv->running--;
+      sl.job = nullptr;
+    }
+    if (!finished.empty()) srv->cv_done.notify_all();
+    if (!started.empty() || !finished.empty()) continue;
+    if (srv->running > 0)
+      srv->cv_exec.wait_for(lk, POLL);
+    else if (next_arrival >= 0)
+      srv->cv_exec.wait_until(lk, srv->t0 + std::chrono::duration_cast<Clock::duration>(
+                                               std::chrono::duration<double>(next_arrival)));
+    else if (!srv->stop)
+      srv->cv_exec.wait(lk);
+  }
+}
+
+void release_slots(tr_srv* srv) {
+  for (auto& sl : srv->slots) {
+    if (sl.s) (void)hipStreamSynchronize(sl.s);
+    if (sl.s2) (void)hipStreamSynchronize(sl.s2);
+    if (sl.s) (void)hipStreamDestroy(sl.s);
+    if (sl.s2) (void)hipStreamDestroy(sl.s2);
+    if (sl.done) (void)hipEventDestroy(sl.done);
+    if (sl.pinned) (void)hipHostFree(sl.pinned);
+    sl = Slot();
+  }
+  for (char* p : srv->old_pinned) (void)hipHostFree(p);
+  srv->old_pinned.clear();
 }
 
 int validate(const tr_job_desc& d) {
@@ -327,20 +434,31 @@ int tr_srv_create(tr_srv** out, size_t hbm_budget_bytes, int max_slots, int flag
   srv->arena.reset(bytes);
   srv->flags = flags;
   srv->slots.resize(max_slots);
-  for (auto& sl : srv->slots)
+  int rc = TR_OK;
+  for (auto& sl : srv->slots) {
+    void* pin = nullptr;
     if (hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&sl.s2, hipStreamNonBlocking) != hipSuccess) {
-      for (auto& q : srv->slots) {
-        if (q.s) (void)hipStreamDestroy(q.s);
-        if (q.s2) (void)hipStreamDestroy(q.s2);
-      }
-      (void)hipFree(base);
-      return TR_EHIP;
+        hipStreamCreateWithFlags(&sl.s2, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
+      rc = TR_EHIP;
+      break;
     }
+    if (hipHostMalloc(&pin, PIN_DEFAULT, 0) != hipSuccess) {
+      rc = TR_ENOMEM;
+      break;
+    }
+    sl.pinned = (char*)pin;
+    sl.pinned_bytes = PIN_DEFAULT;
+  }
+  if (rc) {
+    (void)hipGetLastError();
+    release_slots(srv.get());
+    (void)hipFree(base);
+    return rc;
+  }
   srv->t0 = Clock::now();
   tr_srv* p = srv.release();
-  for (int k = 0; k < max_slots; ++k) p->slots[k].th = std::thread(slot_main, p, k);
-  p->sched = std::thread(sched_main, p);
+  p->exec = std::thread(exec_main, p);
   *out = p;
   return TR_OK;
 }
@@ -382,7 +500,7 @@ int tr_srv_submit(tr_srv* srv, const tr_job_desc* desc, uint64_t* job_id) {
   });
   srv->pending.insert(pos, jp);
   *job_id = jp->id;
-  srv->cv_sched.notify_one();
+  srv->cv_exec.notify_one();
   return TR_OK;
 }
 
@@ -475,17 +593,10 @@ int tr_srv_destroy(tr_srv* srv) {
     }
     srv->pending.clear();
   }
-  srv->cv_sched.notify_all();
-  srv->cv_slot.notify_all();
-  if (srv->sched.joinable()) srv->sched.join();
-  for (auto& sl : srv->slots)
-    if (sl.th.joinable()) sl.th.join();
-  for (auto& sl : srv->slots) {
-    if (sl.s) (void)hipStreamSynchronize(sl.s);
-    if (sl.s2) (void)hipStreamSynchronize(sl.s2);
-    if (sl.s) (void)hipStreamDestroy(sl.s);
-    if (sl.s2) (void)hipStreamDestroy(sl.s2);
-  }
+  srv->cv_exec.notify_all();
+  srv->cv_done.notify_all();
+  if (srv->exec.joinable()) srv->exec.join();
+  release_slots(srv);
   if (srv->arena.base) (void)hipFree(srv->arena.base);
   delete srv;
   return TR_OK;
