@@ -36,6 +36,10 @@ def main():
     ap.add_argument("--prec", default="bf16", choices=["f32", "bf16", "fp8", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-schedules", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-jobs", type=int, default=400)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path (the X stream of one GPU "
@@ -43,6 +47,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_probe:
+        n = 1 << 28                      # 2^28 float32 = 1 GiB read + 1 GiB written per copy
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "copies": 3}))
+        return
     import workloads as W
     from paper_2210_11362_amd import TRContext
 
@@ -82,6 +95,8 @@ def main():
     p99 = per[min(len(per) - 1, int(round(0.99 * (len(per) - 1))))]
 
     # ---- roofline of the X-stream kernel (HIP events on the library stream) --
+    regimes = sorted({ctx.regime(n) for n in range(1, N + 1)})
+    kname = {1: "xgemm_kernel (two-stage X contraction, stage 1)", 2: "xstream_kernel (fused X contraction)"}
     ctx.profile_enable(True)
     ctx.sweep(3, args.prec, refine=1)
     kms, nl, bpl = ctx.profile_read()
@@ -100,7 +115,7 @@ def main():
     else:
         roof = {"bound": "mfma", "achieved": round(achieved_tf, 2), "peak": MFMA_PEAK_TFLOPS["f32"],
                 "unit": "TFLOP/s", "frac": round(achieved_tf / MFMA_PEAK_TFLOPS["f32"], 4), "traffic": None}
-    roof.update({"kernel": "xstream_kernel", "avg_kernel_us": round(avg_kernel_s * 1e6, 2),
+    roof.update({"kernel": " + ".join(kname[r] for r in regimes), "avg_kernel_us": round(avg_kernel_s * 1e6, 2),
                  "launches": nl, "algo_bytes_per_launch": algo_bytes, "flops_per_launch": flops_launch,
                  "achieved_tflops": round(achieved_tf, 2)})
     ctx.close()
@@ -130,6 +145,10 @@ def main():
         sched["fit_delta"] = abs(sched["mixed"]["fit"] - sched["plain"]["fit"])
         sched["speedup_mixed_vs_plain"] = round(sched["plain"]["seconds"] / sched["mixed"]["seconds"], 3)
         extra["schedules_20_sweeps"] = sched
+
+    # ---- serving: a Poisson stream of small jobs through the request loop ---
+    if not args.no_serving and args.serving_jobs > 0:
+        extra["serving"] = serving_leg(args.serving_jobs)
 
     # ---- CPU oracle on a bounded sample ------------------------------------
     cpu = None
@@ -171,6 +190,30 @@ def main():
     }
     out.update(extra)
     print(json.dumps(out))
+
+
+def serving_leg(njobs: int):
+    """Latency and throughput of the request loop on a Poisson stream (200 jobs/s)
+    of planted-TR jobs of order 3-4, mode sizes 16-48, ranks 2-8 (8 BF16 + 2 FP32
+    sweeps each), generated on the device; 8 slots, 16 GiB arena."""
+    import numpy as np
+    import workloads as W
+    from paper_2210_11362_amd import TRServer
+    jobs = W.serving_stream(njobs, orders=(3, 4), dim_range=(16, 48), rank_range=(2, 8))
+    srv = TRServer(16 << 30, 8)
+    ids = [srv.submit(j["dims"], j["ranks"], seed=j["seed"], eta=0.01, prec_mixed="bf16", nsweeps_mixed=8,
+                      prec_fin="f32", nsweeps_fin=2, t_arrival=0.05 + j["t_arrive"]) for j in jobs]
+    srv.drain()
+    infos = [srv.poll(i) for i in ids]
+    st = srv.stats()
+    srv.close()
+    lat = np.array([i["t_done"] - i["t_arrival"] for i in infos])
+    span = max(i["t_done"] for i in infos) - min(i["t_arrival"] for i in infos)
+    return {"stream": f"{njobs} jobs, Poisson 200/s, order 3-4, dims 16-48, ranks 2-8, 8xbf16+2xf32 sweeps",
+            "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
+            "jobs_per_s": round(njobs / span, 2), "failed": int(sum(i["state"] != 2 for i in infos)),
+            "slots": st["slots"], "max_running": st["max_running"], "peak_hbm_bytes": st["peak_in_use"]}
 
 
 if __name__ == "__main__":

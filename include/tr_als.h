@@ -132,6 +132,13 @@ int tr_als_gram(tr_als_ctx* ctx, int k /*1..N*/, double* E_out);
 int tr_als_update_mode(tr_als_ctx* ctx, int n /*1..N*/, int prec, int refine_steps);
 int tr_als_store_cores(tr_als_ctx* ctx);
 
+/* Which X-contraction kernel a sweep uses for mode n: 1 = two-stage (a
+ * tall-skinny MFMA GEMM of X against the partial-subchain table of one group
+ * of memory-contiguous modes, then absorption of the remaining modes), 2 =
+ * fused single pass (subchain rows formed in LDS).  Returns 1 or 2, or a
+ * negative TR_E* code. */
+int tr_als_mode_regime(const tr_als_ctx* ctx, int n /*1..N*/);
+
 /* ||X||_F^2 computed at init (FP64).  host out. */
 int tr_als_xnorm2(const tr_als_ctx* ctx, double* out);
 

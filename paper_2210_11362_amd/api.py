@@ -88,6 +88,13 @@ class TRContext:
         C.check(C.lib().tr_als_gram(self._h, int(k), ctypes.c_void_p(out.data_ptr())), self._h, "tr_als_gram")
         return out.t()
 
+    def regime(self, n: int) -> int:
+        """X-contraction kernel of mode n: 1 two-stage GEMM, 2 fused single pass."""
+        r = C.lib().tr_als_mode_regime(self._h, int(n))
+        if r < 0:
+            C.check(r, self._h, "tr_als_mode_regime")
+        return r
+
     def xnorm2(self) -> float:
         v = ctypes.c_double()
         C.check(C.lib().tr_als_xnorm2(self._h, ctypes.byref(v)), self._h, "tr_als_xnorm2")

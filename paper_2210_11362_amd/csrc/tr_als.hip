@@ -375,7 +375,14 @@ XgArgs xg_config(const tr_als_ctx* c, int m, int prec, const void* X, int esize)
   g.X = X;
   g.M = p.gM; g.K = p.gK; g.C = p.gC; g.nn = p.nn;
   g.vec_ok = (!p.nn && ((p.gK * esize) % 16 == 0) && (((uintptr_t)X) % 16 == 0)) ? 1 : 0;
+  // Row tile and split-K target (workgroups per launch); measured best on the
+  // 100^4 rank-10 workload: 128 rows, ~640 workgroups for BF16 (HBM-bound),
+  // ~1024 for FP32 (MFMA-bound).  TR_ALS_XG_MT / TR_ALS_XG_WGS override.
   g.MT = p.gM > 8192 ? 128 : 64;
+  static const int env_mt = getenv("TR_ALS_XG_MT") ? atoi(getenv("TR_ALS_XG_MT")) : 0;
+  static const int env_wgs = getenv("TR_ALS_XG_WGS") ? atoi(getenv("TR_ALS_XG_WGS")) : 0;
+  if (env_mt == 64 || env_mt == 128) g.MT = env_mt;
+  const int64_t target_wgs = env_wgs > 0 ? env_wgs : ((prec == TR_F32 || prec == TR_F64) ? 1024 : 640);
   g.n_mt = (int)((p.gM + g.MT - 1) / g.MT);
   if (p.gC <= 128) { g.NT = (p.gC + 15) / 16 * 16; g.n_nt = 1; }
   else { g.NT = 128; g.n_nt = (p.gC + 127) / 128; }
@@ -383,7 +390,7 @@ XgArgs xg_config(const tr_als_ctx* c, int m, int prec, const void* X, int esize)
   g.ldb = (p.gK + kt - 1) / kt * kt;
   const int64_t ktiles = g.ldb / kt;
   const int64_t tiles = (int64_t)g.n_mt * g.n_nt;
-  int64_t ns = std::max<int64_t>(1, (640 + tiles - 1) / tiles);
+  int64_t ns = std::max<int64_t>(1, (target_wgs + tiles - 1) / tiles);
   ns = std::min<int64_t>(ns, std::max<int64_t>(1, ktiles / 2));
   const int64_t tps = (ktiles + ns - 1) / ns;
   g.k_per_split = tps * kt;
@@ -1201,6 +1208,11 @@ int tr_als_gram(tr_als_ctx* c, int k, double* Eout) {
   const size_t n = (size_t)c->R[m] * c->R[m + 1];
   HIPCHK(c, hipMemcpyAsync(Eout, c->gram[m], n * n * 8, hipMemcpyDeviceToDevice, c->stream));
   return read_status(c);
+}
+
+int tr_als_mode_regime(const tr_als_ctx* c, int n) {
+  if (!c || c->N < 2 || n < 1 || n > c->N) return TR_EINVAL;
+  return c->plan[n - 1].regime;
 }
 
 int tr_als_xnorm2(const tr_als_ctx* c, double* out) {

@@ -127,6 +127,7 @@ struct tr_srv {
   std::vector<Job*> pending;  // ordered by (arrival, id)
   std::unordered_map<uint64_t, std::unique_ptr<Job>> jobs;
   uint64_t next_id = 1;
+  uint64_t gen = 0;           // bumped by every submit and by stop, under the lock
   bool stop = false;
   int flags = 0;
   int running = 0, max_running = 0;
@@ -142,6 +143,7 @@ namespace {
 
 constexpr double HEAD_MAX_WAIT_S = 0.5;
 constexpr auto POLL = std::chrono::microseconds(50);
+constexpr auto IDLE_MAX = std::chrono::milliseconds(10);
 
 // Enqueue a whole job on its slot: generate (or borrow) X and the initial
 // cores, create a context in the job's arena region, the mixed and finishing
@@ -324,6 +326,7 @@ void exec_main(tr_srv* srv) {
     if (srv->stop && srv->running == 0) break;
     std::vector<int> started;
     double next_arrival = -1;
+    const uint64_t seen = srv->gen;
     if (!srv->stop) admit(srv, &started, &next_arrival);
     lk.unlock();
     for (int k : started) {
@@ -368,13 +371,19 @@ void exec_main(tr_srv* srv) {
     }
     if (!finished.empty()) srv->cv_done.notify_all();
     if (!started.empty() || !finished.empty()) continue;
-    if (srv->running > 0)
+    // A submit (or stop) while the lock was released notified nobody: its job
+    // is not in next_arrival, so admit again instead of waiting.
+    if (srv->gen != seen) continue;
+    if (srv->running > 0) {
       srv->cv_exec.wait_for(lk, POLL);
-    else if (next_arrival >= 0)
-      srv->cv_exec.wait_until(lk, srv->t0 + std::chrono::duration_cast<Clock::duration>(
-                                               std::chrono::duration<double>(next_arrival)));
-    else if (!srv->stop)
-      srv->cv_exec.wait(lk);
+    } else {
+      // idle: until the next arrival or a submit, and never longer than IDLE_MAX
+      const auto until = std::min(Clock::now() + IDLE_MAX,
+                                  next_arrival >= 0 ? srv->t0 + std::chrono::duration_cast<Clock::duration>(
+                                                                    std::chrono::duration<double>(next_arrival))
+                                                    : Clock::time_point::max());
+      srv->cv_exec.wait_until(lk, until);
+    }
   }
 }
 
@@ -495,6 +504,7 @@ int tr_srv_submit(tr_srv* srv, const tr_job_desc* desc, uint64_t* job_id) {
   j->id = srv->next_id++;
   Job* jp = j.get();
   srv->jobs[jp->id] = std::move(j);
+  srv->gen++;
   auto pos = std::upper_bound(srv->pending.begin(), srv->pending.end(), jp, [](const Job* a, const Job* b) {
     return a->t_arrival < b->t_arrival || (a->t_arrival == b->t_arrival && a->id < b->id);
   });
@@ -586,6 +596,7 @@ int tr_srv_destroy(tr_srv* srv) {
   {
     std::lock_guard<std::mutex> lk(srv->mu);
     srv->stop = true;
+    srv->gen++;
     for (Job* j : srv->pending) {
       j->state = TR_JOB_FAILED;
       j->status = TR_EINVAL;

@@ -1,0 +1,152 @@
+"""Parity on the recipes of the ill-conditioned order-5 workload (cores with
+condition number 1e4, non-uniform ranks 6,8,10,8,6) and of the smooth
+order-3 field (separable sinusoids, TR ranks 20: R_n R_{n+1} = 400).
+
+Reduced sizes run whole trajectories against the oracle; the full sizes
+(40^5 and 512x512x256, FP32 storage) check one mode's M_n, the Gram ring and
+the first update against the oracle at the launch configuration a sweep uses.
+Ill-conditioning amplifies rounding in the cores themselves, so these
+workloads are gated on the fit (FP32 path: 1e-5 absolute after FP32 sweeps;
+BF16/FP8 mixed schedules: 1e-3 after FP32 finishing sweeps); core deviations
+are printed.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from tests.gpu_util import cores_from_dev, cores_to_dev, rel, say, to_dev_flat
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(X, cores, dims, ranks, variant="ne"):
+    from paper_2210_11362_amd import TRContext
+    dev = cores_to_dev(cores)
+    return TRContext(to_dev_flat(X), dims, ranks, dev, variant=variant), dev
+
+
+@pytest.mark.parametrize("variant", ["ne", "qr"])
+def test_conditioned_order5_reduced(variant):
+    w = W.make_workload(3, dims=(12, 12, 12, 12, 12))
+    say(f"[cond order-5 reduced, {variant}] dims={w.dims} ranks={w.ranks}")
+    Xd = w.X.astype(np.float64)
+    ctx, dev = _ctx(w.X, w.init_cores, w.dims, w.ranks, variant)
+    ref = [np.array(c) for c in w.init_cores]
+    for s in range(3):
+        ref, _ = O.tr_als(Xd, ref, 1)
+        ctx.sweep(1, "f32", refine=1)
+        got = cores_from_dev(dev, w.dims, w.ranks)
+        say(f"   sweep {s + 1}: max core rel err {max(rel(a, b) for a, b in zip(got, ref)):.2e}")
+    f_gpu, f_ref = ctx.fit(), O.rel_error(Xd, ref)
+    say(f"   fit gpu {f_gpu:.8e} oracle {f_ref:.8e}")
+    assert abs(f_gpu - f_ref) <= 1e-5
+    ctx.close()
+
+
+@pytest.mark.parametrize("variant,prec", [("ne", "bf16"), ("qr", "bf16"), ("qr", "fp8")])
+def test_conditioned_order5_mixed_schedule(variant, prec):
+    """FP8 on the conditioned cores runs the QR variant: with normal equations
+    the subchain table spans far more than E4M3's range under one scale, and the
+    coefficient matrix loses definiteness (reported as TR_ESINGULAR, see
+    test_conditioned_order5_fp8_normal_equation_breakdown_is_reported)."""
+    w = W.make_workload(3, dims=(10, 10, 10, 10, 10))
+    say(f"[cond order-5 mixed {variant} {prec}] dims={w.dims}")
+    Xd = w.X.astype(np.float64)
+    ctx, _ = _ctx(w.X, w.init_cores, w.dims, w.ranks, variant)
+    ctx.sweep(6, prec, refine=1)
+    ctx.sweep(2, "f32", refine=1)
+    ref, _ = O.tr_als(Xd, w.init_cores, 8)
+    f_gpu, f_ref = ctx.fit(), O.rel_error(Xd, ref)
+    say(f"   fit gpu {f_gpu:.6e} oracle {f_ref:.6e}")
+    assert abs(f_gpu - f_ref) <= 1e-3
+    ctx.close()
+
+
+def test_conditioned_order5_fp8_normal_equation_breakdown_is_reported():
+    """No silent failure: a breakdown of the FP8 normal-equation path on the
+    conditioned cores either does not happen or is reported as TR_ESINGULAR with
+    the last good cores kept (finite); the context stays usable, and a further
+    FP32 sweep from those cores either succeeds or reports the same breakdown
+    (no regularisation is applied behind the caller's back)."""
+    from paper_2210_11362_amd import TRError
+    w = W.make_workload(3, dims=(10, 10, 10, 10, 10))
+    ctx, dev = _ctx(w.X, w.init_cores, w.dims, w.ranks)
+    try:
+        ctx.sweep(6, "fp8", refine=1)
+        broke = False
+    except TRError as e:
+        assert e.code == -4
+        broke = True
+    got = cores_from_dev(dev, w.dims, w.ranks)
+    assert all(np.all(np.isfinite(c)) for c in got)
+    try:
+        ctx.sweep(1, "f32", refine=1)
+        again = False
+    except TRError as e:
+        assert e.code == -4
+        again = True
+    f = ctx.fit()
+    say(f"   fp8 NE breakdown: {broke}; FP32 sweep breaks down again: {again}; fit {f:.4e}")
+    assert np.isfinite(f)
+    ctx.close()
+
+
+def test_sinusoid_field_rank20_reduced():
+    """R_n R_{n+1} = 400: fused X stream with column tiles, Cholesky of a
+    400 x 400 coefficient matrix outside LDS."""
+    w = W.make_workload(4, dims=(48, 40, 32))
+    say(f"[sinusoid reduced] dims={w.dims} ranks={w.ranks}")
+    Xd = w.X.astype(np.float64)
+    ctx, dev = _ctx(w.X, w.init_cores, w.dims, w.ranks)
+    ref = [np.array(c) for c in w.init_cores]
+    for s in range(2):
+        ref, _ = O.tr_als(Xd, ref, 1)
+        ctx.sweep(1, "f32", refine=2)
+        got = cores_from_dev(dev, w.dims, w.ranks)
+        say(f"   sweep {s + 1}: max core rel err {max(rel(a, b) for a, b in zip(got, ref)):.2e}")
+    f_gpu, f_ref = ctx.fit(), O.rel_error(Xd, ref)
+    say(f"   fit gpu {f_gpu:.8e} oracle {f_ref:.8e}")
+    assert abs(f_gpu - f_ref) <= 1e-5
+    ctx.close()
+
+
+def test_sinusoid_field_rank20_mixed_schedule():
+    w = W.make_workload(4, dims=(40, 36, 30))
+    say(f"[sinusoid mixed bf16] dims={w.dims}")
+    Xd = w.X.astype(np.float64)
+    ctx, _ = _ctx(w.X, w.init_cores, w.dims, w.ranks)
+    ctx.sweep(3, "bf16", refine=2)
+    ctx.sweep(2, "f32", refine=2)
+    ref, _ = O.tr_als(Xd, w.init_cores, 5)
+    f_gpu, f_ref = ctx.fit(), O.rel_error(Xd, ref)
+    say(f"   fit gpu {f_gpu:.6e} oracle {f_ref:.6e}")
+    assert abs(f_gpu - f_ref) <= 1e-3
+    ctx.close()
+
+
+@pytest.mark.parametrize("cfg", [3, 4])
+def test_full_size_mode1_contraction_and_ring(cfg):
+    """Full-size workloads: M_1 (FP32 contraction) and S_1 from the Gram ring
+    against the oracle's explicit subchain, and the FP32 first update of mode 1."""
+    w = W.make_workload(cfg)
+    say(f"[full size] {w.name}")
+    Xd = w.X.astype(np.float64)
+    ctx, dev = _ctx(w.X, w.init_cores, w.dims, w.ranks)
+    M = ctx.mttsp(1, "f32").cpu().numpy()
+    Mo = O.mttsp(Xd, w.init_cores, 1)
+    e = rel(M, Mo)
+    say(f"   M_1 rel err {e:.2e}")
+    assert e <= 1e-5
+    S = ctx.coef(1).cpu().numpy()
+    So = O.coef_matrix_paper(w.init_cores, 1)
+    assert rel(S, So) <= 1e-12
+    ctx.update_mode(1, "f32", refine=2)
+    ctx.store_cores()
+    G1 = cores_from_dev(dev, w.dims, w.ranks)[0]
+    G1o, _ = O.als_update(Xd, w.init_cores, 1, "ne")
+    e1 = rel(G1, G1o)
+    # reported; gated loosely (conditioning amplifies the FP32 rounding of M_1)
+    say(f"   first update rel err {e1:.2e}")
+    assert e1 <= 1e-2
+    ctx.close()
