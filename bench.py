@@ -111,7 +111,8 @@ def main():
         bound = "mfma"
     if bound == "hbm":
         roof = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": None}
+                "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic() if args.prec == "bf16" else None}
     else:
         roof = {"bound": "mfma", "achieved": round(achieved_tf, 2), "peak": MFMA_PEAK_TFLOPS["f32"],
                 "unit": "TFLOP/s", "frac": round(achieved_tf / MFMA_PEAK_TFLOPS["f32"], 4), "traffic": None}
@@ -190,6 +191,24 @@ def main():
     }
     out.update(extra)
     print(json.dumps(out))
+
+
+def measured_traffic():
+    """HBM bytes per launch of the BF16 X-contraction kernel on this workload,
+    from the committed FETCH_SIZE / WRITE_SIZE counter summary (copy-calibrated);
+    None when the kernel source changed since the counters were taken."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "xgemm_bf16_100x4_R10_hbm_counters.md")
+    src = os.path.join(ROOT, "paper_2210_11362_amd", "csrc", "k_xgemm.hip")
+    try:
+        fields = dict(l.split(":", 1) for l in open(prof) if l.startswith(("traffic_bytes_per_launch:",
+                                                                            "kernel_source_sha256:")))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if fields["kernel_source_sha256"].strip() != sha:
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def serving_leg(njobs: int):

@@ -64,7 +64,8 @@ hipError_t launch_xg_reduce(const XgArgs& g, int prec, double out_scale, double*
 hipError_t launch_table_to_bt(const double* T, int64_t K, int C, int Crows, int64_t ldb, int prec, double scale,
                               void* Bt, hipStream_t s);
 hipError_t launch_absorb(const double* Y, int64_t lo, int64_t I, int64_t hi, int Ru, int Rc, const double* core,
-                         int Rl, int Rr, int side, int final_out, double* out, hipStream_t s);
+                         int Rl, int Rr, int side, int final_out, double* out, double* part, size_t part_bytes,
+                         hipStream_t s);
 hipError_t launch_bond_to_M(const double* Y, int64_t In, int Ru, int Rc, double* M, hipStream_t s);
 hipError_t launch_xstream(const XsArgs& a, int prec, int xdt, int kt, int wlay, size_t lds, hipStream_t s);
 size_t xstream_lds_bytes(const XsArgs& a, int prec, int kt);

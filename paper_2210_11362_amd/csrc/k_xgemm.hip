@@ -9,6 +9,7 @@
 // tiles are summed in a fixed order in FP64.  Stage 2 absorbs the remaining
 // modes other than n one at a time into the small intermediate (FP64).
 #include <algorithm>
+#include <cstdlib>
 #include <type_traits>
 
 #include "common.h"
@@ -322,6 +323,105 @@ __global__ __launch_bounds__(256) void absorb_block_kernel(AbsorbArgs a) {
   if (tid == 0) absorb_store(a, l, h, u2, c2, red[0]);
 }
 
+// Single-read absorption.  With x the contracted bond index, p the passive
+// one and f the free index of the core (side 0: x = u, p = c, f = the core's
+// left index; side 1: x = c, p = u, f = the core's right index), output
+// (l, h, p, f) is the sum over (i, x) of Y[l, i, h, bond(x, p)] core(f, i, x).
+// A lane keeps all f of its output group in registers, so every Y element is
+// loaded once, and issues the Rx loads of one i together (memory-level
+// parallelism); core values come from LDS as wave-uniform broadcasts.
+// Lanes run on l (lo >= 32: narrow fast extents use the one-output-per-
+// workgroup kernel above); 8 waves and S workgroups split i, and the partial
+// sums are added in a fixed order.
+struct Absorb2 {
+  const double* Y; int64_t lo, I, hi; int Ru, Rc, Rl, Rr, final_out; const double* core; double* out;
+  double* part; int S; int64_t out_elems;
+};
+
+template <bool SIDE0>
+__device__ __forceinline__ int64_t absorb2_out(const Absorb2& a, int64_t l, int64_t h, int p, int f) {
+  const int u2 = SIDE0 ? f : p, c2 = SIDE0 ? p : f;
+  const int Ru2 = SIDE0 ? a.Rl : a.Ru, Rc2 = SIDE0 ? a.Rc : a.Rr;
+  if (a.final_out) return (l + a.lo * h) + a.lo * a.hi * (c2 + (int64_t)Rc2 * u2);
+  return l + a.lo * (h + a.hi * (u2 + (int64_t)Ru2 * c2));
+}
+
+// core(f, i, x) -> cs[((i - i0) * Rx + x) * Rf + f] for i in [i0, i1)
+template <bool SIDE0>
+__device__ __forceinline__ void absorb2_stage_core(const Absorb2& a, int64_t i0, int64_t i1, double* cs) {
+  const int Rx = SIDE0 ? a.Ru : a.Rc, Rf = SIDE0 ? a.Rl : a.Rr;
+  const int64_t n = (i1 - i0) * Rx * Rf;
+  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
+    const int f = (int)(e % Rf);
+    const int x = (int)((e / Rf) % Rx);
+    const int64_t i = i0 + e / ((int64_t)Rf * Rx);
+    cs[e] = SIDE0 ? a.core[f + (int64_t)a.Rl * (i + a.I * x)] : a.core[x + (int64_t)a.Rc * (i + a.I * f)];
+  }
+}
+
+constexpr int AW_WAVES = 8;
+
+template <int B, bool SIDE0>
+__global__ __launch_bounds__(64 * AW_WAVES) void absorb_wide_kernel(Absorb2 a, int64_t chunk) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* cs = reinterpret_cast<double*>(smem_raw);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t l = (int64_t)blockIdx.x * 64 + lane;
+  const int Rx = SIDE0 ? a.Ru : a.Rc, Rf = SIDE0 ? a.Rl : a.Rr;
+  const int64_t h = blockIdx.y % a.hi;
+  const int p = (int)(blockIdx.y / a.hi);
+  const int sp = blockIdx.z;
+  const int64_t ib = (int64_t)sp * chunk, ie = min(a.I, ib + chunk);
+  absorb2_stage_core<SIDE0>(a, ib, ie, cs);
+  __syncthreads();
+  const int64_t i0 = ib + (ie - ib) * wave / AW_WAVES, i1 = ib + (ie - ib) * (wave + 1) / AW_WAVES;
+  double acc[B];
+#pragma unroll
+  for (int f = 0; f < B; ++f) acc[f] = 0.0;
+  const int64_t sx = SIDE0 ? a.lo * a.I * a.hi : a.lo * a.I * a.hi * a.Ru;   // Y stride of x
+  const int64_t y0 = l + a.lo * a.I * h + a.lo * a.I * a.hi * (SIDE0 ? (int64_t)a.Ru * p : (int64_t)p);
+  if (l < a.lo) {
+    for (int64_t i = i0; i < i1; ++i) {
+      double y[B];
+#pragma unroll
+      for (int x = 0; x < B; ++x) y[x] = (x < Rx) ? a.Y[y0 + a.lo * i + sx * x] : 0.0;
+      const double* c = cs + (i - ib) * Rx * Rf;
+#pragma unroll
+      for (int x = 0; x < B; ++x) {
+        if (x < Rx) {
+#pragma unroll
+          for (int f = 0; f < B; ++f)
+            if (f < Rf) acc[f] += y[x] * c[x * Rf + f];
+        }
+      }
+    }
+  }
+  __syncthreads();   // the core slice is dead: its LDS holds the wave partials now
+  double* red = cs;  // [AW_WAVES][B][64]
+#pragma unroll
+  for (int f = 0; f < B; ++f) red[(wave * B + f) * 64 + lane] = acc[f];
+  __syncthreads();
+  if (wave == 0 && l < a.lo) {
+    for (int f = 0; f < Rf; ++f) {
+      double v = 0.0;
+#pragma unroll
+      for (int w = 0; w < AW_WAVES; ++w) v += red[(w * B + f) * 64 + lane];
+      const int64_t e = absorb2_out<SIDE0>(a, l, h, p, f);
+      if (a.S == 1) a.out[e] = v;
+      else a.part[(int64_t)sp * a.out_elems + e] = v;
+    }
+  }
+}
+
+// out[e] = sum over splits s (in order) of part[s][e]
+__global__ void absorb_sum_kernel(const double* part, int S, int64_t n, double* out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double v = 0.0;
+  for (int s = 0; s < S; ++s) v += part[(int64_t)s * n + e];
+  out[e] = v;
+}
+
 // M[i + In*(c + Rc*u)] = Y[i + In*(u + Ru*c)] : final reordering when no mode is
 // left to absorb.
 __global__ void bond_to_M_kernel(const double* Y, int64_t In, int Ru, int Rc, double* M) {
@@ -386,9 +486,62 @@ hipError_t launch_table_to_bt(const double* T, int64_t K, int C, int Crows, int6
   return hipGetLastError();
 }
 
+namespace {
+
+constexpr size_t ABSORB_LDS_MAX = 96 * 1024;
+
+template <int B, bool SIDE0>
+hipError_t launch_absorb2(const Absorb2& a, hipStream_t s) {
+  const int Rx = SIDE0 ? a.Ru : a.Rc, Rf = SIDE0 ? a.Rl : a.Rr, Rp = SIDE0 ? a.Rc : a.Ru;
+  const size_t row = (size_t)Rx * Rf * sizeof(double);   // core bytes per value of i
+  if (a.lo >= 32) {
+    const int64_t chunk = cdiv(a.I, a.S);
+    const size_t lds = std::max((size_t)chunk * row, (size_t)AW_WAVES * B * 64 * sizeof(double));
+    if (lds > 64 * 1024)
+      hipFuncSetAttribute((const void*)absorb_wide_kernel<B, SIDE0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)lds);
+    dim3 grid((unsigned)cdiv(a.lo, 64), (unsigned)(a.hi * Rp), (unsigned)cdiv(a.I, chunk));
+    hipLaunchKernelGGL((absorb_wide_kernel<B, SIDE0>), grid, dim3(64 * AW_WAVES), lds, s, a, chunk);
+    if (a.S > 1)
+      hipLaunchKernelGGL(absorb_sum_kernel, dim3((unsigned)cdiv(a.out_elems, 256)), dim3(256), 0, s, a.part, a.S,
+                         a.out_elems, a.out);
+    return hipGetLastError();
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
 hipError_t launch_absorb(const double* Y, int64_t lo, int64_t I, int64_t hi, int Ru, int Rc, const double* core,
-                         int Rl, int Rr, int side, int final_out, double* out, hipStream_t s) {
+                         int Rl, int Rr, int side, int final_out, double* out, double* part, size_t part_bytes,
+                         hipStream_t s) {
   const int Ru2 = side == 0 ? Rl : Ru, Rc2 = side == 0 ? Rc : Rr;
+  const int Rx = side == 0 ? Ru : Rc, Rf = side == 0 ? Rl : Rr, Rp = side == 0 ? Rc : Ru;
+  const int64_t out_elems = lo * hi * Ru2 * Rc2;
+  const size_t row = (size_t)Rx * Rf * sizeof(double);
+  const int Bn = std::max(Rx, Rf);
+  if (lo >= 32 && Bn <= 24 && row * AW_WAVES <= ABSORB_LDS_MAX) {
+    Absorb2 a{Y, lo, I, hi, Ru, Rc, Rl, Rr, final_out, core, out, part, 1, out_elems};
+    // split i over workgroups until there are ~1024 of them, at least 2 values
+    // of i per wave, within the LDS budget for the core slice and the
+    // partial-sum buffer
+    const int64_t groups = cdiv(lo, 64) * hi * Rp;
+    int64_t S = std::max<int64_t>(1, std::min<int64_t>(cdiv(1024, groups), I / (2 * AW_WAVES)));
+    while (S > 1 && ((size_t)S * out_elems * sizeof(double) > part_bytes)) --S;
+    while ((size_t)cdiv(I, S) * row > ABSORB_LDS_MAX) ++S;
+    a.S = (int)cdiv(I, cdiv(I, S));
+    if (a.S > 1 && (size_t)a.S * out_elems * sizeof(double) > part_bytes) a.S = 0;   // no room: other kernels
+    if (a.S > 0) {
+      if (side == 0) {
+        if (Bn <= 8) return launch_absorb2<8, true>(a, s);
+        if (Bn <= 16) return launch_absorb2<16, true>(a, s);
+        return launch_absorb2<24, true>(a, s);
+      }
+      if (Bn <= 8) return launch_absorb2<8, false>(a, s);
+      if (Bn <= 16) return launch_absorb2<16, false>(a, s);
+      return launch_absorb2<24, false>(a, s);
+    }
+  }
   AbsorbArgs a{Y, lo, I, hi, Ru, Rc, core, Rl, Rr, side, final_out, out};
   if (lo >= 32) {
     dim3 grid((unsigned)cdiv(lo, 64), (unsigned)hi, (unsigned)(Ru2 * Rc2));

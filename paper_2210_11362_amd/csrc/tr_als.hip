@@ -486,7 +486,8 @@ int compute_mttsp_two_stage(tr_als_ctx* c, int m, int prec, double* Mout, bool i
     const bool last = q + 1 == p.steps.size();
     double* nxt = last ? Mout : (cur == c->Y0 ? c->Y1 : c->Y0);
     HIPCHK(c, launch_absorb(cur, st.lo, st.I, st.hi, st.Ru, st.Rc, c->cores[st.core], c->R[st.core],
-                            c->R[st.core + 1], st.side, last ? 1 : 0, nxt, s));
+                            c->R[st.core + 1], st.side, last ? 1 : 0, nxt, (double*)c->partial, c->partial_bytes,
+                            s));
     cur = nxt;
   }
   return TR_OK;
