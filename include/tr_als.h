@@ -191,7 +191,11 @@ int tr_gen_planted(int N, const int64_t* dims, const int64_t* ranks, uint64_t se
  * sweeps in prec_mixed, nsweeps_fin sweeps in prec_fin, and the fit; its final
  * cores are kept on the host for tr_srv_result.  All kernels are
  * deterministic, so a job's result does not depend on what else runs.
- * Small same-shape-class jobs are batched (see TR_SRV_BATCH below).
+ * With TR_SRV_BATCH, small NE jobs (order 2..4, ranks <= 8, mode sizes <= 128,
+ * at most 2^18 entries, contraction FP64/FP32/BF16) skip the slots: the small
+ * jobs admitted together go to an idle batch lane, where one persistent launch
+ * runs each whole job (all sweeps, solve, fit) in one workgroup; two lanes
+ * alternate.  A lane job's result is likewise independent of its batch.
  * All times are seconds since tr_srv_create (steady clock).
  * ------------------------------------------------------------------------ */
 
@@ -243,7 +247,7 @@ typedef struct {
  *                     (0: 90% of the free device memory); allocated here.
  *   max_slots         concurrent jobs, 1..64; each slot owns a thread and
  *                     two streams (default priority).
- *   flags             TR_SRV_BATCH: allow batching of small jobs.
+ *   flags             TR_SRV_BATCH: run small jobs in the batch lanes.
  * Returns TR_EINVAL, TR_ENOMEM (arena allocation) or TR_EHIP on failure.
  */
 enum { TR_SRV_BATCH = 1 };

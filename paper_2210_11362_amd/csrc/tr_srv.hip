@@ -20,6 +20,7 @@
 
 #include "common.h"
 #include "runtime.h"
+#include "tiny.h"
 
 namespace {
 
@@ -82,6 +83,7 @@ struct Job {
   int64_t numel = 1;
   size_t bytes_x = 0, bytes_cores = 0, bytes_gen = 0, bytes_ctx = 0, footprint = 0;
   unsigned shadow_mask = 0;
+  bool tiny = false;          // runs in a batch lane
   int state = TR_JOB_QUEUED;
   int status = TR_OK;
   double rel_err = NAN;
@@ -105,6 +107,24 @@ struct Slot {
   std::string err;
 };
 
+// A batch lane runs up to LANE_MAX small jobs as one persistent launch (one
+// workgroup per job): its stream, completion event, descriptor arrays and
+// pinned memory for the jobs' results.
+constexpr int LANE_MAX = 64;
+constexpr int NLANES = 2;
+
+struct Lane {
+  hipStream_t s = nullptr;
+  hipEvent_t done = nullptr;
+  std::vector<Job*> jobs;
+  TinyJob* h_desc = nullptr;   // pinned
+  TinyJob* d_desc = nullptr;   // device
+  char* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  int rc = TR_OK;
+  std::string err;
+};
+
 inline size_t esize(int dt) { return dt == TR_F64 ? 8 : 4; }
 
 inline size_t core_elems(const tr_job_desc& d, int k) {
@@ -120,6 +140,7 @@ struct tr_srv {
   int device = 0;
   Arena arena;
   std::vector<Slot> slots;
+  std::vector<Lane> lanes;
   std::vector<char*> old_pinned;   // outgrown pinned buffers, freed at destroy
   std::thread exec;
   std::mutex mu;
@@ -276,24 +297,45 @@ JobOut finish_job(Slot& sl) {
   return r;
 }
 
-// Admission: arrived jobs in arrival order, each needing a free slot and one
-// contiguous arena region of its footprint.  When the oldest arrived job does
-// not fit, later jobs with footprint <= arena/64 may go first, for at most
-// HEAD_MAX_WAIT_S seconds of the head's waiting.  Called with the lock held;
-// returns the slots that received a job and the next future arrival (or -1).
-void admit(tr_srv* srv, std::vector<int>* started, double* next_arrival) {
+// Admission: arrived jobs in arrival order, each needing one contiguous arena
+// region of its footprint and a free slot (small jobs of a batching server: a
+// place in a batch lane; the jobs admitted to an idle lane in one pass form its
+// next batch).  When the oldest arrived regular job does not fit, later jobs
+// with footprint <= arena/64 may go first, for at most HEAD_MAX_WAIT_S seconds
+// of the head's waiting.  Called with the lock held; returns the slots and
+// lanes that received work and the next future arrival (or -1).
+void admit(tr_srv* srv, std::vector<int>* started, std::vector<int>* lanes_started, double* next_arrival) {
   const double now = srv->now();
   *next_arrival = -1;
   bool head = true, backfill_ok = true;
+  int forming = -1;
   for (size_t q = 0; q < srv->pending.size();) {
     Job* j = srv->pending[q];
     if (j->t_arrival > now) { *next_arrival = j->t_arrival; break; }
+    size_t off = 0;
+    if (j->tiny) {
+      if (forming < 0 || srv->lanes[forming].jobs.size() >= (size_t)LANE_MAX) {
+        forming = -1;
+        for (size_t k = 0; k < srv->lanes.size(); ++k)
+          if (srv->lanes[k].jobs.empty()) { forming = (int)k; break; }
+        if (forming >= 0) lanes_started->push_back(forming);
+      }
+      if (forming < 0 || !srv->arena.alloc(j->footprint, &off)) { ++q; continue; }
+      j->off = off;
+      j->slot = forming;
+      j->state = TR_JOB_RUNNING;
+      j->t_admit = now;
+      srv->lanes[forming].jobs.push_back(j);
+      srv->running++;
+      srv->max_running = std::max(srv->max_running, srv->running);
+      srv->pending.erase(srv->pending.begin() + q);
+      continue;
+    }
     int free_slot = -1;
     for (size_t k = 0; k < srv->slots.size(); ++k)
       if (!srv->slots[k].job) { free_slot = (int)k; break; }
-    if (free_slot < 0) break;
+    if (free_slot < 0) { ++q; continue; }
     const bool small = j->footprint <= srv->arena.cap / 64;
-    size_t off = 0;
     if ((!head && !(backfill_ok && small)) || !srv->arena.alloc(j->footprint, &off)) {
       if (head) {
         if (srv->head_block_id != j->id) { srv->head_block_id = j->id; srv->head_block_since = now; }
@@ -316,6 +358,144 @@ void admit(tr_srv* srv, std::vector<int>* started, double* next_arrival) {
   }
 }
 
+// Generate (or borrow) each job's X and initial cores in its arena region and
+// enqueue the lane's batch: descriptors to the device, one persistent launch,
+// results to pinned memory, completion event.
+int start_batch(tr_srv* srv, Lane& ln) {
+  hipStream_t s = ln.s;
+  size_t need = 0;
+  for (const Job* j : ln.jobs) {
+    need += PIN_HEAD;
+    for (int k = 0; k < j->d.N; ++k) need += core_elems(j->d, k) * 8;
+  }
+  if (need > ln.pinned_bytes) {
+    void* p = nullptr;
+    const size_t want = std::max(need, 2 * ln.pinned_bytes);
+    if (hipHostMalloc(&p, want, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      ln.err = "pinned host allocation failed";
+      return TR_ENOMEM;
+    }
+    if (ln.pinned) srv->old_pinned.push_back(ln.pinned);
+    ln.pinned = (char*)p;
+    ln.pinned_bytes = want;
+  }
+  std::vector<std::vector<double*>> cores_of(ln.jobs.size());
+  for (size_t q = 0; q < ln.jobs.size(); ++q) {
+    const Job* j = ln.jobs[q];
+    const tr_job_desc& d = j->d;
+    char* base = srv->arena.base + j->off;
+    size_t off = 0;
+    auto carve = [&](size_t b) {
+      char* p = base + off;
+      off += trx_round(b);
+      return p;
+    };
+    void* X = d.X ? const_cast<void*>(d.X) : (void*)carve(j->numel * esize(d.x_dtype));
+    double* cores[TR_MAXN] = {nullptr};
+    for (int k = 0; k < d.N; ++k) cores[k] = (double*)carve(core_elems(d, k) * 8);
+    char* shared = base + off;   // generator workspace, then the batch kernel's scratch
+    if (!d.X) {
+      const int rc = trx_gen(d.N, d.dims, d.ranks, d.seed, d.eta, X, d.x_dtype, nullptr,
+                             d.init_cores ? nullptr : cores, shared, j->bytes_gen, s, &ln.err);
+      if (rc) return rc;
+    } else if (!d.init_cores) {
+      for (int k = 0; k < d.N; ++k)
+        if (launch_philox_normal(cores[k], (int64_t)core_elems(d, k), d.seed, GEN_SID_INIT + k, s) != hipSuccess) {
+          ln.err = "initial-core generation failed";
+          return TR_EHIP;
+        }
+    }
+    if (d.init_cores)
+      for (int k = 0; k < d.N; ++k)
+        if (hipMemcpyAsync(cores[k], j->init_ptrs[k], core_elems(d, k) * 8, hipMemcpyDeviceToDevice, s) !=
+            hipSuccess) {
+          ln.err = "copy of the initial cores failed";
+          return TR_EHIP;
+        }
+    tiny_fill(&ln.h_desc[q], d.N, d.dims, d.ranks, X, d.x_dtype, cores, (double*)shared, d.nsweeps_mixed,
+              d.prec_mixed, d.nsweeps_fin, d.prec_fin, d.refine);
+    cores_of[q].assign(cores, cores + d.N);
+  }
+  const int n = (int)ln.jobs.size();
+  if (hipMemcpyAsync(ln.d_desc, ln.h_desc, n * sizeof(TinyJob), hipMemcpyHostToDevice, s) != hipSuccess ||
+      launch_tiny_als(ln.d_desc, n, s) != hipSuccess) {
+    ln.err = "batch launch failed";
+    return TR_EHIP;
+  }
+  size_t po = 0;
+  for (size_t q = 0; q < ln.jobs.size(); ++q) {
+    const tr_job_desc& d = ln.jobs[q]->d;
+    if (hipMemcpyAsync(ln.pinned + po, ln.h_desc[q].status, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(ln.pinned + po + 16, ln.h_desc[q].scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s) !=
+            hipSuccess) {
+      ln.err = "copy of the results failed";
+      return TR_EHIP;
+    }
+    po += PIN_HEAD;
+    for (int k = 0; k < d.N; ++k) {
+      if (hipMemcpyAsync(ln.pinned + po, cores_of[q][k], core_elems(d, k) * 8, hipMemcpyDeviceToHost, s) !=
+          hipSuccess) {
+        ln.err = "copy of the final cores failed";
+        return TR_EHIP;
+      }
+      po += core_elems(d, k) * 8;
+    }
+  }
+  if (hipEventRecord(ln.done, s) != hipSuccess) {
+    ln.err = "event record failed";
+    return TR_EHIP;
+  }
+  return TR_OK;
+}
+
+std::vector<JobOut> finish_batch(Lane& ln) {
+  std::vector<JobOut> out(ln.jobs.size());
+  const bool sync_ok = hipStreamSynchronize(ln.s) == hipSuccess;
+  if (!sync_ok) (void)hipGetLastError();
+  size_t po = 0;
+  for (size_t q = 0; q < ln.jobs.size(); ++q) {
+    JobOut& r = out[q];
+    const tr_job_desc& d = ln.jobs[q]->d;
+    if (ln.rc != TR_OK || !sync_ok) {
+      r.rc = ln.rc != TR_OK ? ln.rc : TR_EHIP;
+      r.err = ln.rc != TR_OK ? ln.err : "stream synchronisation failed";
+      continue;
+    }
+    const int st = *(const int*)(ln.pinned + po);
+    const double* sc = (const double*)(ln.pinned + po + 16);
+    if (st) {
+      r.rc = (st & ST_SINGULAR) ? TR_ESINGULAR : TR_ENONFINITE;
+      r.err = trx_status_text(st);
+    } else {
+      r.rel_err = sc[0] > 0 ? std::sqrt(std::max(0.0, sc[1])) / std::sqrt(sc[0]) : 0.0;
+    }
+    po += PIN_HEAD;
+    r.cores.resize(d.N);
+    for (int k = 0; k < d.N; ++k) {
+      const double* src = (const double*)(ln.pinned + po);
+      r.cores[k].assign(src, src + core_elems(d, k));
+      po += core_elems(d, k) * 8;
+    }
+  }
+  ln.rc = TR_OK;
+  ln.err.clear();
+  return out;
+}
+
+void commit_job(tr_srv* srv, Job* j, JobOut& r) {
+  srv->arena.release(j->off, j->footprint);
+  j->rel_err = r.rel_err;
+  j->cores = std::move(r.cores);
+  j->err = std::move(r.err);
+  j->status = r.rc;
+  j->state = r.rc == TR_OK ? TR_JOB_DONE : TR_JOB_FAILED;
+  j->t_done = srv->now();
+  if (r.rc == TR_OK) srv->n_done++;
+  else srv->n_failed++;
+  srv->running--;
+}
+
 // The executor: the only thread that calls HIP.  It admits jobs, enqueues each
 // admitted job's whole work on its slot, and polls the slots' completion
 // events; queued jobs are dropped and running ones finished when stopping.
@@ -324,15 +504,20 @@ void exec_main(tr_srv* srv) {
   std::unique_lock<std::mutex> lk(srv->mu);
   for (;;) {
     if (srv->stop && srv->running == 0) break;
-    std::vector<int> started;
+    std::vector<int> started, lanes_started;
     double next_arrival = -1;
     const uint64_t seen = srv->gen;
-    if (!srv->stop) admit(srv, &started, &next_arrival);
+    if (!srv->stop) admit(srv, &started, &lanes_started, &next_arrival);
     lk.unlock();
     for (int k : started) {
       Slot& sl = srv->slots[k];
       sl.rc = start_job(srv, sl);
       if (sl.rc != TR_OK) (void)hipGetLastError();
+    }
+    for (int k : lanes_started) {
+      Lane& ln = srv->lanes[k];
+      ln.rc = start_batch(srv, ln);
+      if (ln.rc != TR_OK) (void)hipGetLastError();
     }
     // completions
     std::vector<std::pair<int, JobOut>> finished;
@@ -352,25 +537,36 @@ void exec_main(tr_srv* srv) {
       }
       if (ready) finished.emplace_back((int)k, finish_job(sl));
     }
+    std::vector<std::pair<int, std::vector<JobOut>>> lanes_finished;
+    for (size_t k = 0; k < srv->lanes.size(); ++k) {
+      Lane& ln = srv->lanes[k];
+      if (ln.jobs.empty()) continue;
+      bool ready = ln.rc != TR_OK;
+      if (!ready) {
+        const hipError_t q = hipEventQuery(ln.done);
+        if (q == hipSuccess) ready = true;
+        else if (q != hipErrorNotReady) {
+          (void)hipGetLastError();
+          ln.rc = TR_EHIP;
+          ln.err = "completion event failed";
+          ready = true;
+        }
+      }
+      if (ready) lanes_finished.emplace_back((int)k, finish_batch(ln));
+    }
     lk.lock();
     for (auto& f : finished) {
       Slot& sl = srv->slots[f.first];
-      Job* j = sl.job;
-      JobOut& r = f.second;
-      srv->arena.release(j->off, j->footprint);
-      j->rel_err = r.rel_err;
-      j->cores = std::move(r.cores);
-      j->err = std::move(r.err);
-      j->status = r.rc;
-      j->state = r.rc == TR_OK ? TR_JOB_DONE : TR_JOB_FAILED;
-      j->t_done = srv->now();
-      if (r.rc == TR_OK) srv->n_done++;
-      else srv->n_failed++;
-      srv->running--;
+      commit_job(srv, sl.job, f.second);
       sl.job = nullptr;
     }
-    if (!finished.empty()) srv->cv_done.notify_all();
-    if (!started.empty() || !finished.empty()) continue;
+    for (auto& f : lanes_finished) {
+      Lane& ln = srv->lanes[f.first];
+      for (size_t q = 0; q < ln.jobs.size(); ++q) commit_job(srv, ln.jobs[q], f.second[q]);
+      ln.jobs.clear();
+    }
+    if (!finished.empty() || !lanes_finished.empty()) srv->cv_done.notify_all();
+    if (!started.empty() || !finished.empty() || !lanes_started.empty() || !lanes_finished.empty()) continue;
     // A submit (or stop) while the lock was released notified nobody: its job
     // is not in next_arrival, so admit again instead of waiting.
     if (srv->gen != seen) continue;
@@ -396,6 +592,15 @@ void release_slots(tr_srv* srv) {
     if (sl.done) (void)hipEventDestroy(sl.done);
     if (sl.pinned) (void)hipHostFree(sl.pinned);
     sl = Slot();
+  }
+  for (auto& ln : srv->lanes) {
+    if (ln.s) (void)hipStreamSynchronize(ln.s);
+    if (ln.s) (void)hipStreamDestroy(ln.s);
+    if (ln.done) (void)hipEventDestroy(ln.done);
+    if (ln.h_desc) (void)hipHostFree(ln.h_desc);
+    if (ln.d_desc) (void)hipFree(ln.d_desc);
+    if (ln.pinned) (void)hipHostFree(ln.pinned);
+    ln = Lane();
   }
   for (char* p : srv->old_pinned) (void)hipHostFree(p);
   srv->old_pinned.clear();
@@ -459,6 +664,30 @@ int tr_srv_create(tr_srv** out, size_t hbm_budget_bytes, int max_slots, int flag
     sl.pinned = (char*)pin;
     sl.pinned_bytes = PIN_DEFAULT;
   }
+  if (rc == TR_OK && (flags & TR_SRV_BATCH)) {
+    srv->lanes.resize(NLANES);
+    for (auto& ln : srv->lanes) {
+      void* h = nullptr;
+      void* pin = nullptr;
+      void* dd = nullptr;
+      if (hipStreamCreateWithFlags(&ln.s, hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&ln.done, hipEventDisableTiming) != hipSuccess) {
+        rc = TR_EHIP;
+        break;
+      }
+      if (hipHostMalloc(&h, LANE_MAX * sizeof(TinyJob), 0) != hipSuccess ||
+          hipHostMalloc(&pin, PIN_DEFAULT, 0) != hipSuccess || hipMalloc(&dd, LANE_MAX * sizeof(TinyJob)) != hipSuccess) {
+        if (h) (void)hipHostFree(h);
+        if (pin) (void)hipHostFree(pin);
+        rc = TR_ENOMEM;
+        break;
+      }
+      ln.h_desc = (TinyJob*)h;
+      ln.d_desc = (TinyJob*)dd;
+      ln.pinned = (char*)pin;
+      ln.pinned_bytes = PIN_DEFAULT;
+    }
+  }
   if (rc) {
     (void)hipGetLastError();
     release_slots(srv.get());
@@ -494,7 +723,11 @@ int tr_srv_submit(tr_srv* srv, const tr_job_desc* desc, uint64_t* job_id) {
   for (int k = 0; k < d.N; ++k)
     j->bytes_cores += trx_round((size_t)d.ranks[k] * d.dims[k] * d.ranks[(k + 1) % d.N] * 8);
   j->bytes_gen = d.X ? 0 : trx_gen_workspace(d.N, d.dims, d.ranks, true);
-  j->bytes_ctx = trx_footprint(d.N, d.dims, d.ranks, d.x_dtype, d.variant, j->shadow_mask);
+  auto lane_prec = [](int p) { return p == TR_F64 || p == TR_F32 || p == TR_BF16; };
+  j->tiny = (srv->flags & TR_SRV_BATCH) && d.variant == TR_NE && tiny_eligible(d.N, d.dims, d.ranks) &&
+            (d.nsweeps_mixed == 0 || lane_prec(d.prec_mixed)) && (d.nsweeps_fin == 0 || lane_prec(d.prec_fin));
+  j->bytes_ctx = j->tiny ? trx_round(tiny_ws_bytes(d.N, d.dims, d.ranks))
+                         : trx_footprint(d.N, d.dims, d.ranks, d.x_dtype, d.variant, j->shadow_mask);
   if (j->bytes_ctx == 0 || (!d.X && j->bytes_gen == 0)) return TR_EINVAL;
   j->footprint = j->bytes_x + j->bytes_cores + std::max(j->bytes_gen, j->bytes_ctx);
   if (j->footprint > srv->arena.cap) return TR_ENOMEM;
@@ -523,7 +756,7 @@ static void fill_info(const Job& j, tr_job_info* info) {
   info->t_done = j.t_done;
   info->footprint = j.footprint;
   info->slot = j.slot;
-  info->batched = 0;
+  info->batched = j.tiny ? 1 : 0;
 }
 
 int tr_srv_poll(tr_srv* srv, uint64_t id, tr_job_info* info) {

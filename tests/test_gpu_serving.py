@@ -187,3 +187,80 @@ def test_failed_job_does_not_disturb_others():
     assert "positive definite" in srv.error(bad)
     assert ig["state"] == 2 and 0.0 < ig["rel_err"] < 1.0
     srv.close()
+
+
+# ---------------------------------------------------------------------------
+# Batched lane: small jobs (order <= 4, ranks <= 8, mode sizes <= 128, at most
+# 2^18 entries) run whole inside one persistent workgroup each, many per launch.
+# ---------------------------------------------------------------------------
+
+def _batch_server(budget=4 * GB, slots=4):
+    from paper_2210_11362_amd import TRServer
+    return TRServer(budget, slots, batch=True)
+
+
+LANE_JOBS = [((12, 10, 9), (2, 3, 2)), ((9, 8, 7, 6), (2, 2, 3, 2)), ((20, 17, 15), (4, 3, 5)),
+             ((16, 12, 10, 8), (3, 4, 3, 2)), ((30, 25), (3, 4)), ((24, 20, 18), (6, 5, 4))]
+
+
+def test_batched_lane_matches_oracle_fp64():
+    srv = _batch_server()
+    ids = []
+    for k, (dims, ranks) in enumerate(LANE_JOBS):
+        ids.append(srv.submit(dims, ranks, seed=500 + k, eta=0.02, prec_mixed="f64", nsweeps_mixed=3,
+                              prec_fin="f64", nsweeps_fin=0, x_dtype="f64"))
+    srv.drain()
+    for k, ((dims, ranks), jid) in enumerate(zip(LANE_JOBS, ids)):
+        info = srv.poll(jid)
+        say(f"[lane f64] dims={dims} ranks={ranks} state={info['state']} batched={info['batched']}")
+        assert info["state"] == 2, srv.error(jid)
+        assert info["batched"]
+        X, _, init = PH.planted_job(dims, ranks, 500 + k, 0.02, np.float64)
+        ref, _ = O.tr_als(X, init, 3)
+        got = srv.result(jid, dims, ranks)
+        errs = [rel(a, b) for a, b in zip(got, ref)]
+        say(f"   core rel errs max {max(errs):.2e}; fit {info['rel_err']:.6e} vs {O.rel_error(X, ref):.6e}")
+        assert max(errs) <= 1e-10
+        assert abs(info["rel_err"] - O.rel_error(X, ref)) <= 1e-10
+    srv.close()
+
+
+def test_batched_lane_mixed_schedule_fit():
+    srv = _batch_server()
+    ids = [srv.submit(dims, ranks, seed=600 + k, eta=0.01, prec_mixed="bf16", nsweeps_mixed=6, prec_fin="f32",
+                      nsweeps_fin=2) for k, (dims, ranks) in enumerate(LANE_JOBS)]
+    srv.drain()
+    for k, ((dims, ranks), jid) in enumerate(zip(LANE_JOBS, ids)):
+        info = srv.poll(jid)
+        assert info["state"] == 2 and info["batched"], srv.error(jid)
+        X, _, init = PH.planted_job(dims, ranks, 600 + k, 0.01, np.float32)
+        Xd = X.astype(np.float64)
+        ref, _ = O.tr_als(Xd, init, 8)
+        f_ref = O.rel_error(Xd, ref)
+        say(f"[lane mixed] dims={dims} fit gpu {info['rel_err']:.6e} oracle {f_ref:.6e}")
+        assert abs(info["rel_err"] - f_ref) <= 1e-3
+    srv.close()
+
+
+def test_batched_results_identical_alone_and_in_batch():
+    kw = dict(eta=0.01, prec_mixed="bf16", nsweeps_mixed=4, prec_fin="f32", nsweeps_fin=2)
+    srv = _batch_server()
+    alone = []
+    for k, (dims, ranks) in enumerate(LANE_JOBS):
+        jid = srv.submit(dims, ranks, seed=700 + k, **kw)
+        info = srv.wait(jid)
+        assert info["state"] == 2 and info["batched"], srv.error(jid)
+        alone.append((srv.result(jid, dims, ranks), info["rel_err"]))
+    # now all together (one batch), behind a job that takes the per-job path
+    big = srv.submit((60, 50, 40), (10, 10, 10), seed=1, **kw)
+    ids = [srv.submit(dims, ranks, seed=700 + k, **kw) for k, (dims, ranks) in enumerate(LANE_JOBS)]
+    srv.drain()
+    ib = srv.poll(big)
+    assert ib["state"] == 2 and not ib["batched"], srv.error(big)
+    for (dims, ranks), jid, (cores_a, fit_a) in zip(LANE_JOBS, ids, alone):
+        info = srv.poll(jid)
+        assert info["state"] == 2
+        for a, b in zip(cores_a, srv.result(jid, dims, ranks)):
+            assert np.array_equal(a, b)
+        assert info["rel_err"] == fit_a
+    srv.close()
