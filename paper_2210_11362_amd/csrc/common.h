@@ -54,6 +54,7 @@ struct XgArgs {
   int64_t ldb;
   int64_t k_per_split;
   int nsplit;
+  int xcd_map;        // 1: 1-D grid, workgroups on one XCD share k-splits (nsplit % 8 == 0)
   void* partial;      // [nsplit][n_mt*n_nt][MT][NT] FP32 (FP64 for the FP64 path)
 };
 

@@ -87,8 +87,21 @@ __global__ __launch_bounds__(NTHR) void xgemm_kernel(XgArgs g) {
   op_t* Bs = As + MT * ST;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int mt = blockIdx.x % g.n_mt, nt = blockIdx.x / g.n_mt;
-  const int split = blockIdx.y;
+  // Tile and k-split of this workgroup.  Workgroups are dispatched round-robin
+  // over the 8 XCDs by linear id; with xcd_map the ones that land on one XCD
+  // take the same k-splits, so each slice of the operand table is fetched
+  // into one L2 and reused there by every row tile.
+  const int ntiles = g.n_mt * g.n_nt;
+  int tile, split;
+  if (g.xcd_map) {
+    const int L = blockIdx.x, xcd = L & 7, j = L >> 3, s8 = g.nsplit >> 3;
+    split = xcd * s8 + j % s8;
+    tile = j / s8;
+  } else {
+    tile = blockIdx.x;
+    split = blockIdx.y;
+  }
+  const int mt = tile % g.n_mt, nt = tile / g.n_mt;
   const int64_t r0 = (int64_t)mt * MT;
   const int NT = g.NT, NB = NT / 16;
   const Tin* X = reinterpret_cast<const Tin*>(g.X);
@@ -177,7 +190,7 @@ __global__ __launch_bounds__(NTHR) void xgemm_kernel(XgArgs g) {
   }
 
   using part_t = typename std::conditional<P == TR_F64, double, float>::type;
-  part_t* out = reinterpret_cast<part_t*>(g.partial) + ((size_t)split * gridDim.x + blockIdx.x) * (size_t)MT * NT;
+  part_t* out = reinterpret_cast<part_t*>(g.partial) + ((size_t)split * ntiles + tile) * (size_t)MT * NT;
 #pragma unroll
   for (int r = 0; r < MBW; ++r)
 #pragma unroll
@@ -440,7 +453,7 @@ template <int P, typename Tin, bool NN, int MT, int KT>
 hipError_t launch_g(const XgArgs& g, hipStream_t s) {
   using op_t = typename PT<P>::op_t;
   const size_t lds = (size_t)(MT + g.NT) * (KT + Pad<P>::v) * sizeof(op_t);
-  dim3 grid(g.n_mt * g.n_nt, g.nsplit);
+  const dim3 grid = g.xcd_map ? dim3((unsigned)(g.n_mt * g.n_nt * g.nsplit)) : dim3(g.n_mt * g.n_nt, g.nsplit);
   auto k = xgemm_kernel<P, Tin, NN, MT, KT, 8>;
   if (lds > 64 * 1024) hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(k, grid, dim3(NTHR), lds, s, g);

@@ -392,9 +392,24 @@ XgArgs xg_config(const tr_als_ctx* c, int m, int prec, const void* X, int esize)
   const int64_t tiles = (int64_t)g.n_mt * g.n_nt;
   int64_t ns = std::max<int64_t>(1, (target_wgs + tiles - 1) / tiles);
   ns = std::min<int64_t>(ns, std::max<int64_t>(1, ktiles / 2));
+  // XCD-aware mapping (TR_ALS_XG_XCD=1) when there are enough splits: a
+  // multiple of 8 of them.  It brings the fetched bytes of the 100^4 rank-10
+  // launch down to the algorithmic ones (202-213 MB instead of 240-294 MB) but
+  // measured ~6% slower, so it is off by default.
+  static const bool env_xcd = getenv("TR_ALS_XG_XCD") && getenv("TR_ALS_XG_XCD")[0] == '1';
+  g.xcd_map = 0;
+  if (env_xcd && ns >= 6 && ktiles >= 16) {
+    const int64_t ns8 = std::max<int64_t>(8, (ns + 4) / 8 * 8);
+    const int64_t tps8 = (ktiles + ns8 - 1) / ns8;
+    if ((ktiles + tps8 - 1) / tps8 == ns8) {   // every one of the ns8 splits has work
+      ns = ns8;
+      g.xcd_map = 1;
+    }
+  }
   const int64_t tps = (ktiles + ns - 1) / ns;
   g.k_per_split = tps * kt;
   g.nsplit = (int)((p.gK + g.k_per_split - 1) / g.k_per_split);
+  if (g.xcd_map && g.nsplit != ns) g.xcd_map = 0;
   g.Bt = c->Bt;
   g.partial = c->partial;
   return g;
