@@ -38,6 +38,8 @@ def main():
     ap.add_argument("--no-schedules", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-jobs", type=int, default=400)
+    ap.add_argument("--serving-only", action="store_true",
+                    help="only run the serving stream and print its JSON (the bench runs it in a child process)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -46,6 +48,9 @@ def main():
               "is the unit; see the sharding notes shipped with the package)", file=sys.stderr)
         sys.exit(2)
 
+    if args.serving_only:
+        print(json.dumps(serving_leg(args.serving_jobs)))
+        return
     import torch
     if args.copy_probe:
         n = 1 << 28                      # 2^28 float32 = 1 GiB read + 1 GiB written per copy
@@ -149,7 +154,7 @@ def main():
 
     # ---- serving: a Poisson stream of small jobs through the request loop ---
     if not args.no_serving and args.serving_jobs > 0:
-        extra["serving"] = serving_leg(args.serving_jobs)
+        extra["serving"] = serving_child(args.serving_jobs)
 
     # ---- CPU oracle on a bounded sample ------------------------------------
     cpu = None
@@ -209,6 +214,21 @@ def measured_traffic():
         return float(fields["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
         return None
+
+
+def serving_child(njobs: int):
+    """The serving stream in a child process (its own device context): a failure
+    there is reported in the bench line instead of ending the bench."""
+    import subprocess
+    try:
+        p = subprocess.run([sys.executable, os.path.abspath(__file__), "--serving-only", "--serving-jobs", str(njobs)],
+                           stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, timeout=300)
+    except subprocess.TimeoutExpired:
+        return {"error": "serving stream timed out after 300 s"}
+    lines = [l for l in p.stdout.splitlines() if l.startswith("{")]
+    if p.returncode != 0 or not lines:
+        return {"error": f"serving stream exited with status {p.returncode}", "stderr_tail": p.stderr[-400:]}
+    return json.loads(lines[-1])
 
 
 def serving_leg(njobs: int):

@@ -48,7 +48,7 @@ struct XgArgs {
   int64_t M, K;
   int C;              // columns of Y (bond pairs)
   int nn;             // 1: group = slowest modes; 0: group = fastest modes
-  int vec_ok;         // rows of A start 16-byte aligned (K-contiguous case)
+  int vec_ok;         // contiguous runs of A (rows, or columns when nn) start 16-byte aligned
   int MT, NT, n_mt, n_nt;
   const void* Bt;
   int64_t ldb;
@@ -90,6 +90,10 @@ hipError_t launch_gemm64(int64_t M, int64_t N, int64_t K, double alpha, MatView 
 hipError_t launch_realign_S(MatView W, int Ra, int Rb, double* S, hipStream_t s);
 hipError_t launch_chol(const double* S, int n, double* L, double* LT, double* work, int* status, hipStream_t s);
 bool solve_in_lds(int n);
+// S^{-1} of an SPD matrix with n <= 128 by the symmetric sweep operator (one
+// workgroup, registers); a non-positive pivot latches ST_SINGULAR.
+bool spd_inverse_fits(int n);
+hipError_t launch_spd_inverse(const double* S, int n, double* Sinv, int* status, hipStream_t s);
 hipError_t launch_chol_lds(const double* S, int n, double* L, double* LT, double* rdiag, int* status, hipStream_t s);
 hipError_t launch_trsm_rhs(const double* L, const double* rdiag, int n, const double* Rhs, int64_t I, double* G,
                            int accumulate, const int* status, hipStream_t s, int mode = 0);
@@ -109,11 +113,23 @@ hipError_t launch_chol_inv(const double* S, int n, double* L, double* LT, double
                            hipStream_t s);
 hipError_t launch_chol_solve(const double* L, const double* LT, int n, const double* Rhs, int64_t I,
                              double* G, int accumulate, const int* status, hipStream_t s);
+// Normal-equation apply: G = M S^{-1} plus `refine` refinement steps
+// (R = M - G S, G += R S^{-1}), 8 rows of M per workgroup; a non-finite G
+// latches ST_NONFINITE.  Skipped when the status word is set.
+hipError_t launch_ne_apply(const double* M, int64_t I, int n, const double* S, const double* Sinv, int refine,
+                           double* G, int* status, hipStream_t s);
+// Commit G into the core layout (status word clear) and write the core's Gram.
+hipError_t launch_commit_gram(const double* G, int64_t I, int Ra, int Rb, double* core, double* E, int* status,
+                              hipStream_t s);
 hipError_t launch_commit_core(const double* G, int64_t I, int Ra, int Rb, double* core, int* status, hipStream_t s,
                               bool checked = false);
 hipError_t launch_sumsq(const void* X, int xdt, int64_t n, double* partials, int nblk, double* out, hipStream_t s);
 hipError_t launch_absmax(const void* X, int xdt, int64_t n, float* partials, int nblk, float* out, hipStream_t s);
 hipError_t launch_to_bf16(const void* X, int xdt, int64_t n, void* out, hipStream_t s);
+// Transposed low-precision shadow (BF16, or FP8 with the scale of absmax) of
+// X seen as an M x K matrix: out[k + K*r] = X[r + M*k].
+hipError_t launch_to_lowp_t(const void* X, int xdt, int64_t M, int64_t K, const float* absmax, int prec, void* out,
+                            hipStream_t s);
 hipError_t launch_to_fp8(const void* X, int xdt, int64_t n, const float* absmax, float* scale_out, void* out,
                          hipStream_t s);
 hipError_t launch_fit(const void* X, int xdt, int64_t I, int64_t K, const double* G0, const double* F1,

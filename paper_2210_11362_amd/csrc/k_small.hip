@@ -63,25 +63,26 @@ __global__ void identity_table_kernel(int R, double* out) {
 // Gram of a core (Alg. 2 Gram step, Prop. 3.1): E = G_(2)^T G_(2) with
 // G_(2)[i, a + Rl*b] = core[a + Rl*(i + I*b)].  One wave per 16x16 block.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void gram_kernel(const double* core, int Rl, int64_t I, int Rr, double* E) {
-  // one 16x16 block of E per workgroup; the 4 waves split the i range
-  __shared__ double red[4][64][4];
+// Block (blk % nb, blk / nb) of E, read from the core layout or, with
+// from_g, from the solve output G[i + I*(a + Rl*b)] (the same matrix G_(2)).
+__device__ __forceinline__ void gram_block(const double* src, bool from_g, int Rl, int64_t I, int Rr, double* E,
+                                           int blk, double (*red)[64][4]) {
   const int RR = Rl * Rr;
   const int nb = (RR + 15) / 16;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int blk = blockIdx.x;
   const int bp = blk % nb, bq = blk / nb;
   const int p = bp * 16 + (lane & 15), q = bq * 16 + (lane & 15);
   const bool pok = p < RR, qok = q < RR;
-  const int64_t offp = pok ? (p % Rl) + (int64_t)Rl * I * (p / Rl) : 0;
-  const int64_t offq = qok ? (q % Rl) + (int64_t)Rl * I * (q / Rl) : 0;
+  const int64_t si = from_g ? 1 : Rl;
+  const int64_t offp = !pok ? 0 : from_g ? I * p : (p % Rl) + (int64_t)Rl * I * (p / Rl);
+  const int64_t offq = !qok ? 0 : from_g ? I * q : (q % Rl) + (int64_t)Rl * I * (q / Rl);
   const int64_t nst = (I + 3) / 4;
   const int64_t s0 = nst * wave / 4, s1 = nst * (wave + 1) / 4;
   f64x4 acc = {0, 0, 0, 0};
   for (int64_t st = s0; st < s1; ++st) {
     const int64_t i = st * 4 + (lane >> 4);
-    const double av = (pok && i < I) ? core[offp + Rl * i] : 0.0;
-    const double bv = (qok && i < I) ? core[offq + Rl * i] : 0.0;
+    const double av = (pok && i < I) ? src[offp + si * i] : 0.0;
+    const double bv = (qok && i < I) ? src[offq + si * i] : 0.0;
     mma64(acc, av, bv);
   }
   for (int v = 0; v < 4; ++v) red[wave][lane][v] = acc[v];
@@ -93,6 +94,164 @@ __global__ __launch_bounds__(256) void gram_kernel(const double* core, int Rl, i
       if (row < RR && col < RR) E[row + (int64_t)RR * col] = x;
     }
   }
+}
+
+__global__ __launch_bounds__(256) void gram_kernel(const double* core, int Rl, int64_t I, int Rr, double* E) {
+  // one 16x16 block of E per workgroup; the 4 waves split the i range
+  __shared__ double red[4][64][4];
+  gram_block(core, false, Rl, I, Rr, E, blockIdx.x, red);
+}
+
+// Commit of a solved core and its Gram in one launch: the first nb^2
+// workgroups form E (from G when the status word is clear, else from the
+// unchanged core), the rest copy G into the core layout when the status word
+// is clear.
+__global__ __launch_bounds__(256) void commit_gram_kernel(const double* G, int64_t I, int Ra, int Rb, double* core,
+                                                          double* E, const int* status) {
+  __shared__ double red[4][64][4];
+  const int nb = (Ra * Rb + 15) / 16;
+  const bool ok = *status == 0;
+  if ((int)blockIdx.x < nb * nb) {
+    gram_block(ok ? G : core, ok, Ra, I, Rb, E, blockIdx.x, red);
+    return;
+  }
+  if (!ok) return;
+  const int64_t e = (int64_t)(blockIdx.x - nb * nb) * 256 + threadIdx.x;
+  if (e >= I * Ra * Rb) return;
+  const int a = (int)(e % Ra);
+  const int64_t i = (e / Ra) % I;
+  const int b = (int)(e / ((int64_t)Ra * I));
+  core[e] = G[i + I * (a + (int64_t)Ra * b)];
+}
+
+// ---------------------------------------------------------------------------
+// Normal-equation apply with iterative refinement (Alg. 2 solve step): for a
+// block of 8 rows of M, G = M S^{-1}, then per refinement step R = M - G S and
+// G += R S^{-1}; the row blocks stay in LDS (k-major) between the products.
+// RG row groups of 8/RG rows split the 256 threads so small n keeps every
+// thread busy.  With STAGE the n x n operand of each product is first copied
+// to LDS in one coalesced pass (leading dimension n|1 against bank
+// conflicts, stored transposed so a wave reads consecutive words), the next
+// product's operand being fetched into registers meanwhile; otherwise it is
+// read from global memory.  The k loop keeps 8 operand pairs in flight.
+// A non-finite entry of the final G latches ST_NONFINITE.
+// ---------------------------------------------------------------------------
+constexpr int NE_APPLY_STAGE_MAX = 112;   // largest n whose operand is staged in LDS
+
+template <int RG, bool STAGE>
+__global__ __launch_bounds__(256) void ne_apply_kernel(const double* __restrict__ M, int64_t I, int n,
+                                                       const double* __restrict__ S,
+                                                       const double* __restrict__ Sinv, int refine,
+                                                       double* __restrict__ G, int* status) {
+  constexpr int RB = 8, RPT = RB / RG, CT = 256 / RG, KB = 8;
+  constexpr int NPF = STAGE ? (NE_APPLY_STAGE_MAX * NE_APPLY_STAGE_MAX / 2 + 255) / 256 : 1;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* Ms = reinterpret_cast<double*>(smem_raw);
+  double* Gs = Ms + RB * n;
+  double* Rs = Gs + RB * n;
+  double* Bs = Rs + RB * n;   // STAGE only: B transposed, Bs[j + ldb*k] = B[k + n*j]
+  const int ldb = n | 1;
+  if (*status != 0) return;
+  const int tid = threadIdx.x, grp = tid / CT, jt = tid % CT;
+  const int64_t i0 = (int64_t)blockIdx.x * RB;
+  const int rows = (int)min((int64_t)RB, I - i0);
+  // STAGE: the n x n operand of the next product travels in registers (pairs
+  // (e, e+1) of B, 16-byte loads) while the current product computes
+  const int nn = n * n, npair = nn / 2;
+  double2 pf[NPF];
+  auto prefetch = [&](const double* B) {
+#pragma unroll
+    for (int u = 0; u < NPF; ++u) {
+      const int q = tid + 256 * u;
+      pf[u] = q < npair ? reinterpret_cast<const double2*>(B)[q] : double2{0.0, 0.0};
+    }
+  };
+  auto stage = [&](const double* B) {   // (k, j) of element e = 2q walks by 512
+    const int dk = 512 % n, dj = 512 / n;
+    int k = (2 * tid) % n, j = (2 * tid) / n;
+#pragma unroll
+    for (int u = 0; u < NPF; ++u) {
+      if (tid + 256 * u < npair) {
+        int k1 = k + 1, j1 = j;
+        if (k1 == n) { k1 = 0; ++j1; }
+        Bs[j + ldb * k] = pf[u].x;
+        Bs[j1 + ldb * k1] = pf[u].y;
+      }
+      k += dk;
+      j += dj;
+      if (k >= n) { k -= n; ++j; }
+    }
+    if ((nn & 1) && tid == 0) Bs[(n - 1) + ldb * (n - 1)] = B[nn - 1];
+  };
+  if (STAGE) prefetch(Sinv);
+  for (int e0 = 0; e0 < RB * n; e0 += 4 * 256) {   // four loads in flight per thread
+    double t[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + tid + 256 * u, r = e % RB, k = e / RB;
+      t[u] = (e < RB * n && r < rows) ? M[(i0 + r) + I * k] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (e0 + tid + 256 * u < RB * n) Ms[e0 + tid + 256 * u] = t[u];
+  }
+  // Phase 0: G = M S^{-1}; odd phases: R = M - G S; even phases > 0: G += R S^{-1}.
+  const int nph = 1 + 2 * refine;
+  for (int ph = 0; ph < nph; ++ph) {
+    const bool res = ph & 1;
+    const double* A = ph == 0 ? Ms : res ? Gs : Rs;
+    const double* B = res ? S : Sinv;
+    const double* Cin = ph == 0 ? nullptr : res ? Ms : Gs;
+    const double alpha = res ? -1.0 : 1.0;
+    double* Out = res ? Rs : Gs;
+    if (STAGE) {
+      __syncthreads();   // the previous phase's reads of Bs are done
+      stage(B);
+      if (ph + 1 < nph) prefetch(res ? Sinv : S);
+    }
+    __syncthreads();
+    for (int j = jt; j < n; j += CT) {
+      double acc[RPT];
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) acc[r] = 0.0;
+      const double* ak = A + grp * RPT;
+      int k = 0;
+      for (; k + KB <= n; k += KB) {   // KB operand pairs in flight, then the FMAs in k order
+        double bv[KB], av[KB][RPT];
+#pragma unroll
+        for (int u = 0; u < KB; ++u) bv[u] = STAGE ? Bs[j + ldb * (k + u)] : B[(k + u) + (int64_t)n * j];
+#pragma unroll
+        for (int u = 0; u < KB; ++u)
+#pragma unroll
+          for (int r = 0; r < RPT; ++r) av[u][r] = ak[(k + u) * RB + r];
+#pragma unroll
+        for (int u = 0; u < KB; ++u)
+#pragma unroll
+          for (int r = 0; r < RPT; ++r) acc[r] = fma(av[u][r], bv[u], acc[r]);
+      }
+      for (; k < n; ++k) {
+        const double b = STAGE ? Bs[j + ldb * k] : B[k + (int64_t)n * j];
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) acc[r] = fma(ak[k * RB + r], b, acc[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+        const int o = j * RB + grp * RPT + r;
+        Out[o] = (Cin ? Cin[o] : 0.0) + alpha * acc[r];
+      }
+    }
+    __syncthreads();
+  }
+  bool bad = false;
+  for (int e = tid; e < RB * n; e += 256) {
+    const int r = e % RB, j = e / RB;
+    if (r < rows) {
+      const double v = Gs[e];
+      bad = bad || !isfinite(v);
+      G[(i0 + r) + I * j] = v;
+    }
+  }
+  if (bad) atomicOr(status, ST_NONFINITE);
 }
 
 // ---------------------------------------------------------------------------
@@ -450,6 +609,38 @@ __global__ void to_fp8_kernel(const T* X, int64_t n, const float* absmax, float*
     out[e] = (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32((float)X[e] * s, 0.0f, 0, false) & 0xff);
 }
 
+// Low-precision shadow of X seen as an M x K matrix (X[r + M*k]) stored
+// transposed (out[k + K*r]), so that a contraction over the slowest modes
+// reads contiguous rows.  64 x 64 tiles through LDS, 1-D grid of tiles; the
+// values are rounded exactly as in the plain shadows (FP8: same per-tensor
+// scale from the same absmax).
+template <typename T, bool FP8>
+__global__ __launch_bounds__(256) void to_lowp_t_kernel(const T* X, int64_t M, int64_t K, const float* absmax,
+                                                        void* out) {
+  __shared__ float tile[64][65];
+  const int64_t ntr = (M + 63) / 64;
+  const int64_t r0 = ((int64_t)blockIdx.x % ntr) * 64, k0 = ((int64_t)blockIdx.x / ntr) * 64;
+  float s = 1.0f;
+  if (FP8) {
+    const float am = *absmax;
+    s = am > 0.0f ? 448.0f / am : 1.0f;
+  }
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int kk = ty; kk < 64; kk += 4) {
+    const int64_t r = r0 + tx, k = k0 + kk;
+    tile[kk][tx] = (r < M && k < K) ? (float)X[r + M * k] : 0.0f;
+  }
+  __syncthreads();
+  for (int rr = ty; rr < 64; rr += 4) {
+    const int64_t r = r0 + rr, k = k0 + tx;
+    if (r < M && k < K) {
+      const float v = tile[tx][rr];
+      if (FP8) static_cast<uint8_t*>(out)[k + K * r] = (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(v * s, 0.0f, 0, false) & 0xff);
+      else static_cast<__bf16*>(out)[k + K * r] = (__bf16)v;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Explicit fit (Sec. 4 error formula): sum over X of (X - Xhat)^2 with
 // Xhat_(1)[i, k] = sum_c G_1(2)[i, c] B[k][c] and B[k] = G^{!=1}(k) formed
@@ -672,5 +863,48 @@ hipError_t launch_fit(const void* X, int xdt, int64_t I, int64_t K, const double
     hipLaunchKernelGGL(fit_kernel<float>, dim3(nblk), dim3(256), lds, s, (const float*)X, I, K, G0, F1, F2, d1, m1,
                        d2, m2, Rb, Rmid, Ra, kt, partials);
   hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(64), 0, s, partials, nblk, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_ne_apply(const double* M, int64_t I, int n, const double* S, const double* Sinv, int refine,
+                           double* G, int* status, hipStream_t s) {
+  const size_t rows_lds = (size_t)3 * 8 * n * sizeof(double);
+  const size_t staged = rows_lds + (size_t)(n | 1) * n * sizeof(double);
+  const bool stage = n <= NE_APPLY_STAGE_MAX;
+  const size_t lds = stage ? staged : rows_lds;
+  const dim3 grid((unsigned)cdiv(I, 8));
+  const void* k;
+  if (stage) k = n <= 64 ? (const void*)ne_apply_kernel<4, true> : (const void*)ne_apply_kernel<2, true>;
+  else k = n <= 128 ? (const void*)ne_apply_kernel<2, false> : (const void*)ne_apply_kernel<1, false>;
+  if (lds > 64 * 1024) hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  void* args[] = {(void*)&M, (void*)&I, (void*)&n, (void*)&S, (void*)&Sinv, (void*)&refine, (void*)&G, (void*)&status};
+  return hipLaunchKernel(k, grid, dim3(256), args, lds, s);
+}
+
+hipError_t launch_commit_gram(const double* G, int64_t I, int Ra, int Rb, double* core, double* E, int* status,
+                              hipStream_t s) {
+  const int nb = (Ra * Rb + 15) / 16;
+  const int64_t ncommit = cdiv(I * Ra * Rb, 256);
+  hipLaunchKernelGGL(commit_gram_kernel, dim3((unsigned)(nb * nb + ncommit)), dim3(256), 0, s, G, I, Ra, Rb, core, E,
+                     (const int*)status);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_lowp_t(const void* X, int xdt, int64_t M, int64_t K, const float* absmax, int prec, void* out,
+                            hipStream_t s) {
+  const int64_t tiles = cdiv(M, 64) * cdiv(K, 64);
+  if (tiles > 0x7fffffff) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)tiles);
+  if (prec == TR_FP8) {
+    if (xdt == TR_F64)
+      hipLaunchKernelGGL((to_lowp_t_kernel<double, true>), grid, dim3(256), 0, s, (const double*)X, M, K, absmax, out);
+    else
+      hipLaunchKernelGGL((to_lowp_t_kernel<float, true>), grid, dim3(256), 0, s, (const float*)X, M, K, absmax, out);
+  } else {
+    if (xdt == TR_F64)
+      hipLaunchKernelGGL((to_lowp_t_kernel<double, false>), grid, dim3(256), 0, s, (const double*)X, M, K, absmax, out);
+    else
+      hipLaunchKernelGGL((to_lowp_t_kernel<float, false>), grid, dim3(256), 0, s, (const float*)X, M, K, absmax, out);
+  }
   return hipGetLastError();
 }

@@ -235,6 +235,125 @@ __global__ __launch_bounds__(256) void trsm_rhs_kernel(const double* Lg, const d
   }
 }
 
+// Reciprocal of a positive FP64 pivot: hardware estimate plus two Newton steps
+// (within an ulp or two of 1/d; the solve that uses the inverse is refined).
+__device__ __forceinline__ double pivot_recip(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return fma(r, fma(-d, r, 1.0), r);
+}
+
+// S^{-1} of a symmetric positive definite S (n <= 16 * NBT) by the symmetric
+// sweep operator: sweeping pivot k of A sets
+//   A_ij -= A_ik A_kj / A_kk  (i, j != k),  A_ik = A_ki = A_ik / A_kk,  A_kk = -1 / A_kk,
+// and sweeping every pivot of S leaves -S^{-1}.  For SPD S every pivot is a
+// Schur-complement diagonal, hence positive; a pivot that is not (S not
+// positive definite in working precision) latches ST_SINGULAR.
+//
+// One workgroup of 16 x 16 threads holds the matrix in registers: thread
+// (ti, tj) owns A(16r + ti, 16c + tj) for the lower block triangle c <= r
+// (the upper halves of the diagonal blocks are scratch, never read).  Per
+// pivot the current column k is exchanged through a double-buffered LDS
+// vector, so each pivot costs one barrier.
+template <int NBT>
+__global__ __launch_bounds__(256) void spd_sweep_inv_kernel(const double* __restrict__ S, int n,
+                                                            double* __restrict__ Sinv, int* status) {
+  __shared__ double col[2][16 * NBT];
+  const int tid = threadIdx.x, ti = tid & 15, tj = tid >> 4;
+  if (*status != 0) return;
+  double a[NBT][NBT];
+#pragma unroll
+  for (int r = 0; r < NBT; ++r)
+#pragma unroll
+    for (int c = 0; c <= r; ++c) {
+      const int i = 16 * r + ti, j = 16 * c + tj;
+      a[r][c] = (i < n && j < n) ? S[i + (int64_t)n * j] : (i == j ? 1.0 : 0.0);
+    }
+  // column 0 (canonical entries (i, 0), i >= 0, owned by tj == 0)
+  if (tj == 0) {
+#pragma unroll
+    for (int r = 0; r < NBT; ++r) col[0][16 * r + ti] = a[r][0];
+  }
+  int buf = 0;
+#pragma unroll
+  for (int rk = 0; rk < NBT; ++rk) {
+    const int tend = min(16, n - 16 * rk);
+    for (int tk = 0; tk < tend; ++tk) {
+      const int k = 16 * rk + tk;
+      __syncthreads();
+      const double* cb = col[buf];
+      const double d = cb[k];
+      if (!(d > 0.0) || !isfinite(d)) {   // same value in every thread: uniform exit
+        if (tid == 0) atomicOr(status, ST_SINGULAR);
+        return;
+      }
+      const double p = pivot_recip(d);
+      double x[NBT], v[NBT];
+#pragma unroll
+      for (int r = 0; r < NBT; ++r) {
+        x[r] = cb[16 * r + ti];
+        v[r] = cb[16 * r + tj] * p;
+      }
+#pragma unroll
+      for (int r = 0; r < NBT; ++r)
+#pragma unroll
+        for (int c = 0; c <= r; ++c) a[r][c] = fma(-x[r], v[c], a[r][c]);
+      // column k, rows i >= k: A_ik / A_kk, and -1 / A_kk on the diagonal
+      if (tj == tk) {
+#pragma unroll
+        for (int r = rk; r < NBT; ++r) a[r][rk] = (16 * r + ti == k) ? -p : x[r] * p;
+      }
+      // row k, columns j < k: A_jk / A_kk
+      if (ti == tk) {
+#pragma unroll
+        for (int c = 0; c <= rk; ++c)
+          if (16 * c + tj < k) a[rk][c] = v[c];
+      }
+      // publish column k + 1 into the other buffer: entries (i, k+1) with
+      // i >= k+1 from its column owners, (k+1, j) with j < k+1 from its row owners
+      const int k1 = k + 1;
+      double* cn = col[buf ^ 1];
+      if (k1 < n) {
+        if (tk + 1 < 16) {
+          const int t1 = tk + 1;
+          if (tj == t1) {
+#pragma unroll
+            for (int r = rk; r < NBT; ++r)
+              if (16 * r + ti >= k1) cn[16 * r + ti] = a[r][rk];
+          }
+          if (ti == t1) {
+#pragma unroll
+            for (int c = 0; c <= rk; ++c)
+              if (16 * c + tj < k1) cn[16 * c + tj] = a[rk][c];
+          }
+        } else if (rk + 1 < NBT) {
+          if (tj == 0) {
+#pragma unroll
+            for (int r = rk + 1; r < NBT; ++r) cn[16 * r + ti] = a[r][rk + 1];
+          }
+          if (ti == 0) {
+#pragma unroll
+            for (int c = 0; c <= rk; ++c) cn[16 * c + tj] = a[rk + 1][c];
+          }
+        }
+      }
+      buf ^= 1;
+    }
+  }
+  // -A = S^{-1}: write both triangles from the canonical entries
+#pragma unroll
+  for (int r = 0; r < NBT; ++r)
+#pragma unroll
+    for (int c = 0; c <= r; ++c) {
+      const int i = 16 * r + ti, j = 16 * c + tj;
+      if (i < n && j <= i) {
+        const double v = -a[r][c];
+        Sinv[i + (int64_t)n * j] = v;
+        Sinv[j + (int64_t)n * i] = v;
+      }
+    }
+}
+
 }  // namespace
 
 // LDS-resident versions for n <= 128; larger systems use the global-memory
@@ -256,5 +375,20 @@ hipError_t launch_trsm_rhs(const double* L, const double* rdiag, int n, const do
   if (lds > 64 * 1024) hipFuncSetAttribute((const void*)trsm_rhs_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(trsm_rhs_kernel, dim3((unsigned)((I + NRHS - 1) / NRHS)), dim3(256), lds, s, L, rdiag, n, Rhs,
                      I, G, accumulate, status, mode);
+  return hipGetLastError();
+}
+
+bool spd_inverse_fits(int n) { return n >= 1 && n <= 128; }
+
+hipError_t launch_spd_inverse(const double* S, int n, double* Sinv, int* status, hipStream_t s) {
+  const int nbt = (n + 15) / 16;
+  switch (nbt) {
+#define SPD_INV_CASE(B) \
+  case B: hipLaunchKernelGGL(spd_sweep_inv_kernel<B>, dim3(1), dim3(256), 0, s, S, n, Sinv, status); break;
+    SPD_INV_CASE(1) SPD_INV_CASE(2) SPD_INV_CASE(3) SPD_INV_CASE(4)
+    SPD_INV_CASE(5) SPD_INV_CASE(6) SPD_INV_CASE(7) SPD_INV_CASE(8)
+#undef SPD_INV_CASE
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }

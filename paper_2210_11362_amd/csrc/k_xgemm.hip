@@ -17,6 +17,8 @@
 
 namespace {
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
 template <int P> struct PT;
 template <> struct PT<TR_F64>  { using op_t = double;  using acc_t = f64x4; static constexpr int KS = 4;  };
 template <> struct PT<TR_F32>  { using op_t = float;   using acc_t = f32x4; static constexpr int KS = 4;  };
@@ -71,7 +73,7 @@ constexpr int NTHR = 256;
 // Elements per 16-byte vector of the operand type.
 template <int P> struct Vec { static constexpr int n = 16 / sizeof(typename PT<P>::op_t); };
 
-template <int P, typename Tin, bool NN, int MT, int KT, int NBMAX>
+template <int P, typename Tin, bool NN, bool VEC, int MT, int KT, int NBMAX>
 __global__ __launch_bounds__(NTHR) void xgemm_kernel(XgArgs g) {
   using op_t = typename PT<P>::op_t;
   using acc_t = typename PT<P>::acc_t;
@@ -119,60 +121,107 @@ __global__ __launch_bounds__(NTHR) void xgemm_kernel(XgArgs g) {
       for (int v = 0; v < 4; ++v) acc[r][c][v] = 0;
 
   // per-thread coordinates of its packed A vectors: (row, kvec)
-  op_t areg[AV][V];
+  op_t areg[VEC ? 1 : AV][V];
+  // VEC (fastest-modes group, A[r,k] = X[k + K*r]): one 16-byte load per
+  // packed vector.
+  u32x4 vreg[VEC ? AV : 1];
   auto load_a = [&](int64_t k0) {
+    if constexpr (VEC) {
 #pragma unroll
-    for (int q = 0; q < AV; ++q) {
-      const int e = tid + q * NTHR;
-      int row, kv;
-      if (NN) { row = e % MT; kv = e / MT; }   // consecutive threads walk rows (contiguous in X)
-      else { kv = e % KV; row = e / KV; }      // consecutive threads walk k (contiguous in X)
-      const int64_t r = r0 + row;
-      const int64_t kb = k0 + kv * V;
-      if (!NN && sizeof(Tin) == sizeof(op_t) && g.vec_ok && r < g.M && kb + V <= kend) {
-        // K-contiguous rows with 16-byte aligned starts: one vector load
-        const uint4 w = *reinterpret_cast<const uint4*>(X + kb + g.K * r);
-        *reinterpret_cast<uint4*>(&areg[q][0]) = w;
-        continue;
+      for (int q = 0; q < AV; ++q) {
+        const int e = tid + q * NTHR, kv = e % KV, row = e / KV;
+        const int64_t r = r0 + row, kb = k0 + kv * V;
+        vreg[q] = (r < g.M && kb < kend) ? *reinterpret_cast<const u32x4*>(X + kb + g.K * r) : u32x4{0, 0, 0, 0};
       }
+    } else {
 #pragma unroll
-      for (int j = 0; j < V; ++j) {
-        const int64_t k = kb + j;
-        op_t v = x_to_op<P, Tin>((Tin)0);
-        if (r < g.M && k < kend) v = x_to_op<P, Tin>(NN ? X[r + g.M * k] : X[k + g.K * r]);
-        areg[q][j] = v;
+      for (int q = 0; q < AV; ++q) {
+        const int e = tid + q * NTHR;
+        int row, kv;
+        if (NN) { row = e % MT; kv = e / MT; }   // consecutive threads walk rows (contiguous in X)
+        else { kv = e % KV; row = e / KV; }      // consecutive threads walk k (contiguous in X)
+        const int64_t r = r0 + row;
+        const int64_t kb = k0 + kv * V;
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+          const int64_t k = kb + j;
+          op_t v = x_to_op<P, Tin>((Tin)0);
+          if (r < g.M && k < kend) v = x_to_op<P, Tin>(NN ? X[r + g.M * k] : X[k + g.K * r]);
+          areg[q][j] = v;
+        }
       }
     }
   };
   auto store_a = [&]() {
+    if constexpr (VEC) {
 #pragma unroll
-    for (int q = 0; q < AV; ++q) {
-      const int e = tid + q * NTHR;
-      int row, kv;
-      if (NN) { row = e % MT; kv = e / MT; }
-      else { kv = e % KV; row = e / KV; }
-      op_t* dst = As + row * ST + kv * V;
+      for (int q = 0; q < AV; ++q) {
+        const int e = tid + q * NTHR, kv = e % KV, row = e / KV;
+        *reinterpret_cast<u32x4*>(As + row * ST + kv * V) = vreg[q];
+      }
+    } else {
 #pragma unroll
-      for (int j = 0; j < V; ++j) dst[j] = areg[q][j];
+      for (int q = 0; q < AV; ++q) {
+        const int e = tid + q * NTHR;
+        int row, kv;
+        if (NN) { row = e % MT; kv = e / MT; }
+        else { kv = e % KV; row = e / KV; }
+        op_t* dst = As + row * ST + kv * V;
+#pragma unroll
+        for (int j = 0; j < V; ++j) dst[j] = areg[q][j];
+      }
     }
   };
-  // B tile: NT rows of KT contiguous elements, zero-padded in the table itself
-  auto copy_b = [&](int64_t k0) {
-    const int nvec = NT * KV;
-    for (int e = tid; e < nvec; e += NTHR) {
-      const int row = e / KV, kv = e % KV;
-      const uint4 v = *reinterpret_cast<const uint4*>(Bt + (size_t)row * g.ldb + k0 + kv * V);
-      *reinterpret_cast<uint4*>(Bs + row * ST + kv * V) = v;
+  // B tile: NT rows of KT contiguous elements, zero-padded in the table
+  // itself.  For 8/16-bit operands it is fetched into registers one tile
+  // ahead of its LDS store; wider operands copy it when it is needed.
+  constexpr int BQ = (NBMAX * 16 * KV + NTHR - 1) / NTHR;
+  constexpr bool BPF = BQ <= 4;
+  u32x4 breg[BPF ? BQ : 1];
+  auto load_b = [&](int64_t k0) {
+    if constexpr (BPF) {
+#pragma unroll
+      for (int q = 0; q < BQ; ++q) {
+        const int e = tid + q * NTHR;
+        if (e < NT * KV) {
+          const int row = e / KV, kv = e % KV;
+          breg[q] = *reinterpret_cast<const u32x4*>(Bt + (size_t)row * g.ldb + k0 + kv * V);
+        }
+      }
+    }
+  };
+  auto store_b = [&](int64_t k0) {
+    if constexpr (BPF) {
+#pragma unroll
+      for (int q = 0; q < BQ; ++q) {
+        const int e = tid + q * NTHR;
+        if (e < NT * KV) {
+          const int row = e / KV, kv = e % KV;
+          *reinterpret_cast<u32x4*>(Bs + row * ST + kv * V) = breg[q];
+        }
+      }
+    } else {
+      for (int e = tid; e < NT * KV; e += NTHR) {
+        const int row = e / KV, kv = e % KV;
+        *reinterpret_cast<u32x4*>(Bs + row * ST + kv * V) =
+            *reinterpret_cast<const u32x4*>(Bt + (size_t)row * g.ldb + k0 + kv * V);
+      }
     }
   };
 
-  if (kbeg < kend) load_a(kbeg);
+  if (kbeg < kend) {
+    load_a(kbeg);
+    load_b(kbeg);
+  }
   for (int64_t k0 = kbeg; k0 < kend; k0 += KT) {
     __syncthreads();
     store_a();
-    copy_b(k0);
+    store_b(k0);
     __syncthreads();
-    if (k0 + KT < kend) load_a(k0 + KT);     // next tile's global loads overlap the MFMAs below
+    if (k0 + KT < kend) {                    // next tile's global loads overlap the MFMAs below
+      load_a(k0 + KT);
+      load_b(k0 + KT);
+    }
 #pragma unroll
     for (int kb = 0; kb < KT; kb += KS) {
       frag_t af[MBW];
@@ -336,6 +385,55 @@ __global__ __launch_bounds__(256) void absorb_block_kernel(AbsorbArgs a) {
   if (tid == 0) absorb_store(a, l, h, u2, c2, red[0]);
 }
 
+// Narrow fast extents (lo < 32): one workgroup per (l, h, p) forms all Rf
+// outputs f, so every Y element is read once; the (i, x) terms are walked
+// with i fastest (contiguous in Y), each thread keeping its Rf partial sums
+// in registers, then a fixed-order wave and workgroup reduction.
+template <int B, bool SIDE0>
+__global__ __launch_bounds__(256) void absorb_narrow_kernel(AbsorbArgs a) {
+  __shared__ double red[4][B];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int Rx = SIDE0 ? a.Ru : a.Rc, Rf = SIDE0 ? a.Rl : a.Rr, Rp = SIDE0 ? a.Rc : a.Ru;
+  const int64_t e = blockIdx.x;
+  const int64_t l = e % a.lo, h = (e / a.lo) % a.hi;
+  const int p = (int)(e / (a.lo * a.hi));
+  const int64_t T = a.I * Rx;
+  const int64_t sB = a.lo * a.I * a.hi;
+  double acc[B];
+#pragma unroll
+  for (int f = 0; f < B; ++f) acc[f] = 0.0;
+  int64_t i = tid % a.I;
+  int x = (int)(tid / a.I);
+  const int64_t di = 256 % a.I;
+  const int dx = (int)(256 / a.I);
+  for (int64_t t = tid; t < T; t += 256) {
+    const int bond = SIDE0 ? x + a.Ru * p : p + a.Ru * x;
+    const double y = a.Y[l + a.lo * (i + a.I * h) + sB * bond];
+#pragma unroll
+    for (int f = 0; f < B; ++f)
+      if (f < Rf) {
+        const double cv = SIDE0 ? a.core[f + (int64_t)a.Rl * (i + a.I * x)] : a.core[x + (int64_t)a.Rc * (i + a.I * f)];
+        acc[f] = fma(y, cv, acc[f]);
+      }
+    i += di;
+    x += dx;
+    if (i >= a.I) { i -= a.I; ++x; }
+  }
+#pragma unroll
+  for (int f = 0; f < B; ++f) {
+    double v = acc[f];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0) red[wave][f] = v;
+  }
+  __syncthreads();
+  if (tid < Rf) {
+    const double v = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+    absorb_store(a, l, h, SIDE0 ? tid : p, SIDE0 ? p : tid, v);
+  }
+  (void)Rp;
+}
+
 // Single-read absorption.  With x the contracted bond index, p the passive
 // one and f the free index of the core (side 0: x = u, p = c, f = the core's
 // left index; side 1: x = c, p = u, f = the core's right index), output
@@ -449,22 +547,31 @@ __global__ void bond_to_M_kernel(const double* Y, int64_t In, int Ru, int Rc, do
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-template <int P, typename Tin, bool NN, int MT, int KT>
+template <int P, typename Tin, bool NN, bool VEC, int MT, int KT>
 hipError_t launch_g(const XgArgs& g, hipStream_t s) {
   using op_t = typename PT<P>::op_t;
   const size_t lds = (size_t)(MT + g.NT) * (KT + Pad<P>::v) * sizeof(op_t);
   const dim3 grid = g.xcd_map ? dim3((unsigned)(g.n_mt * g.n_nt * g.nsplit)) : dim3(g.n_mt * g.n_nt, g.nsplit);
-  auto k = xgemm_kernel<P, Tin, NN, MT, KT, 8>;
+  auto k = xgemm_kernel<P, Tin, NN, VEC, MT, KT, 8>;
   if (lds > 64 * 1024) hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(k, grid, dim3(NTHR), lds, s, g);
   return hipGetLastError();
 }
 
+// Vector loads of A: rows of the fastest-modes group when the operand type is
+// the stored type and the rows start 16-byte aligned (vec_ok).
+template <int P, typename Tin, bool NN, int MT, int KT>
+hipError_t launch_v(const XgArgs& g, hipStream_t s) {
+  constexpr bool can_vec = !NN && sizeof(Tin) == sizeof(typename PT<P>::op_t);
+  if (can_vec && g.vec_ok) return launch_g<P, Tin, NN, can_vec, MT, KT>(g, s);
+  return launch_g<P, Tin, NN, false, MT, KT>(g, s);
+}
+
 template <int P, typename Tin>
 hipError_t launch_p(const XgArgs& g, hipStream_t s) {
   constexpr int KT = (P == TR_F64) ? 32 : 64;
-  if (g.MT == 64) return g.nn ? launch_g<P, Tin, true, 64, KT>(g, s) : launch_g<P, Tin, false, 64, KT>(g, s);
-  return g.nn ? launch_g<P, Tin, true, 128, KT>(g, s) : launch_g<P, Tin, false, 128, KT>(g, s);
+  if (g.MT == 64) return g.nn ? launch_v<P, Tin, true, 64, KT>(g, s) : launch_v<P, Tin, false, 64, KT>(g, s);
+  return g.nn ? launch_v<P, Tin, true, 128, KT>(g, s) : launch_v<P, Tin, false, 128, KT>(g, s);
 }
 
 }  // namespace
@@ -559,6 +666,17 @@ hipError_t launch_absorb(const double* Y, int64_t lo, int64_t I, int64_t hi, int
   if (lo >= 32) {
     dim3 grid((unsigned)cdiv(lo, 64), (unsigned)hi, (unsigned)(Ru2 * Rc2));
     hipLaunchKernelGGL(absorb_lanes_kernel, grid, dim3(1024), 0, s, a);
+  } else if (Rf <= 24 && lo * hi * Rp <= 0x7fffffff) {
+    const dim3 grid((unsigned)(lo * hi * Rp));
+    if (side == 0) {
+      if (Rf <= 8) hipLaunchKernelGGL((absorb_narrow_kernel<8, true>), grid, dim3(256), 0, s, a);
+      else if (Rf <= 16) hipLaunchKernelGGL((absorb_narrow_kernel<16, true>), grid, dim3(256), 0, s, a);
+      else hipLaunchKernelGGL((absorb_narrow_kernel<24, true>), grid, dim3(256), 0, s, a);
+    } else {
+      if (Rf <= 8) hipLaunchKernelGGL((absorb_narrow_kernel<8, false>), grid, dim3(256), 0, s, a);
+      else if (Rf <= 16) hipLaunchKernelGGL((absorb_narrow_kernel<16, false>), grid, dim3(256), 0, s, a);
+      else hipLaunchKernelGGL((absorb_narrow_kernel<24, false>), grid, dim3(256), 0, s, a);
+    }
   } else {
     hipLaunchKernelGGL(absorb_block_kernel, dim3((unsigned)(lo * hi * Ru2 * Rc2)), dim3(256), 0, s, a);
   }

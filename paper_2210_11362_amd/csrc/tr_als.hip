@@ -74,7 +74,7 @@ struct tr_als_ctx {
   bool bf16_ready = false, fp8_ready = false;
   double *F1 = nullptr, *F2 = nullptr, *T0 = nullptr, *T1 = nullptr;
   double *M = nullptr, *S = nullptr, *W0 = nullptr, *W1 = nullptr, *Lf = nullptr, *LTf = nullptr, *cholw = nullptr;
-  double *Gn = nullptr, *Res = nullptr, *G0u = nullptr, *LinvT = nullptr, *Tsol = nullptr;
+  double *Gn = nullptr, *G0u = nullptr, *LinvT = nullptr, *Tsol = nullptr;
   double *Y0 = nullptr, *Y1 = nullptr;   // stage-2 intermediates
   void* Bt = nullptr;                    // stage-1 table, transposed, operand type
   size_t bt_bytes = 0;
@@ -87,6 +87,11 @@ struct tr_als_ctx {
   int* status = nullptr;
   void* xbf16 = nullptr;
   void* xfp8 = nullptr;
+  // transposed BF16/FP8 shadows for the two-stage modes that contract the
+  // slowest modes at split t_gK (0: none)
+  void* xbf16t = nullptr;
+  void* xfp8t = nullptr;
+  int64_t t_gK = 0;
   float fp8_scale = 1.0f;
   double xnorm2 = 0.0;
   int nred = 1024;
@@ -369,12 +374,14 @@ XsCfg xs_config(const tr_als_ctx* c, int m, int prec) {
   return x;
 }
 
-XgArgs xg_config(const tr_als_ctx* c, int m, int prec, const void* X, int esize) {
+XgArgs xg_config(const tr_als_ctx* c, int m, int prec, const void* X, int esize, bool transposed = false) {
   const Plan& p = c->plan[m];
   XgArgs g;
   g.X = X;
-  g.M = p.gM; g.K = p.gK; g.C = p.gC; g.nn = p.nn;
-  g.vec_ok = (!p.nn && ((p.gK * esize) % 16 == 0) && (((uintptr_t)X) % 16 == 0)) ? 1 : 0;
+  g.M = p.gM; g.K = p.gK; g.C = p.gC; g.nn = transposed ? 0 : p.nn;
+  // 16-byte aligned starts of the contiguous runs of A: rows (fastest-modes
+  // group) or columns (slowest-modes group, BF16 row-vector loads)
+  g.vec_ok = ((((g.nn ? p.gM : p.gK) * esize) % 16 == 0) && (((uintptr_t)X) % 16 == 0)) ? 1 : 0;
   // Row tile and split-K target (workgroups per launch); measured best on the
   // 100^4 rank-10 workload: 128 rows, ~640 workgroups for BF16 (HBM-bound),
   // ~1024 for FP32 (MFMA-bound).  TR_ALS_XG_MT / TR_ALS_XG_WGS override.
@@ -436,6 +443,13 @@ int ensure_shadow(tr_als_ctx* c, int prec) {
       if (rc) return rc;
     }
     HIPCHK(c, launch_to_bf16(c->X, c->xdt, c->numel, c->xbf16, s));
+    if (c->t_gK) {
+      if (!c->xbf16t) {
+        int rc = alloc(c, &c->xbf16t, (size_t)c->numel * 2);
+        if (rc) return rc;
+      }
+      HIPCHK(c, launch_to_lowp_t(c->X, c->xdt, c->numel / c->t_gK, c->t_gK, nullptr, TR_BF16, c->xbf16t, s));
+    }
     c->bf16_ready = true;
   }
   if (prec == TR_FP8 && !c->fp8_ready) {
@@ -446,6 +460,13 @@ int ensure_shadow(tr_als_ctx* c, int prec) {
     c->fp8_ready = true;
     HIPCHK(c, launch_absmax(c->X, c->xdt, c->numel, c->fpart, c->nred, c->fscal, s));
     HIPCHK(c, launch_to_fp8(c->X, c->xdt, c->numel, c->fscal, c->fscal + 1, c->xfp8, s));
+    if (c->t_gK) {
+      if (!c->xfp8t) {
+        int rc = alloc(c, &c->xfp8t, (size_t)c->numel);
+        if (rc) return rc;
+      }
+      HIPCHK(c, launch_to_lowp_t(c->X, c->xdt, c->numel / c->t_gK, c->t_gK, c->fscal, TR_FP8, c->xfp8t, s));
+    }
     HIPCHK(c, hipMemcpyAsync(&c->fp8_scale, c->fscal + 1, sizeof(float), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
   }
@@ -462,9 +483,12 @@ int compute_mttsp_two_stage(tr_als_ctx* c, int m, int prec, double* Mout, bool i
   if (rc) return rc;
   rc = ensure_shadow(c, prec);
   if (rc) return rc;
-  const void* X = prec == TR_BF16 ? c->xbf16 : prec == TR_FP8 ? c->xfp8 : c->X;
+  // the slowest-modes group reads the transposed shadow as a fastest-modes one
+  const bool use_t = p.nn && c->t_gK == p.gK && ((prec == TR_BF16 && c->xbf16t) || (prec == TR_FP8 && c->xfp8t));
+  const void* X = use_t ? (prec == TR_BF16 ? c->xbf16t : c->xfp8t)
+                        : prec == TR_BF16 ? c->xbf16 : prec == TR_FP8 ? c->xfp8 : c->X;
   const int esize = prec == TR_BF16 ? 2 : prec == TR_FP8 ? 1 : (c->xdt == TR_F64 ? 8 : 4);
-  XgArgs g = xg_config(c, m, prec, X, esize);
+  XgArgs g = xg_config(c, m, prec, X, esize, use_t);
   if (xg_partial_bytes(g, prec) > c->partial_bytes || xg_bt_bytes(g, prec) > c->bt_bytes)
     return fail(c, TR_EHIP, "internal: stage-1 buffers too small");
   double bscale = 1.0, out_scale = 1.0;
@@ -600,9 +624,8 @@ int update_mode_ne(tr_als_ctx* c, int m, int prec, int refine, bool in_sweep) {
   HIPCHK(c, hipStreamWaitEvent(s2, c->ev_fork, 0));
   int rc = compute_coef(c, m, c->S, s2);
   if (rc) return rc;
-  if (solve_in_lds(n)) {
-    HIPCHK(c, launch_chol_lds(c->S, n, c->Lf, c->LTf, c->rdiag, c->status, s2));
-    HIPCHK(c, launch_trsm_rhs(c->Lf, c->rdiag, n, nullptr, n, c->Sinv, 0, c->status, s2));
+  if (spd_inverse_fits(n)) {
+    HIPCHK(c, launch_spd_inverse(c->S, n, c->Sinv, c->status, s2));
   } else {
     HIPCHK(c, launch_chol(c->S, n, c->Lf, c->LTf, c->cholw, c->status, s2));
     HIPCHK(c, launch_chol_solve(c->Lf, c->LTf, n, nullptr, n, c->Sinv, 0, c->status, s2));
@@ -611,17 +634,10 @@ int update_mode_ne(tr_als_ctx* c, int m, int prec, int refine, bool in_sweep) {
   rc = compute_mttsp(c, m, prec, c->M, in_sweep);
   if (rc) return rc;
   HIPCHK(c, hipStreamWaitEvent(s, c->ev_join, 0));
-  MatView Mv{c->M, p.I, 0, 0, 0}, Si{c->Sinv, n, 0, 0, 0};
-  HIPCHK(c, launch_gemm64(p.I, n, n, 1.0, Mv, Si, 0.0, nullptr, 0, c->Gn, p.I, s, refine == 0 ? c->status : nullptr));
-  for (int r = 0; r < refine; ++r) {
-    MatView G{c->Gn, p.I, 0, 0, 0}, Sv{c->S, n, 0, 0, 0}, Rv{c->Res, p.I, 0, 0, 0};
-    HIPCHK(c, launch_gemm64(p.I, n, n, -1.0, G, Sv, 1.0, c->M, p.I, c->Res, p.I, s));
-    HIPCHK(c, launch_gemm64(p.I, n, n, 1.0, Rv, Si, 1.0, c->Gn, p.I, c->Gn, p.I, s,
-                            r + 1 == refine ? c->status : nullptr));
-  }
-  // the last solve GEMM latched any non-finite entry of the new core
-  HIPCHK(c, launch_commit_core(c->Gn, p.I, p.Ra, p.Rb, c->cores[m], c->status, s, true));
-  HIPCHK(c, launch_gram(c->cores[m], c->R[m], c->dims[m], c->R[m + 1], c->gram[m], s));
+  // G = M S^{-1} with refinement; the apply latches any non-finite entry, and
+  // the commit keeps the old core (and its Gram) when the status word is set
+  HIPCHK(c, launch_ne_apply(c->M, p.I, n, c->S, c->Sinv, refine, c->Gn, c->status, s));
+  HIPCHK(c, launch_commit_gram(c->Gn, p.I, p.Ra, p.Rb, c->cores[m], c->gram[m], c->status, s));
   return TR_OK;
 }
 
@@ -857,7 +873,6 @@ int trx_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ranks,
   A((void**)&c->T1, (size_t)maxT * 8);
   A((void**)&c->M, (size_t)maxI * maxRR * 8);
   A((void**)&c->Gn, (size_t)maxI * maxRR * 8);
-  A((void**)&c->Res, (size_t)maxI * maxRR * 8);
   A((void**)&c->G0u, (size_t)maxI * maxRR * 8);
   A((void**)&c->S, (size_t)maxRR * maxRR * 8);
   A((void**)&c->Lf, (size_t)maxRR * maxRR * 8);
@@ -936,8 +951,24 @@ int trx_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ranks,
     A((void**)&c->qpart, (size_t)c->qpart_elems * 8);
     if (rc) { tr_als_destroy(c); return rc; }
   }
-  if (o.shadow_mask & (1u << TR_BF16)) A(&c->xbf16, (size_t)numel * 2);
-  if (o.shadow_mask & (1u << TR_FP8)) A(&c->xfp8, (size_t)numel);
+  // One transposed low-precision shadow serves the two-stage modes of the NE
+  // variant that contract the slowest modes at the first such split
+  // (TR_ALS_NO_XT=1: none, those modes read the plain shadow).
+  static const bool no_xt = getenv("TR_ALS_NO_XT") && getenv("TR_ALS_NO_XT")[0] == '1';
+  if (variant == TR_NE && !no_xt)
+    for (int m = 0; m < N; ++m)
+      if (c->plan[m].regime == 1 && c->plan[m].nn) {
+        c->t_gK = c->plan[m].gK;
+        break;
+      }
+  if (o.shadow_mask & (1u << TR_BF16)) {
+    A(&c->xbf16, (size_t)numel * 2);
+    if (c->t_gK) A(&c->xbf16t, (size_t)numel * 2);
+  }
+  if (o.shadow_mask & (1u << TR_FP8)) {
+    A(&c->xfp8, (size_t)numel);
+    if (c->t_gK) A(&c->xfp8t, (size_t)numel);
+  }
   if (rc) { tr_als_destroy(c); return rc; }
   if (c->measure) {
     *o.measured = c->region_off;
