@@ -126,70 +126,37 @@ __global__ __launch_bounds__(256) void commit_gram_kernel(const double* G, int64
 
 // ---------------------------------------------------------------------------
 // Normal-equation apply with iterative refinement (Alg. 2 solve step): for a
-// block of 8 rows of M, G = M S^{-1}, then per refinement step R = M - G S and
-// G += R S^{-1}; the row blocks stay in LDS (k-major) between the products.
-// RG row groups of 8/RG rows split the 256 threads so small n keeps every
-// thread busy.  With STAGE the n x n operand of each product is first copied
-// to LDS in one coalesced pass (leading dimension n|1 against bank
-// conflicts, stored transposed so a wave reads consecutive words), the next
-// product's operand being fetched into registers meanwhile; otherwise it is
-// read from global memory.  The k loop keeps 8 operand pairs in flight.
-// A non-finite entry of the final G latches ST_NONFINITE.
+// block of NE_APPLY_ROWS rows of M, G = M S^{-1}, then per refinement step
+// R = M - G S and G += R S^{-1}; the row blocks stay in LDS (k-major) between
+// the products, the n x n operands are read from L2 (8 values of k in flight
+// per thread).  RG row groups split the 256 threads so that small n keeps
+// every thread busy.  A non-finite entry of the final G latches ST_NONFINITE.
+// (Staging the operand in LDS and 8- or 16-row blocks measured slower.)
 // ---------------------------------------------------------------------------
-constexpr int NE_APPLY_STAGE_MAX = 112;   // largest n whose operand is staged in LDS
+constexpr int NE_APPLY_ROWS = 4;
 
-template <int RG, bool STAGE>
+template <int RG>
 __global__ __launch_bounds__(256) void ne_apply_kernel(const double* __restrict__ M, int64_t I, int n,
                                                        const double* __restrict__ S,
                                                        const double* __restrict__ Sinv, int refine,
                                                        double* __restrict__ G, int* status) {
-  constexpr int RB = 8, RPT = RB / RG, CT = 256 / RG, KB = 8;
-  constexpr int NPF = STAGE ? (NE_APPLY_STAGE_MAX * NE_APPLY_STAGE_MAX / 2 + 255) / 256 : 1;
+  constexpr int RB = NE_APPLY_ROWS, RPT = RB / RG, CT = 256 / RG, KB = 8;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* Ms = reinterpret_cast<double*>(smem_raw);
   double* Gs = Ms + RB * n;
   double* Rs = Gs + RB * n;
-  double* Bs = Rs + RB * n;   // STAGE only: B transposed, Bs[j + ldb*k] = B[k + n*j]
-  const int ldb = n | 1;
   if (*status != 0) return;
   const int tid = threadIdx.x, grp = tid / CT, jt = tid % CT;
   const int64_t i0 = (int64_t)blockIdx.x * RB;
   const int rows = (int)min((int64_t)RB, I - i0);
-  // STAGE: the n x n operand of the next product travels in registers (pairs
-  // (e, e+1) of B, 16-byte loads) while the current product computes
-  const int nn = n * n, npair = nn / 2;
-  double2 pf[NPF];
-  auto prefetch = [&](const double* B) {
-#pragma unroll
-    for (int u = 0; u < NPF; ++u) {
-      const int q = tid + 256 * u;
-      pf[u] = q < npair ? reinterpret_cast<const double2*>(B)[q] : double2{0.0, 0.0};
-    }
-  };
-  auto stage = [&](const double* B) {   // (k, j) of element e = 2q walks by 512
-    const int dk = 512 % n, dj = 512 / n;
-    int k = (2 * tid) % n, j = (2 * tid) / n;
-#pragma unroll
-    for (int u = 0; u < NPF; ++u) {
-      if (tid + 256 * u < npair) {
-        int k1 = k + 1, j1 = j;
-        if (k1 == n) { k1 = 0; ++j1; }
-        Bs[j + ldb * k] = pf[u].x;
-        Bs[j1 + ldb * k1] = pf[u].y;
-      }
-      k += dk;
-      j += dj;
-      if (k >= n) { k -= n; ++j; }
-    }
-    if ((nn & 1) && tid == 0) Bs[(n - 1) + ldb * (n - 1)] = B[nn - 1];
-  };
-  if (STAGE) prefetch(Sinv);
   for (int e0 = 0; e0 < RB * n; e0 += 4 * 256) {   // four loads in flight per thread
     double t[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int e = e0 + tid + 256 * u, r = e % RB, k = e / RB;
-      t[u] = (e < RB * n && r < rows) ? M[(i0 + r) + I * k] : 0.0;
+      const bool ok = e < RB * n && r < rows;
+      const double v = M[ok ? (i0 + r) + I * k : 0];   // clamped: no branch, all in flight
+      t[u] = ok ? v : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -204,22 +171,18 @@ __global__ __launch_bounds__(256) void ne_apply_kernel(const double* __restrict_
     const double* Cin = ph == 0 ? nullptr : res ? Ms : Gs;
     const double alpha = res ? -1.0 : 1.0;
     double* Out = res ? Rs : Gs;
-    if (STAGE) {
-      __syncthreads();   // the previous phase's reads of Bs are done
-      stage(B);
-      if (ph + 1 < nph) prefetch(res ? Sinv : S);
-    }
     __syncthreads();
     for (int j = jt; j < n; j += CT) {
       double acc[RPT];
 #pragma unroll
       for (int r = 0; r < RPT; ++r) acc[r] = 0.0;
       const double* ak = A + grp * RPT;
+      const double* bj = B + (int64_t)n * j;
       int k = 0;
       for (; k + KB <= n; k += KB) {   // KB operand pairs in flight, then the FMAs in k order
         double bv[KB], av[KB][RPT];
 #pragma unroll
-        for (int u = 0; u < KB; ++u) bv[u] = STAGE ? Bs[j + ldb * (k + u)] : B[(k + u) + (int64_t)n * j];
+        for (int u = 0; u < KB; ++u) bv[u] = bj[k + u];
 #pragma unroll
         for (int u = 0; u < KB; ++u)
 #pragma unroll
@@ -230,9 +193,8 @@ __global__ __launch_bounds__(256) void ne_apply_kernel(const double* __restrict_
           for (int r = 0; r < RPT; ++r) acc[r] = fma(av[u][r], bv[u], acc[r]);
       }
       for (; k < n; ++k) {
-        const double b = STAGE ? Bs[j + ldb * k] : B[k + (int64_t)n * j];
 #pragma unroll
-        for (int r = 0; r < RPT; ++r) acc[r] = fma(ak[k * RB + r], b, acc[r]);
+        for (int r = 0; r < RPT; ++r) acc[r] = fma(ak[k * RB + r], bj[k], acc[r]);
       }
 #pragma unroll
       for (int r = 0; r < RPT; ++r) {
@@ -240,8 +202,8 @@ __global__ __launch_bounds__(256) void ne_apply_kernel(const double* __restrict_
         Out[o] = (Cin ? Cin[o] : 0.0) + alpha * acc[r];
       }
     }
-    __syncthreads();
   }
+  __syncthreads();
   bool bad = false;
   for (int e = tid; e < RB * n; e += 256) {
     const int r = e % RB, j = e / RB;
@@ -868,14 +830,9 @@ hipError_t launch_fit(const void* X, int xdt, int64_t I, int64_t K, const double
 
 hipError_t launch_ne_apply(const double* M, int64_t I, int n, const double* S, const double* Sinv, int refine,
                            double* G, int* status, hipStream_t s) {
-  const size_t rows_lds = (size_t)3 * 8 * n * sizeof(double);
-  const size_t staged = rows_lds + (size_t)(n | 1) * n * sizeof(double);
-  const bool stage = n <= NE_APPLY_STAGE_MAX;
-  const size_t lds = stage ? staged : rows_lds;
-  const dim3 grid((unsigned)cdiv(I, 8));
-  const void* k;
-  if (stage) k = n <= 64 ? (const void*)ne_apply_kernel<4, true> : (const void*)ne_apply_kernel<2, true>;
-  else k = n <= 128 ? (const void*)ne_apply_kernel<2, false> : (const void*)ne_apply_kernel<1, false>;
+  const size_t lds = (size_t)3 * NE_APPLY_ROWS * n * sizeof(double);
+  const dim3 grid((unsigned)cdiv(I, NE_APPLY_ROWS));
+  const void* k = n <= 64 ? (const void*)ne_apply_kernel<4> : (const void*)ne_apply_kernel<2>;
   if (lds > 64 * 1024) hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   void* args[] = {(void*)&M, (void*)&I, (void*)&n, (void*)&S, (void*)&Sinv, (void*)&refine, (void*)&G, (void*)&status};
   return hipLaunchKernel(k, grid, dim3(256), args, lds, s);

@@ -385,53 +385,76 @@ __global__ __launch_bounds__(256) void absorb_block_kernel(AbsorbArgs a) {
   if (tid == 0) absorb_store(a, l, h, u2, c2, red[0]);
 }
 
-// Narrow fast extents (lo < 32): one workgroup per (l, h, p) forms all Rf
-// outputs f, so every Y element is read once; the (i, x) terms are walked
-// with i fastest (contiguous in Y), each thread keeping its Rf partial sums
-// in registers, then a fixed-order wave and workgroup reduction.
+// Narrow fast extents (lo < 32) as a tall-skinny product: output row
+// (l, h, p) x column f, summed over k = (i, x) with i fastest.  A lane owns
+// one row and all Rf columns; the waves of a workgroup and S workgroups split
+// the k range; core values are wave-uniform (scalar loads).  Partial sums are
+// combined in a fixed order (waves in LDS, workgroups by absorb_sum_kernel).
+__device__ __forceinline__ int64_t absorb_index(const AbsorbArgs& a, int64_t l, int64_t h, int u2, int c2) {
+  const int Ru2 = a.side == 0 ? a.Rl : a.Ru;
+  const int Rc2 = a.side == 0 ? a.Rc : a.Rr;
+  if (a.final_out) return (l + a.lo * h) + a.lo * a.hi * (c2 + (int64_t)Rc2 * u2);
+  return l + a.lo * (h + a.hi * (u2 + (int64_t)Ru2 * c2));
+}
+
 template <int B, bool SIDE0>
-__global__ __launch_bounds__(256) void absorb_narrow_kernel(AbsorbArgs a) {
-  __shared__ double red[4][B];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+__global__ __launch_bounds__(256) void absorb_narrow_kernel(AbsorbArgs a, double* part, int64_t out_elems) {
+  __shared__ double red[4][B][64];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int Rx = SIDE0 ? a.Ru : a.Rc, Rf = SIDE0 ? a.Rl : a.Rr, Rp = SIDE0 ? a.Rc : a.Ru;
-  const int64_t e = blockIdx.x;
-  const int64_t l = e % a.lo, h = (e / a.lo) % a.hi;
-  const int p = (int)(e / (a.lo * a.hi));
-  const int64_t T = a.I * Rx;
+  const int64_t LH = a.lo * a.hi, rows = LH * Rp;
+  const int64_t r = (int64_t)blockIdx.x * 64 + lane;
+  const bool live = r < rows;
+  const int64_t rc = live ? r : 0;
+  const int64_t lh = rc % LH, l = lh % a.lo, h = lh / a.lo;
+  const int p = (int)(rc / LH);
   const int64_t sB = a.lo * a.I * a.hi;
+  const double* yrow = a.Y + l + a.lo * a.I * h + sB * (SIDE0 ? (int64_t)a.Ru * p : (int64_t)p);
+  const int64_t sx = SIDE0 ? sB : sB * a.Ru;   // Y stride of x
+  // k range of this workgroup, then of this wave
+  const int64_t K = a.I * Rx, S = gridDim.y;
+  const int64_t kb = K * blockIdx.y / S, ke = K * (blockIdx.y + 1) / S;
+  const int64_t k0 = kb + (ke - kb) * wave / 4, k1 = kb + (ke - kb) * (wave + 1) / 4;
   double acc[B];
 #pragma unroll
   for (int f = 0; f < B; ++f) acc[f] = 0.0;
-  int64_t i = tid % a.I;
-  int x = (int)(tid / a.I);
-  const int64_t di = 256 % a.I;
-  const int dx = (int)(256 / a.I);
-  for (int64_t t = tid; t < T; t += 256) {
-    const int bond = SIDE0 ? x + a.Ru * p : p + a.Ru * x;
-    const double y = a.Y[l + a.lo * (i + a.I * h) + sB * bond];
+  int64_t i = k0 % a.I;
+  int x = (int)(k0 / a.I);
+  const int64_t cf = SIDE0 ? 1 : (int64_t)a.Rc * a.I;   // core stride of f
+  for (int64_t k = k0; k < k1; k += 4) {   // four values of k per step: their loads in flight together
+    double y[4];
+    int64_t ii[4];
+    int xx[4];
 #pragma unroll
-    for (int f = 0; f < B; ++f)
-      if (f < Rf) {
-        const double cv = SIDE0 ? a.core[f + (int64_t)a.Rl * (i + a.I * x)] : a.core[x + (int64_t)a.Rc * (i + a.I * f)];
-        acc[f] = fma(y, cv, acc[f]);
-      }
-    i += di;
-    x += dx;
-    if (i >= a.I) { i -= a.I; ++x; }
+    for (int u = 0; u < 4; ++u) {
+      const bool ok = live && k + u < k1;
+      ii[u] = i;
+      xx[u] = x;
+      const double v = yrow[ok ? a.lo * i + sx * x : 0];
+      y[u] = ok ? v : 0.0;
+      if (++i == a.I) { i = 0; ++x; }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int xu = k + u < k1 ? xx[u] : 0;   // clamped: the term is zero anyway
+      const int64_t iu = k + u < k1 ? ii[u] : 0;
+      const double* c = SIDE0 ? a.core + (int64_t)a.Rl * (iu + a.I * xu) : a.core + xu + (int64_t)a.Rc * iu;
+#pragma unroll
+      for (int f = 0; f < B; ++f) acc[f] = fma(y[u], c[cf * (f < Rf ? f : 0)], acc[f]);
+    }
   }
 #pragma unroll
-  for (int f = 0; f < B; ++f) {
-    double v = acc[f];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    if (lane == 0) red[wave][f] = v;
-  }
+  for (int f = 0; f < B; ++f) red[wave][f][lane] = acc[f];
   __syncthreads();
-  if (tid < Rf) {
-    const double v = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
-    absorb_store(a, l, h, SIDE0 ? tid : p, SIDE0 ? p : tid, v);
+  if (wave == 0 && live) {
+    for (int f = 0; f < Rf; ++f) {
+      const double v = (red[0][f][lane] + red[1][f][lane]) + (red[2][f][lane] + red[3][f][lane]);
+      const int64_t e = absorb_index(a, l, h, SIDE0 ? f : p, SIDE0 ? p : f);
+      if (S == 1) a.out[e] = v;
+      else part[blockIdx.y * out_elems + e] = v;
+    }
   }
-  (void)Rp;
 }
 
 // Single-read absorption.  With x the contracted bond index, p the passive
@@ -461,24 +484,33 @@ __device__ __forceinline__ int64_t absorb2_out(const Absorb2& a, int64_t l, int6
 template <bool SIDE0>
 __device__ __forceinline__ void absorb2_stage_core(const Absorb2& a, int64_t i0, int64_t i1, double* cs) {
   const int Rx = SIDE0 ? a.Ru : a.Rc, Rf = SIDE0 ? a.Rl : a.Rr;
-  const int64_t n = (i1 - i0) * Rx * Rf;
-  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
-    const int f = (int)(e % Rf);
-    const int x = (int)((e / Rf) % Rx);
-    const int64_t i = i0 + e / ((int64_t)Rf * Rx);
-    cs[e] = SIDE0 ? a.core[f + (int64_t)a.Rl * (i + a.I * x)] : a.core[x + (int64_t)a.Rc * (i + a.I * f)];
+  const int n = (int)((i1 - i0) * Rx * Rf);   // a slice of one core: 32-bit offsets
+  const int bd = blockDim.x;
+  for (int e0 = 0; e0 < n; e0 += 4 * bd) {    // four loads in flight per thread (clamped index)
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + (int)threadIdx.x + u * bd, ec = e < n ? e : 0;
+      const int f = ec % Rf, q = ec / Rf, x = q % Rx;
+      const int64_t i = i0 + q / Rx;
+      v[u] = SIDE0 ? a.core[f + (int64_t)a.Rl * (i + a.I * x)] : a.core[x + (int64_t)a.Rc * (i + a.I * f)];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (e0 + (int)threadIdx.x + u * bd < n) cs[e0 + threadIdx.x + u * bd] = v[u];
   }
 }
 
 constexpr int AW_WAVES = 8;
 
-template <int B, bool SIDE0>
+// EXACT: Rx == Rf == B, so every rank loop has a fixed trip count.
+template <int B, bool SIDE0, bool EXACT>
 __global__ __launch_bounds__(64 * AW_WAVES) void absorb_wide_kernel(Absorb2 a, int64_t chunk) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* cs = reinterpret_cast<double*>(smem_raw);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t l = (int64_t)blockIdx.x * 64 + lane;
-  const int Rx = SIDE0 ? a.Ru : a.Rc, Rf = SIDE0 ? a.Rl : a.Rr;
+  const int Rx = EXACT ? B : (SIDE0 ? a.Ru : a.Rc), Rf = EXACT ? B : (SIDE0 ? a.Rl : a.Rr);
   const int64_t h = blockIdx.y % a.hi;
   const int p = (int)(blockIdx.y / a.hi);
   const int sp = blockIdx.z;
@@ -495,14 +527,17 @@ __global__ __launch_bounds__(64 * AW_WAVES) void absorb_wide_kernel(Absorb2 a, i
     for (int64_t i = i0; i < i1; ++i) {
       double y[B];
 #pragma unroll
-      for (int x = 0; x < B; ++x) y[x] = (x < Rx) ? a.Y[y0 + a.lo * i + sx * x] : 0.0;
+      for (int x = 0; x < B; ++x) {   // unconditional loads (clamped index): all in flight together
+        const double v = a.Y[y0 + a.lo * i + sx * (EXACT || x < Rx ? x : 0)];
+        y[x] = EXACT || x < Rx ? v : 0.0;
+      }
       const double* c = cs + (i - ib) * Rx * Rf;
 #pragma unroll
       for (int x = 0; x < B; ++x) {
-        if (x < Rx) {
+        if (EXACT || x < Rx) {
 #pragma unroll
           for (int f = 0; f < B; ++f)
-            if (f < Rf) acc[f] += y[x] * c[x * Rf + f];
+            if (EXACT || f < Rf) acc[f] += y[x] * c[x * Rf + f];
         }
       }
     }
@@ -610,7 +645,7 @@ namespace {
 
 constexpr size_t ABSORB_LDS_MAX = 96 * 1024;
 
-template <int B, bool SIDE0>
+template <int B, bool SIDE0, bool EXACT>
 hipError_t launch_absorb2(const Absorb2& a, hipStream_t s) {
   const int Rx = SIDE0 ? a.Ru : a.Rc, Rf = SIDE0 ? a.Rl : a.Rr, Rp = SIDE0 ? a.Rc : a.Ru;
   const size_t row = (size_t)Rx * Rf * sizeof(double);   // core bytes per value of i
@@ -618,10 +653,10 @@ hipError_t launch_absorb2(const Absorb2& a, hipStream_t s) {
     const int64_t chunk = cdiv(a.I, a.S);
     const size_t lds = std::max((size_t)chunk * row, (size_t)AW_WAVES * B * 64 * sizeof(double));
     if (lds > 64 * 1024)
-      hipFuncSetAttribute((const void*)absorb_wide_kernel<B, SIDE0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+      hipFuncSetAttribute((const void*)absorb_wide_kernel<B, SIDE0, EXACT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)lds);
     dim3 grid((unsigned)cdiv(a.lo, 64), (unsigned)(a.hi * Rp), (unsigned)cdiv(a.I, chunk));
-    hipLaunchKernelGGL((absorb_wide_kernel<B, SIDE0>), grid, dim3(64 * AW_WAVES), lds, s, a, chunk);
+    hipLaunchKernelGGL((absorb_wide_kernel<B, SIDE0, EXACT>), grid, dim3(64 * AW_WAVES), lds, s, a, chunk);
     if (a.S > 1)
       hipLaunchKernelGGL(absorb_sum_kernel, dim3((unsigned)cdiv(a.out_elems, 256)), dim3(256), 0, s, a.part, a.S,
                          a.out_elems, a.out);
@@ -652,31 +687,49 @@ hipError_t launch_absorb(const double* Y, int64_t lo, int64_t I, int64_t hi, int
     a.S = (int)cdiv(I, cdiv(I, S));
     if (a.S > 1 && (size_t)a.S * out_elems * sizeof(double) > part_bytes) a.S = 0;   // no room: other kernels
     if (a.S > 0) {
-      if (side == 0) {
-        if (Bn <= 8) return launch_absorb2<8, true>(a, s);
-        if (Bn <= 16) return launch_absorb2<16, true>(a, s);
-        return launch_absorb2<24, true>(a, s);
+      if (Rx == Rf) {   // equal ranks: fixed trip counts for the common ones
+        switch (Rx) {
+#define AW_EXACT(R) \
+  case R: return side == 0 ? launch_absorb2<R, true, true>(a, s) : launch_absorb2<R, false, true>(a, s);
+          AW_EXACT(4) AW_EXACT(8) AW_EXACT(10) AW_EXACT(12) AW_EXACT(16) AW_EXACT(20)
+#undef AW_EXACT
+          default: break;
+        }
       }
-      if (Bn <= 8) return launch_absorb2<8, false>(a, s);
-      if (Bn <= 16) return launch_absorb2<16, false>(a, s);
-      return launch_absorb2<24, false>(a, s);
+      if (side == 0) {
+        if (Bn <= 8) return launch_absorb2<8, true, false>(a, s);
+        if (Bn <= 16) return launch_absorb2<16, true, false>(a, s);
+        return launch_absorb2<24, true, false>(a, s);
+      }
+      if (Bn <= 8) return launch_absorb2<8, false, false>(a, s);
+      if (Bn <= 16) return launch_absorb2<16, false, false>(a, s);
+      return launch_absorb2<24, false, false>(a, s);
     }
   }
   AbsorbArgs a{Y, lo, I, hi, Ru, Rc, core, Rl, Rr, side, final_out, out};
   if (lo >= 32) {
     dim3 grid((unsigned)cdiv(lo, 64), (unsigned)hi, (unsigned)(Ru2 * Rc2));
     hipLaunchKernelGGL(absorb_lanes_kernel, grid, dim3(1024), 0, s, a);
-  } else if (Rf <= 24 && lo * hi * Rp <= 0x7fffffff) {
-    const dim3 grid((unsigned)(lo * hi * Rp));
+  } else if (Rf <= 24 && cdiv(lo * hi * Rp, 64) <= 0x7fffffff) {
+    const int64_t rb = cdiv(lo * hi * Rp, 64);
+    // k splits until ~512 workgroups, at least 64 values of k per split, within the partial buffer
+    int64_t S = std::max<int64_t>(1, std::min<int64_t>(cdiv(512, rb), (I * Rx) / 64));
+    S = std::min<int64_t>(S, 65535);
+    while (S > 1 && (size_t)S * out_elems * sizeof(double) > part_bytes) --S;
+    const dim3 grid((unsigned)rb, (unsigned)S);
+    auto go = [&](auto kern) { hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, a, part, out_elems); };
     if (side == 0) {
-      if (Rf <= 8) hipLaunchKernelGGL((absorb_narrow_kernel<8, true>), grid, dim3(256), 0, s, a);
-      else if (Rf <= 16) hipLaunchKernelGGL((absorb_narrow_kernel<16, true>), grid, dim3(256), 0, s, a);
-      else hipLaunchKernelGGL((absorb_narrow_kernel<24, true>), grid, dim3(256), 0, s, a);
+      if (Rf <= 8) go(absorb_narrow_kernel<8, true>);
+      else if (Rf <= 16) go(absorb_narrow_kernel<16, true>);
+      else go(absorb_narrow_kernel<24, true>);
     } else {
-      if (Rf <= 8) hipLaunchKernelGGL((absorb_narrow_kernel<8, false>), grid, dim3(256), 0, s, a);
-      else if (Rf <= 16) hipLaunchKernelGGL((absorb_narrow_kernel<16, false>), grid, dim3(256), 0, s, a);
-      else hipLaunchKernelGGL((absorb_narrow_kernel<24, false>), grid, dim3(256), 0, s, a);
+      if (Rf <= 8) go(absorb_narrow_kernel<8, false>);
+      else if (Rf <= 16) go(absorb_narrow_kernel<16, false>);
+      else go(absorb_narrow_kernel<24, false>);
     }
+    if (S > 1)
+      hipLaunchKernelGGL(absorb_sum_kernel, dim3((unsigned)cdiv(out_elems, 256)), dim3(256), 0, s, part, (int)S,
+                         out_elems, out);
   } else {
     hipLaunchKernelGGL(absorb_block_kernel, dim3((unsigned)(lo * hi * Ru2 * Rc2)), dim3(256), 0, s, a);
   }
