@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -74,6 +75,7 @@ struct tr_als_ctx {
   bool bf16_ready = false, fp8_ready = false;
   double *F1 = nullptr, *F2 = nullptr, *T0 = nullptr, *T1 = nullptr;
   double *M = nullptr, *S = nullptr, *W0 = nullptr, *W1 = nullptr, *Lf = nullptr, *LTf = nullptr, *cholw = nullptr;
+  double* Wpre = nullptr;   // ring prefix of the next mode within a sweep (order >= 4)
   double *Gn = nullptr, *G0u = nullptr, *LinvT = nullptr, *Tsol = nullptr;
   double *Y0 = nullptr, *Y1 = nullptr;   // stage-2 intermediates
   void* Bt = nullptr;                    // stage-1 table, transposed, operand type
@@ -475,7 +477,12 @@ int ensure_shadow(tr_als_ctx* c, int prec) {
 
 // Two-stage M_n: group table -> transposed operand table -> stage-1 GEMM over
 // X -> ordered reduction -> stage-2 absorptions.
-int compute_mttsp_two_stage(tr_als_ctx* c, int m, int prec, double* Mout, bool in_sweep) {
+// `after_main` (may be empty) is enqueued right after the X-contraction
+// launch: the NE update forks its coefficient branch there, so that a graph
+// built from the sweep releases the contraction before the branch.
+using Hook = std::function<int()>;
+
+int compute_mttsp_two_stage(tr_als_ctx* c, int m, int prec, double* Mout, bool in_sweep, const Hook& after_main) {
   hipStream_t s = c->stream;
   const Plan& p = c->plan[m];
   const bool reuse = in_sweep && p.reuse_prev && prec != TR_FP8;
@@ -514,6 +521,10 @@ int compute_mttsp_two_stage(tr_als_ctx* c, int m, int prec, double* Mout, bool i
     c->evs.push_back({e0, e1});
     c->prof_bytes = (double)esize * (double)c->numel;
   }
+  if (after_main) {
+    const int hr = after_main();
+    if (hr) return hr;
+  }
   double* cur = p.steps.empty() ? c->Y1 : c->Y0;
   HIPCHK(c, launch_xg_reduce(g, prec, out_scale, cur, c->status, s));
   if (p.steps.empty()) {
@@ -534,10 +545,10 @@ int compute_mttsp_two_stage(tr_als_ctx* c, int m, int prec, double* Mout, bool i
 
 // M_n = X_[n] G^{!=n}_[2] for the context's current cores (tables + X stream +
 // ordered split-K reduction).
-int compute_mttsp(tr_als_ctx* c, int m, int prec, double* Mout, bool in_sweep = false) {
+int compute_mttsp(tr_als_ctx* c, int m, int prec, double* Mout, bool in_sweep = false, const Hook& after_main = Hook()) {
   hipStream_t s = c->stream;
   const Plan& p = c->plan[m];
-  if (p.regime == 1) return compute_mttsp_two_stage(c, m, prec, Mout, in_sweep);
+  if (p.regime == 1) return compute_mttsp_two_stage(c, m, prec, Mout, in_sweep, after_main);
   int rc = build_table(c, p.f1c, p.Rmid, c->F1);
   if (rc) return rc;
   rc = build_table(c, p.f2c, p.Rmid, c->F2);
@@ -580,36 +591,79 @@ int compute_mttsp(tr_als_ctx* c, int m, int prec, double* Mout, bool in_sweep = 
                     : prec == TR_BF16 ? 2 : 1;
     c->prof_bytes = eb * (double)c->numel;
   }
+  if (after_main) {
+    const int hr = after_main();
+    if (hr) return hr;
+  }
   HIPCHK(c, launch_xs_reduce(x.a, prec, out_scale, Mout, c->status, s));
   return TR_OK;
 }
 
 // S_n<2> from the Gram ring: W = K_{m+1} K_{m+2} ... K_{m-1} (Kronecker-order
 // Grams), then realigned.
-int compute_coef(tr_als_ctx* c, int m, double* Sout, hipStream_t s) {
-  const int N = c->N;
-  std::vector<int> chain;
-  for (int k = 1; k < N; ++k) chain.push_back((m + k) % N);
+// Ring product of Prop. 3.1 for mode m: W = K_{m+1} K_{m+2} ... K_{m-1} over
+// the Kronecker-form Gram views, then realigned into S_m.  Within a sweep of
+// order >= 4 the prefix K_{m+1} ... K_{m-2} (it excludes the cores of modes
+// m-1 and m) is formed by the previous mode's branch (ring_prefix), so only
+// the last factor, refreshed by that mode, is multiplied here.
+int ring_gemms(tr_als_ctx* c, const std::vector<int>& chain, MatView W, int64_t rows, double* last_out,
+               hipStream_t s) {
   auto gview = [&](int k) {
     MatView v;
     v.p = c->gram[k]; v.ld = 0; v.kind = 1; v.Rl = c->R[k]; v.Rr = c->R[k + 1];
     return v;
   };
-  MatView W = gview(chain[0]);
   double* bufs[2] = {c->W0, c->W1};
   int cur = 0;
-  int64_t rows = (int64_t)c->R[chain[0]] * c->R[chain[0]];
-  for (size_t q = 1; q < chain.size(); ++q) {
+  for (size_t q = 0; q < chain.size(); ++q) {
     const int k = chain[q];
     const int64_t inner = (int64_t)c->R[k] * c->R[k];
     const int64_t cols = (int64_t)c->R[k + 1] * c->R[k + 1];
-    MatView B = gview(k);
-    HIPCHK(c, launch_gemm64(rows, cols, inner, 1.0, W, B, 0.0, nullptr, 0, bufs[cur], rows, s));
-    W.p = bufs[cur]; W.ld = rows; W.kind = 0;
+    double* out = (q + 1 == chain.size() && last_out) ? last_out : bufs[cur];
+    HIPCHK(c, launch_gemm64(rows, cols, inner, 1.0, W, gview(k), 0.0, nullptr, 0, out, rows, s));
+    W.p = out; W.ld = rows; W.kind = 0;
     cur ^= 1;
   }
-  HIPCHK(c, launch_realign_S(W, c->R[m], c->R[m + 1], Sout, s));
   return TR_OK;
+}
+
+MatView ring_first(const tr_als_ctx* c, int k) {
+  MatView v;
+  v.p = c->gram[k]; v.ld = 0; v.kind = 1; v.Rl = c->R[k]; v.Rr = c->R[k + 1];
+  return v;
+}
+
+int compute_coef(tr_als_ctx* c, int m, double* Sout, hipStream_t s, bool use_prefix = false) {
+  const int N = c->N;
+  const int64_t rows = (int64_t)c->R[(m + 1) % N] * c->R[(m + 1) % N];
+  MatView W;
+  std::vector<int> rest;
+  if (use_prefix) {   // Wpre = K_{m+1} ... K_{m-2}
+    W.p = c->Wpre; W.ld = rows; W.kind = 0; W.Rl = 0; W.Rr = 0;
+    rest.push_back((m + N - 1) % N);
+  } else {
+    W = ring_first(c, (m + 1) % N);
+    for (int k = 2; k < N; ++k) rest.push_back((m + k) % N);
+  }
+  int rc = ring_gemms(c, rest, W, rows, nullptr, s);
+  if (rc) return rc;
+  MatView Wf;
+  if (rest.empty()) Wf = W;
+  else {
+    Wf.p = (rest.size() & 1) ? c->W0 : c->W1;
+    Wf.ld = rows; Wf.kind = 0; Wf.Rl = 0; Wf.Rr = 0;
+  }
+  HIPCHK(c, launch_realign_S(Wf, c->R[m], c->R[m + 1], Sout, s));
+  return TR_OK;
+}
+
+// Prefix K_{m+1} ... K_{m-2} of mode m's ring, into Wpre (order >= 4).
+int ring_prefix(tr_als_ctx* c, int m, hipStream_t s) {
+  const int N = c->N;
+  const int64_t rows = (int64_t)c->R[(m + 1) % N] * c->R[(m + 1) % N];
+  std::vector<int> rest;
+  for (int k = 2; k <= N - 2; ++k) rest.push_back((m + k) % N);
+  return ring_gemms(c, rest, ring_first(c, (m + 1) % N), rows, c->Wpre, s);
 }
 
 // One NE mode update.  The coefficient branch (Gram ring -> S_n -> Cholesky ->
@@ -621,17 +675,27 @@ int update_mode_ne(tr_als_ctx* c, int m, int prec, int refine, bool in_sweep) {
   const Plan& p = c->plan[m];
   const int n = p.Ra * p.Rb;
   HIPCHK(c, hipEventRecord(c->ev_fork, s));
-  HIPCHK(c, hipStreamWaitEvent(s2, c->ev_fork, 0));
-  int rc = compute_coef(c, m, c->S, s2);
-  if (rc) return rc;
-  if (spd_inverse_fits(n)) {
-    HIPCHK(c, launch_spd_inverse(c->S, n, c->Sinv, c->status, s2));
-  } else {
-    HIPCHK(c, launch_chol(c->S, n, c->Lf, c->LTf, c->cholw, c->status, s2));
-    HIPCHK(c, launch_chol_solve(c->Lf, c->LTf, n, nullptr, n, c->Sinv, 0, c->status, s2));
-  }
-  HIPCHK(c, hipEventRecord(c->ev_join, s2));
-  rc = compute_mttsp(c, m, prec, c->M, in_sweep);
+  // coefficient branch on the second stream, forked after the X-contraction
+  // launch (it needs only the Grams, which are ready at the fork)
+  // within a sweep of order >= 4 the previous mode formed this mode's ring
+  // prefix (mode 1 of a sweep starts from scratch: nothing crosses sweeps)
+  const bool prefix = in_sweep && c->N >= 4;
+  auto branch = [&]() -> int {
+    HIPCHK(c, hipStreamWaitEvent(s2, c->ev_fork, 0));
+    const int r = compute_coef(c, m, c->S, s2, prefix && m > 0);
+    if (r) return r;
+    if (spd_inverse_fits(n)) {
+      HIPCHK(c, launch_spd_inverse(c->S, n, c->Sinv, c->status, s2));
+    } else {
+      HIPCHK(c, launch_chol(c->S, n, c->Lf, c->LTf, c->cholw, c->status, s2));
+      HIPCHK(c, launch_chol_solve(c->Lf, c->LTf, n, nullptr, n, c->Sinv, 0, c->status, s2));
+    }
+    HIPCHK(c, hipEventRecord(c->ev_join, s2));
+    // after the join: the next mode's prefix excludes this mode's core
+    if (prefix && m + 1 < c->N) return ring_prefix(c, m + 1, s2);
+    return TR_OK;
+  };
+  int rc = compute_mttsp(c, m, prec, c->M, in_sweep, branch);
   if (rc) return rc;
   HIPCHK(c, hipStreamWaitEvent(s, c->ev_join, 0));
   // G = M S^{-1} with refinement; the apply latches any non-finite entry, and
@@ -886,6 +950,7 @@ int trx_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ranks,
   A((void**)&c->Y0, (size_t)maxY * 8);
   A((void**)&c->Y1, (size_t)maxY * 8);
   A((void**)&c->W1, (size_t)maxW * 8);
+  if (N >= 4) A((void**)&c->Wpre, (size_t)maxW * 8);
   A((void**)&c->dpart, (size_t)c->nred * 8);
   A((void**)&c->fpart, (size_t)c->nred * 4);
   A((void**)&c->dscal, 8 * 8);
