@@ -62,6 +62,10 @@ struct XgArgs {
 int xgemm_kt(int prec);
 hipError_t launch_xgemm(const XgArgs& g, int prec, int xdt, hipStream_t s);
 hipError_t launch_xg_reduce(const XgArgs& g, int prec, double out_scale, double* Y, int* status, hipStream_t s);
+// Operand table (transposed, zero-padded, in the operand type; not FP8) of a
+// group of one or two cores, formed directly from the cores.
+hipError_t launch_group_bt(const double* G0, int Rl, int64_t I0, int Rm, const double* G1, int64_t I1, int two,
+                           int64_t K, int C, int Crows, int64_t ldb, int prec, void* Bt, hipStream_t s);
 hipError_t launch_table_to_bt(const double* T, int64_t K, int C, int Crows, int64_t ldb, int prec, double scale,
                               void* Bt, hipStream_t s);
 hipError_t launch_absorb(const double* Y, int64_t lo, int64_t I, int64_t hi, int Ru, int Rc, const double* core,

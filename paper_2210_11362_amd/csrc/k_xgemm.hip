@@ -253,34 +253,65 @@ __global__ __launch_bounds__(NTHR) void xgemm_kernel(XgArgs g) {
       }
 }
 
-// Y[r + M*c] = out_scale * sum over splits of the partial tiles (fixed order).
+// Y[r + M*c] = out_scale * sum over splits of the partial tiles (fixed
+// order).  A workgroup takes a block of 64 rows x 16 columns of one tile:
+// partial rows are read as 16-column runs (row-major tiles), summed,
+// transposed through LDS and written as 64-row runs of the column-major Y.
+// Each thread has four elements, all their loads in flight together.
 template <int P>
-__global__ void xg_reduce_kernel(XgArgs g, int MT, double out_scale, double* Y, int* status) {
+__global__ __launch_bounds__(256) void xg_reduce_kernel(XgArgs g, int MT, double out_scale, double* Y, int* status) {
   using part_t = typename std::conditional<P == TR_F64, double, float>::type;
-  const int64_t tsz = (int64_t)MT * g.NT;
+  __shared__ double tl[16][65];
+  const int NT = g.NT;
+  const int64_t tsz = (int64_t)MT * NT;
   const int64_t ntile = (int64_t)g.n_mt * g.n_nt;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= ntile * tsz) return;
-  const int64_t tile = idx / tsz;
-  const int row = (int)((idx % tsz) / g.NT), col = (int)(idx % g.NT);
+  const int rbs = MT / 64, cbs = NT / 16;
+  const int64_t tile = blockIdx.x / (rbs * cbs);
+  const int rem = (int)(blockIdx.x % (rbs * cbs));
+  const int rb = (rem % rbs) * 64, cb = (rem / rbs) * 16;
   const int mt = (int)(tile % g.n_mt), nt = (int)(tile / g.n_mt);
-  const int64_t r = (int64_t)mt * MT + row;
-  const int64_t c = (int64_t)nt * g.NT + col;
-  if (r >= g.M || c >= g.C) return;
-  const part_t* p = reinterpret_cast<const part_t*>(g.partial) + idx;
+  const part_t* base = reinterpret_cast<const part_t*>(g.partial) + tile * tsz + (int64_t)rb * NT + cb;
   const size_t ss = (size_t)(ntile * tsz);
-  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  double acc[4][4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[q][u] = 0.0;
   int sp = 0;
   for (; sp + 4 <= g.nsplit; sp += 4) {
-    s0 += (double)p[(sp + 0) * ss];
-    s1 += (double)p[(sp + 1) * ss];
-    s2 += (double)p[(sp + 2) * ss];
-    s3 += (double)p[(sp + 3) * ss];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = threadIdx.x + 256 * q, row = e >> 4, col = e & 15;
+      const part_t* p = base + (int64_t)row * NT + col;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[q][u] += (double)p[(sp + u) * ss];
+    }
   }
-  for (; sp < g.nsplit; ++sp) s0 += (double)p[sp * ss];
-  const double s = ((s0 + s1) + (s2 + s3)) * out_scale;
-  if (!isfinite(s)) atomicOr(status, ST_NONFINITE);
-  Y[r + g.M * c] = s;
+  for (; sp < g.nsplit; ++sp) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = threadIdx.x + 256 * q, row = e >> 4, col = e & 15;
+      acc[q][0] += (double)base[(int64_t)row * NT + col + sp * ss];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = threadIdx.x + 256 * q, row = e >> 4, col = e & 15;
+    tl[col][row] = ((acc[q][0] + acc[q][1]) + (acc[q][2] + acc[q][3])) * out_scale;
+  }
+  __syncthreads();
+  bool bad = false;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = threadIdx.x + 256 * q, col = e >> 6, row = e & 63;
+    const int64_t r = (int64_t)mt * MT + rb + row, c = (int64_t)nt * NT + cb + col;
+    if (r < g.M && c < g.C) {
+      const double v = tl[col][row];
+      bad = bad || !isfinite(v);
+      Y[r + g.M * c] = v;
+    }
+  }
+  if (bad) atomicOr(status, ST_NONFINITE);
 }
 
 // Bt[c * ldb + k] = op(T[k * C + c] * scale), zero for k >= K or c >= C (padding).
@@ -296,6 +327,53 @@ __global__ void table_to_bt_kernel(const double* T, int64_t K, int C, int Crows,
       Bt[e] = (__bf16)(float)v;
     else
       Bt[e] = (O)v;
+  }
+}
+
+// Operand table of a group of one or two cores straight from the cores (no
+// FP64 table in between): entry k = j + I0*i of the partial subchain
+// G0(:, j, :) G1(:, i, :) (one core: G0(:, k, :)), column r + Rl*c, written
+// transposed and zero-padded like table_to_bt_kernel.  A thread forms the Rl
+// entries (r, c) of one k from one column of G1 and the slice G0(:, j, :),
+// summing over the inner bond in increasing order in FP64; blockIdx.y = c,
+// and the last y row writes the padding rows C..Crows-1.
+template <typename O, int RB>
+__global__ __launch_bounds__(256) void group_bt_kernel(const double* G0, int Rl, int64_t I0, int Rm,
+                                                       const double* G1, int64_t I1, int two, int64_t K, int C,
+                                                       int Crows, int64_t ldb, O* Bt) {
+  const int c = blockIdx.y, Rc = C / Rl;
+  auto put = [&](int col, int64_t k, double v) {
+    if constexpr (std::is_same<O, __bf16>::value) Bt[col * ldb + k] = (__bf16)(float)v;
+    else Bt[col * ldb + k] = (O)v;
+  };
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ldb; k += (int64_t)gridDim.x * blockDim.x) {
+    if (c == Rc) {   // padding rows
+      for (int col = C; col < Crows; ++col) put(col, k, 0.0);
+      continue;
+    }
+    double acc[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) acc[r] = 0.0;
+    if (k < K) {
+      if (two) {
+        const int64_t j = k % I0, i = k / I0;
+        const double* g1 = G1 + (int64_t)Rm * (i + I1 * c);
+        const double* g0 = G0 + (int64_t)Rl * j;
+#pragma unroll 5
+        for (int m = 0; m < Rm; ++m) {   // unrolled: the loads of several m in flight together
+          const double b = g1[m];
+          const double* g0m = g0 + (int64_t)Rl * I0 * m;
+#pragma unroll
+          for (int r = 0; r < RB; ++r) acc[r] = fma(g0m[r < Rl ? r : 0], b, acc[r]);
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < RB; ++r) acc[r] = G0[(r < Rl ? r : 0) + (int64_t)Rl * (k + I0 * c)];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+      if (r < Rl) put(r + Rl * c, k, acc[r]);
   }
 }
 
@@ -621,11 +699,11 @@ hipError_t launch_xgemm(const XgArgs& g, int prec, int xdt, hipStream_t s) {
 }
 
 hipError_t launch_xg_reduce(const XgArgs& g, int prec, double out_scale, double* Y, int* status, hipStream_t s) {
-  const int64_t n = (int64_t)g.n_mt * g.n_nt * g.MT * g.NT;
+  const int64_t blocks = (int64_t)g.n_mt * g.n_nt * (g.MT / 64) * (g.NT / 16);
   if (prec == TR_F64)
-    hipLaunchKernelGGL(xg_reduce_kernel<TR_F64>, dim3(cdiv(n, 256)), dim3(256), 0, s, g, g.MT, out_scale, Y, status);
+    hipLaunchKernelGGL(xg_reduce_kernel<TR_F64>, dim3((unsigned)blocks), dim3(256), 0, s, g, g.MT, out_scale, Y, status);
   else
-    hipLaunchKernelGGL(xg_reduce_kernel<TR_F32>, dim3(cdiv(n, 256)), dim3(256), 0, s, g, g.MT, out_scale, Y, status);
+    hipLaunchKernelGGL(xg_reduce_kernel<TR_F32>, dim3((unsigned)blocks), dim3(256), 0, s, g, g.MT, out_scale, Y, status);
   return hipGetLastError();
 }
 
@@ -637,6 +715,30 @@ hipError_t launch_table_to_bt(const double* T, int64_t K, int C, int Crows, int6
     case TR_F32: hipLaunchKernelGGL(table_to_bt_kernel<float>, dim3(grid), dim3(256), 0, s, T, K, C, Crows, ldb, scale, (float*)Bt); break;
     case TR_BF16: hipLaunchKernelGGL(table_to_bt_kernel<__bf16>, dim3(grid), dim3(256), 0, s, T, K, C, Crows, ldb, scale, (__bf16*)Bt); break;
     default: hipLaunchKernelGGL(table_to_bt_kernel<uint8_t>, dim3(grid), dim3(256), 0, s, T, K, C, Crows, ldb, scale, (uint8_t*)Bt); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_group_bt(const double* G0, int Rl, int64_t I0, int Rm, const double* G1, int64_t I1, int two,
+                           int64_t K, int C, int Crows, int64_t ldb, int prec, void* Bt, hipStream_t s) {
+  if (Rl > 24) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)std::min<int64_t>(cdiv(ldb, 256), 1024), (unsigned)(C / Rl + 1));
+  auto go = [&](auto* out, auto rb) {
+    constexpr int RB = decltype(rb)::value;
+    using O = std::remove_pointer_t<decltype(out)>;
+    hipLaunchKernelGGL((group_bt_kernel<O, RB>), grid, dim3(256), 0, s, G0, Rl, I0, Rm, G1, I1, two, K, C, Crows, ldb,
+                       out);
+  };
+  auto by_rank = [&](auto* out) {
+    if (Rl <= 8) go(out, std::integral_constant<int, 8>());
+    else if (Rl <= 16) go(out, std::integral_constant<int, 16>());
+    else go(out, std::integral_constant<int, 24>());
+  };
+  switch (prec) {
+    case TR_F64: by_rank((double*)Bt); break;
+    case TR_F32: by_rank((float*)Bt); break;
+    case TR_BF16: by_rank((__bf16*)Bt); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

@@ -486,7 +486,9 @@ int compute_mttsp_two_stage(tr_als_ctx* c, int m, int prec, double* Mout, bool i
   hipStream_t s = c->stream;
   const Plan& p = c->plan[m];
   const bool reuse = in_sweep && p.reuse_prev && prec != TR_FP8;
-  int rc = reuse ? TR_OK : build_table(c, p.gcores, 1, c->F1);
+  // groups of one or two cores: operand table straight from the cores
+  const bool direct = prec != TR_FP8 && (p.gcores.size() == 1 || p.gcores.size() == 2) && c->R[p.gcores[0]] <= 24;
+  int rc = (reuse || direct) ? TR_OK : build_table(c, p.gcores, 1, c->F1);
   if (rc) return rc;
   rc = ensure_shadow(c, prec);
   if (rc) return rc;
@@ -507,7 +509,14 @@ int compute_mttsp_two_stage(tr_als_ctx* c, int m, int prec, double* Mout, bool i
     bscale = tm > 0 ? std::ldexp(1.0, (int)std::floor(std::log2(448.0 / tm))) : 1.0;
     out_scale = 1.0 / ((double)c->fp8_scale * bscale);
   }
-  if (!reuse) HIPCHK(c, launch_table_to_bt(c->F1, p.gK, p.gC, g.n_nt * g.NT, g.ldb, prec, bscale, c->Bt, s));
+  if (!reuse && direct) {
+    const int g0 = p.gcores[0], two = p.gcores.size() == 2;
+    const int g1 = two ? p.gcores[1] : g0;
+    HIPCHK(c, launch_group_bt(c->cores[g0], c->R[g0], c->dims[g0], c->R[g0 + 1], c->cores[g1], c->dims[g1], two, p.gK,
+                              p.gC, g.n_nt * g.NT, g.ldb, prec, c->Bt, s));
+  } else if (!reuse) {
+    HIPCHK(c, launch_table_to_bt(c->F1, p.gK, p.gC, g.n_nt * g.NT, g.ldb, prec, bscale, c->Bt, s));
+  }
   const bool prof = c->prof;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (prof) {
