@@ -149,6 +149,13 @@ int tr_als_profile_enable(tr_als_ctx* ctx, int enable);
 int tr_als_profile_read(tr_als_ctx* ctx, double* xstream_ms /*host*/, int64_t* launches /*host*/,
                         double* bytes_per_launch /*host, algorithmic X bytes*/);
 
+// Debugging aid.  With TR_ALS_CANARY=1 in the environment at context creation,
+// every workspace buffer of a context is followed by a 4 KiB guard band filled
+// with a byte pattern, and destroying the context checks the bands; returns
+// the number of overrun buffers found so far in this process (each is also
+// reported on stderr).  Always 0 without TR_ALS_CANARY.
+int tr_als_debug_overruns(void);
+
 /* ------------------------------------------------------------------------ *
  * Planted test tensors generated on the device.
  *

@@ -1,6 +1,7 @@
 // Host runtime of the TR-ALS library: context, per-mode plans, workspace, the
 // Gauss-Seidel sweep driver (Alg. 2 / Alg. 3) and the C ABI of tr_als.h.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -76,6 +77,13 @@ struct tr_als_ctx {
   double *F1 = nullptr, *F2 = nullptr, *T0 = nullptr, *T1 = nullptr;
   double *M = nullptr, *S = nullptr, *W0 = nullptr, *W1 = nullptr, *Lf = nullptr, *LTf = nullptr, *cholw = nullptr;
   double* Wpre = nullptr;   // ring prefix of the next mode within a sweep (order >= 4)
+  int64_t w_cap = 0;        // elements of W0, W1 and Wpre
+  // TR_ALS_CANARY=1: every workspace buffer is followed by a guard band filled
+  // with a byte pattern, checked when the context is destroyed
+  bool canary = false;
+  std::vector<std::pair<char*, int>> guards;   // (guard band, allocation index)
+  size_t guards_filled = 0;
+  int nalloc = 0;
   double *Gn = nullptr, *G0u = nullptr, *LinvT = nullptr, *Tsol = nullptr;
   double *Y0 = nullptr, *Y1 = nullptr;   // stage-2 intermediates
   void* Bt = nullptr;                    // stage-1 table, transposed, operand type
@@ -120,8 +128,18 @@ int fail(tr_als_ctx* c, int code, const std::string& msg) {
       return fail(ctx, TR_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));         \
   } while (0)
 
+constexpr size_t GUARD_BYTES = 4096;
+constexpr unsigned char GUARD_BYTE = 0xA5;
+std::atomic<int> g_overruns{0};
+
 int alloc(tr_als_ctx* c, void** p, size_t bytes) {
   if (bytes == 0) bytes = 16;
+  const size_t guard = c->canary ? GUARD_BYTES : 0;
+  bytes = trx_round(bytes) + guard;
+  const int idx = c->nalloc++;
+  auto note = [&]() {
+    if (guard && !c->measure) c->guards.push_back({(char*)*p + bytes - guard, idx});
+  };
   if (c->measure || c->region) {
     const size_t b = trx_round(bytes);
     if (c->region && c->region_off + b > c->region_cap) {
@@ -131,6 +149,7 @@ int alloc(tr_als_ctx* c, void** p, size_t bytes) {
     // sizing only: a distinct, never dereferenced, aligned placeholder
     *p = c->region ? (void*)(c->region + c->region_off) : (void*)(TRX_ALIGN + c->region_off);
     c->region_off += b;
+    note();
     return TR_OK;
   }
   hipError_t e = hipMalloc(p, bytes);
@@ -140,7 +159,31 @@ int alloc(tr_als_ctx* c, void** p, size_t bytes) {
     return fail(c, TR_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
   }
   c->allocs.push_back(*p);
+  note();
   return TR_OK;
+}
+
+// Guard bands: filled in stream order after their allocation (never inside a
+// graph capture: allocation happens before), checked at destruction.
+void fill_guards(tr_als_ctx* c, hipStream_t s) {
+  for (; c->guards_filled < c->guards.size(); ++c->guards_filled)
+    (void)hipMemsetAsync(c->guards[c->guards_filled].first, GUARD_BYTE, GUARD_BYTES, s);
+}
+
+void check_guards(tr_als_ctx* c) {
+  std::vector<unsigned char> h(GUARD_BYTES);
+  for (auto& g : c->guards) {
+    if (hipMemcpy(h.data(), g.first, GUARD_BYTES, hipMemcpyDeviceToHost) != hipSuccess) {
+      (void)hipGetLastError();
+      continue;
+    }
+    for (size_t q = 0; q < GUARD_BYTES; ++q)
+      if (h[q] != GUARD_BYTE) {
+        g_overruns++;
+        fprintf(stderr, "tr_als: workspace buffer %d overrun (guard byte %zu written)\n", g.second, q);
+        break;
+      }
+  }
 }
 
 int64_t prod(const int64_t* d, int a, int b) {  // prod of dims[a..b)
@@ -439,6 +482,10 @@ size_t partial_bytes_needed(const XsCfg& x, int prec) {
 
 int ensure_shadow(tr_als_ctx* c, int prec) {
   hipStream_t s = c->stream;
+  struct Fill {   // guard bands of shadows allocated here, in stream order
+    tr_als_ctx* c; hipStream_t s;
+    ~Fill() { if (c->canary) fill_guards(c, s); }
+  } fill{c, s};
   if (prec == TR_BF16 && !c->bf16_ready) {
     if (!c->xbf16) {
       int rc = alloc(c, &c->xbf16, (size_t)c->numel * 2);
@@ -629,6 +676,7 @@ int ring_gemms(tr_als_ctx* c, const std::vector<int>& chain, MatView W, int64_t 
     const int64_t inner = (int64_t)c->R[k] * c->R[k];
     const int64_t cols = (int64_t)c->R[k + 1] * c->R[k + 1];
     double* out = (q + 1 == chain.size() && last_out) ? last_out : bufs[cur];
+    if (rows * cols > c->w_cap) return fail(c, TR_EINVAL, "internal: ring workspace too small");
     HIPCHK(c, launch_gemm64(rows, cols, inner, 1.0, W, gview(k), 0.0, nullptr, 0, out, rows, s));
     W.p = out; W.ld = rows; W.kind = 0;
     cur ^= 1;
@@ -860,6 +908,7 @@ int tr_als_destroy(tr_als_ctx* ctx) {
   }
   if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
   if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+  if (ctx->canary) check_guards(ctx);
   for (void* p : ctx->allocs) (void)hipFree(p);
   delete ctx;
   return TR_OK;
@@ -893,6 +942,8 @@ int trx_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ranks,
   tr_als_ctx* c = new tr_als_ctx();
   c->measure = o.measure;
   c->region = o.region;
+  static const bool env_canary = getenv("TR_ALS_CANARY") && getenv("TR_ALS_CANARY")[0] == '1';
+  c->canary = env_canary;
   c->region_cap = o.region_bytes;
   c->N = N;
   for (int k = 0; k < N; ++k) { c->dims[k] = dims[k]; c->R[k] = (int)ranks[k]; }
@@ -921,6 +972,14 @@ int trx_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ranks,
     maxI = std::max<int64_t>(maxI, dims[k]);
     maxRR = std::max<int64_t>(maxRR, (int64_t)c->R[k] * c->R[k + 1]);
     maxW = std::max<int64_t>(maxW, (int64_t)c->R[k] * c->R[k] * c->R[k + 1] * c->R[k + 1]);
+  }
+  // ring intermediates of mode m: R_{m+1}^2 x R_{k+1}^2 after the factor K_k
+  for (int m = 0; m < N; ++m) {
+    const int64_t a = (int64_t)c->R[(m + 1) % N] * c->R[(m + 1) % N];
+    for (int q = 2; q < N; ++q) {
+      const int64_t r = c->R[(m + q + 1) % N];
+      maxW = std::max<int64_t>(maxW, a * r * r);
+    }
   }
   int64_t maxY = 16;
   for (int m = 0; m < N; ++m) {
@@ -960,6 +1019,7 @@ int trx_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ranks,
   A((void**)&c->Y1, (size_t)maxY * 8);
   A((void**)&c->W1, (size_t)maxW * 8);
   if (N >= 4) A((void**)&c->Wpre, (size_t)maxW * 8);
+  c->w_cap = maxW;
   A((void**)&c->dpart, (size_t)c->nred * 8);
   A((void**)&c->fpart, (size_t)c->nred * 4);
   A((void**)&c->dscal, 8 * 8);
@@ -1056,6 +1116,7 @@ int trx_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ranks,
     c->err = std::string(what) + ": " + hipGetErrorString(e);
     return true;
   };
+  fill_guards(c, s);
   if (hipfail(hipMemsetAsync(c->status, 0, 16, s), "memset") ||
       (o.stream2 ? ((c->stream2 = o.stream2), (c->own_stream2 = false)) :
                    hipfail(hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking), "stream")) ||
@@ -1376,6 +1437,8 @@ const char* trx_status_text(int st) {
 }
 
 extern "C" {
+
+int tr_als_debug_overruns(void) { return g_overruns.load(); }
 
 int tr_als_profile_enable(tr_als_ctx* c, int enable) {
   if (!valid_ctx(c)) return TR_EINVAL;
