@@ -156,6 +156,12 @@ int tr_als_profile_read(tr_als_ctx* ctx, double* xstream_ms /*host*/, int64_t* l
 // reported on stderr).  Always 0 without TR_ALS_CANARY.
 int tr_als_debug_overruns(void);
 
+// Debugging aid.  Number of sweep graphs (one per precision and refinement
+// count) the context has captured and instantiated so far, or TR_EINVAL.  If
+// `note` (host, `note_len` bytes) is given it receives, NUL-terminated, why the
+// last capture was abandoned (empty if none was); sweeps then launch eagerly.
+int tr_als_debug_graphs(const tr_als_ctx* ctx, char* note /*host, may be NULL*/, int note_len);
+
 /* ------------------------------------------------------------------------ *
  * Planted test tensors generated on the device.
  *

@@ -39,6 +39,7 @@ _SIGS = {
     "tr_als_mode_regime": (ctypes.c_int, [_vp, ctypes.c_int]),
     "tr_als_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "tr_als_debug_overruns": (ctypes.c_int, []),
+    "tr_als_debug_graphs": (ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.c_int]),
     "tr_als_profile_read": (ctypes.c_int, [_vp, _dp, _i64p, _dp]),
 }
 

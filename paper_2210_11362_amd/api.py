@@ -109,6 +109,14 @@ class TRContext:
                 "tr_als_profile_read")
         return ms.value, n.value, b.value
 
+    def graphs(self):
+        """(number of captured sweep graphs, why the last capture was abandoned)."""
+        buf = ctypes.create_string_buffer(256)
+        r = C.lib().tr_als_debug_graphs(self._h, buf, len(buf))
+        if r < 0:
+            C.check(r, self._h, "tr_als_debug_graphs")
+        return r, buf.value.decode()
+
     def close(self):
         if getattr(self, "_h", None):
             C.lib().tr_als_destroy(self._h)

@@ -3,6 +3,9 @@
 // forward/backward substitution that runs 16 right-hand sides per workgroup
 // with L staged in LDS.  A non-positive or non-finite pivot latches
 // ST_SINGULAR; later steps see the status word and leave their outputs alone.
+#include <type_traits>
+#include <utility>
+
 #include "common.h"
 #include "../../include/tr_als.h"
 
@@ -243,115 +246,226 @@ __device__ __forceinline__ double pivot_recip(double d) {
   return fma(r, fma(-d, r, 1.0), r);
 }
 
-// S^{-1} of a symmetric positive definite S (n <= 16 * NBT) by the symmetric
-// sweep operator: sweeping pivot k of A sets
-//   A_ij -= A_ik A_kj / A_kk  (i, j != k),  A_ik = A_ki = A_ik / A_kk,  A_kk = -1 / A_kk,
-// and sweeping every pivot of S leaves -S^{-1}.  For SPD S every pivot is a
-// Schur-complement diagonal, hence positive; a pivot that is not (S not
-// positive definite in working precision) latches ST_SINGULAR.
-//
-// One workgroup of 16 x 16 threads holds the matrix in registers: thread
-// (ti, tj) owns A(16r + ti, 16c + tj) for the lower block triangle c <= r
-// (the upper halves of the diagonal blocks are scratch, never read).  Per
-// pivot the current column k is exchanged through a double-buffered LDS
-// vector, so each pivot costs one barrier.
-template <int NBT>
-__global__ __launch_bounds__(256) void spd_sweep_inv_kernel(const double* __restrict__ S, int n,
-                                                            double* __restrict__ Sinv, int* status) {
-  __shared__ double col[2][16 * NBT];
-  const int tid = threadIdx.x, ti = tid & 15, tj = tid >> 4;
-  if (*status != 0) return;
-  double a[NBT][NBT];
-#pragma unroll
-  for (int r = 0; r < NBT; ++r)
-#pragma unroll
-    for (int c = 0; c <= r; ++c) {
-      const int i = 16 * r + ti, j = 16 * c + tj;
-      a[r][c] = (i < n && j < n) ? S[i + (int64_t)n * j] : (i == j ? 1.0 : 0.0);
-    }
-  // column 0 (canonical entries (i, 0), i >= 0, owned by tj == 0)
-  if (tj == 0) {
-#pragma unroll
-    for (int r = 0; r < NBT; ++r) col[0][16 * r + ti] = a[r][0];
+// Lane exchanges of a double within a wave64.
+template <int P> __device__ __forceinline__ double row_bcast(double x) {   // lane (l & ~15) | P
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)u, 0x150 + P, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), 0x150 + P, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double lane_get(double x, int src) {             // lane src (any)
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+  const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)u);
+  const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(u >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double lane_uniform(double x, int src) {         // lane src, as a scalar
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+  const int lo = __builtin_amdgcn_readlane((int)u, src);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), src);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ f64x4 mma64(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <int I, int N, typename F> __device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
   }
-  int buf = 0;
+}
+
+constexpr int PST = 17;   // panel row stride in doubles (odd: spreads rows over the LDS banks)
+
+// S^{-1} of a symmetric positive definite S (n <= 16 * NBT) by the symmetric
+// sweep operator.  Sweeping pivot k of A sets
+//   A_ij -= A_ik A_kj / A_kk  (i, j != k),  A_ik = A_ik / A_kk,  A_kj = A_kj / A_kk,  A_kk = -1 / A_kk,
+// and sweeping every pivot of S leaves -S^{-1}.  Sweeping the 16 pivots of a
+// diagonal block D = A_kk at once is the block form
+//   A_ij -= A_ik D^{-1} A_kj,  A_ik = A_ik D^{-1},  A_kj = D^{-1} A_kj,  A_kk = -D^{-1},
+// which is what this kernel does, block by block.  For SPD S every scalar
+// pivot met inside D is a Schur-complement diagonal, hence positive; one that
+// is not (S not positive definite in working precision) latches ST_SINGULAR.
+//
+// One workgroup of four waves.  The lower block triangle lives in registers
+// as 16x16 FP64 MFMA accumulator tiles (lane l, element v holds row
+// (l >> 4) + 4v, column l & 15); wave W owns block rows W and NBT-1-W, fixed
+// at compile time so that each wave's update is straight-line MFMA code.  Per
+// block step the owners publish block column k to LDS (one barrier); every
+// wave then sweeps D in its own registers (pivot column by DPP row broadcast,
+// pivot row by bpermute, no barrier) and applies the block update to its
+// tiles.  D^{-1} is symmetric, so the same registers serve as its A-operand
+// and B-operand fragments, and (-D^{-1}) A_kr computed in the accumulator
+// layout is already the A-operand of -A_rk D^{-1}.
+template <int NBT, int W>
+__device__ __forceinline__ void spd_block_inv_wave(const double* __restrict__ S, int n, double* __restrict__ Sinv,
+                                                   int* status, double* panel, int lane) {
+  constexpr int NP = 16 * NBT;
+  constexpr int ROW[2] = {W, NBT - 1 - W};
+  constexpr bool HAS[2] = {W < NBT, NBT - 1 - W > W};
+  constexpr int MAXR = HAS[1] ? ROW[1] : HAS[0] ? ROW[0] : -1;   // highest block row owned
+  const int g = lane >> 4, c16 = lane & 15;
+  f64x4 t[2][NBT];
+  static_for<0, 2>([&](auto sc) {
+    constexpr int s = decltype(sc)::value;
+    if constexpr (HAS[s]) {
 #pragma unroll
-  for (int rk = 0; rk < NBT; ++rk) {
-    const int tend = min(16, n - 16 * rk);
-    for (int tk = 0; tk < tend; ++tk) {
-      const int k = 16 * rk + tk;
-      __syncthreads();
-      const double* cb = col[buf];
-      const double d = cb[k];
-      if (!(d > 0.0) || !isfinite(d)) {   // same value in every thread: uniform exit
-        if (tid == 0) atomicOr(status, ST_SINGULAR);
-        return;
+      for (int c = 0; c <= ROW[s]; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = 16 * ROW[s] + g + 4 * v, j = 16 * c + c16;   // padded to the identity
+          const double x = S[min(i, n - 1) + (int64_t)n * min(j, n - 1)];
+          t[s][c][v] = (i < n && j < n) ? x : (i == j ? 1.0 : 0.0);
+        }
+    }
+  });
+  // block column k of the current matrix: P[i][q] = A(i, 16k + q), from the
+  // tiles (r, k), r >= k, and (by symmetry) the tiles (k, c), c < k
+  auto publish = [&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    double* P = panel + (k & 1) * NP * PST;
+    static_for<0, 2>([&](auto sc) {
+      constexpr int s = decltype(sc)::value, r = ROW[s];
+      if constexpr (HAS[s] && r >= k) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) P[(16 * r + g + 4 * v) * PST + c16] = t[s][k][v];
       }
-      const double p = pivot_recip(d);
-      double x[NBT], v[NBT];
+      if constexpr (HAS[s] && r == k) {
 #pragma unroll
-      for (int r = 0; r < NBT; ++r) {
-        x[r] = cb[16 * r + ti];
-        v[r] = cb[16 * r + tj] * p;
+        for (int c = 0; c < k; ++c)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) P[(16 * c + c16) * PST + g + 4 * v] = t[s][c][v];
       }
+    });
+  };
+  bool stop = false;
+  auto step = [&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    if (stop) return;
+    __syncthreads();
+    const double* P = panel + (k & 1) * NP * PST;
+    // D (lower triangle mirrored) in the accumulator layout, swept in place to -D^{-1}
+    double a[4];
 #pragma unroll
-      for (int r = 0; r < NBT; ++r)
+    for (int v = 0; v < 4; ++v) {
+      const int row = g + 4 * v;
+      const double lo = P[(16 * k + row) * PST + c16], up = P[(16 * k + c16) * PST + row];
+      a[v] = row >= c16 ? lo : up;
+    }
+    bool bad = false;
+    static_for<0, 16>([&](auto pc) {
+      constexpr int p = decltype(pc)::value, pv = p >> 2, pg = p & 3;
+      const double app = lane_uniform(a[pv], (pg << 4) | p);
+      bad |= !(app > 0.0) || !isfinite(app);
+      const double rp = pivot_recip(app);
+      double colv[4];   // A(g + 4v, p): lane p of this lane's 16-lane row
 #pragma unroll
-        for (int c = 0; c <= r; ++c) a[r][c] = fma(-x[r], v[c], a[r][c]);
-      // column k, rows i >= k: A_ik / A_kk, and -1 / A_kk on the diagonal
-      if (tj == tk) {
+      for (int v = 0; v < 4; ++v) colv[v] = row_bcast<p>(a[v]);
+      const double rowv = lane_get(a[pv], (pg << 4) | c16);   // A(p, c16)
+      // column p: A(i, p) / A_pp; row p: A(p, j) / A_pp; diagonal: -1 / A_pp
+      const bool colp = c16 == p;
+      const double tsel = colp ? -rp : rowv * rp;
 #pragma unroll
-        for (int r = rk; r < NBT; ++r) a[r][rk] = (16 * r + ti == k) ? -p : x[r] * p;
+      for (int v = 0; v < 4; ++v) {
+        double nv = fma(-colv[v], tsel, colp ? 0.0 : a[v]);
+        if (g + 4 * v == p) nv = tsel;
+        a[v] = nv;
       }
-      // row k, columns j < k: A_jk / A_kk
-      if (ti == tk) {
+      __builtin_amdgcn_sched_barrier(0);   // one pivot at a time: keeps the live ranges short
+    });
+    // the same pivots in every wave: uniform exit
+    if (__builtin_amdgcn_readfirstlane((int)bad)) {
+      if (W == 0 && lane == 0) atomicOr(status, ST_SINGULAR);
+      stop = true;
+      return;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // B-operand fragments of block column k: A_kc(4q + g, c16) = A(16c + c16, 16k + 4q + g)
+    auto frag = [&](int c, double* f) {
 #pragma unroll
-        for (int c = 0; c <= rk; ++c)
-          if (16 * c + tj < k) a[rk][c] = v[c];
-      }
-      // publish column k + 1 into the other buffer: entries (i, k+1) with
-      // i >= k+1 from its column owners, (k+1, j) with j < k+1 from its row owners
-      const int k1 = k + 1;
-      double* cn = col[buf ^ 1];
-      if (k1 < n) {
-        if (tk + 1 < 16) {
-          const int t1 = tk + 1;
-          if (tj == t1) {
+      for (int q = 0; q < 4; ++q) f[q] = P[(16 * c + c16) * PST + 4 * q + g];
+    };
+    // per owned row r: its fragments and (-D^{-1}) A_kr, whose element q is the
+    // A-operand fragment q of -A_rk D^{-1}
+    double pr[2][4];
+    f64x4 nw[2];
+    static_for<0, 2>([&](auto sc) {
+      constexpr int s = decltype(sc)::value, r = ROW[s];
+      if constexpr (HAS[s]) {
+        frag(r, pr[s]);
+        nw[s] = f64x4{0, 0, 0, 0};
+        if constexpr (r != k) {
 #pragma unroll
-            for (int r = rk; r < NBT; ++r)
-              if (16 * r + ti >= k1) cn[16 * r + ti] = a[r][rk];
-          }
-          if (ti == t1) {
-#pragma unroll
-            for (int c = 0; c <= rk; ++c)
-              if (16 * c + tj < k1) cn[16 * c + tj] = a[rk][c];
-          }
-        } else if (rk + 1 < NBT) {
-          if (tj == 0) {
-#pragma unroll
-            for (int r = rk + 1; r < NBT; ++r) cn[16 * r + ti] = a[r][rk + 1];
-          }
-          if (ti == 0) {
-#pragma unroll
-            for (int c = 0; c <= rk; ++c) cn[16 * c + tj] = a[rk + 1][c];
-          }
+          for (int q = 0; q < 4; ++q) nw[s] = mma64(a[q], pr[s][q], nw[s]);
         }
       }
-      buf ^= 1;
+    });
+    // column by column, both owned rows
+    static_for<0, MAXR + 1>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      double pc[4];
+      frag(c, pc);
+      static_for<0, 2>([&](auto sc) {
+        constexpr int s = decltype(sc)::value, r = ROW[s];
+        if constexpr (HAS[s] && c <= r) {
+          if constexpr (r == k && c == k) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) t[s][c][v] = a[v];
+          } else if constexpr (r == k) {            // A_kc <- D^{-1} A_kc
+            f64x4 acc = {0, 0, 0, 0};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc = mma64(a[q], pc[q], acc);
+            t[s][c] = -acc;
+          } else if constexpr (c == k) {            // A_rk <- A_rk D^{-1}
+            f64x4 acc = {0, 0, 0, 0};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc = mma64(pr[s][q], a[q], acc);
+            t[s][c] = -acc;
+          } else {                                  // A_rc <- A_rc - A_rk D^{-1} A_kc
+#pragma unroll
+            for (int q = 0; q < 4; ++q) t[s][c] = mma64(nw[s][q], pc[q], t[s][c]);
+          }
+        }
+      });
+    });
+    if constexpr (k + 1 < NBT) publish(std::integral_constant<int, k + 1>{});
+  };
+  publish(std::integral_constant<int, 0>{});
+  static_for<0, NBT>(step);
+  if (stop) return;
+  // -A = S^{-1}: write both triangles from the lower entries
+  static_for<0, 2>([&](auto sc) {
+    constexpr int s = decltype(sc)::value, r = ROW[s];
+    if constexpr (HAS[s]) {
+#pragma unroll
+      for (int c = 0; c <= r; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = 16 * r + g + 4 * v, j = 16 * c + c16;
+          if (i < n && j <= i) {
+            const double val = -t[s][c][v];
+            Sinv[i + (int64_t)n * j] = val;
+            Sinv[j + (int64_t)n * i] = val;
+          }
+        }
     }
+  });
+}
+
+template <int NBT>
+__global__ __launch_bounds__(256) void spd_block_inv_kernel(const double* __restrict__ S, int n,
+                                                            double* __restrict__ Sinv, int* status) {
+  __shared__ double panel[2 * 16 * NBT * PST];
+  if (*status != 0) return;
+  const int lane = threadIdx.x & 63;
+  switch (__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6))) {   // wave index, uniform per wave
+    case 0: spd_block_inv_wave<NBT, 0>(S, n, Sinv, status, panel, lane); break;
+    case 1: spd_block_inv_wave<NBT, 1>(S, n, Sinv, status, panel, lane); break;
+    case 2: spd_block_inv_wave<NBT, 2>(S, n, Sinv, status, panel, lane); break;
+    default: spd_block_inv_wave<NBT, 3>(S, n, Sinv, status, panel, lane); break;
   }
-  // -A = S^{-1}: write both triangles from the canonical entries
-#pragma unroll
-  for (int r = 0; r < NBT; ++r)
-#pragma unroll
-    for (int c = 0; c <= r; ++c) {
-      const int i = 16 * r + ti, j = 16 * c + tj;
-      if (i < n && j <= i) {
-        const double v = -a[r][c];
-        Sinv[i + (int64_t)n * j] = v;
-        Sinv[j + (int64_t)n * i] = v;
-      }
-    }
 }
 
 }  // namespace
@@ -384,7 +498,7 @@ hipError_t launch_spd_inverse(const double* S, int n, double* Sinv, int* status,
   const int nbt = (n + 15) / 16;
   switch (nbt) {
 #define SPD_INV_CASE(B) \
-  case B: hipLaunchKernelGGL(spd_sweep_inv_kernel<B>, dim3(1), dim3(256), 0, s, S, n, Sinv, status); break;
+  case B: hipLaunchKernelGGL(spd_block_inv_kernel<B>, dim3(1), dim3(256), 0, s, S, n, Sinv, status); break;
     SPD_INV_CASE(1) SPD_INV_CASE(2) SPD_INV_CASE(3) SPD_INV_CASE(4)
     SPD_INV_CASE(5) SPD_INV_CASE(6) SPD_INV_CASE(7) SPD_INV_CASE(8)
 #undef SPD_INV_CASE

@@ -30,6 +30,7 @@ struct Plan {
   int64_t gK = 1, gM = 1;     // group size and rows of the intermediate
   int gC = 1, gRu = 1, gRc = 1;
   bool reuse_prev = false;    // same group table as the previous mode of the sweep
+  bool reuse_y = false;       // and the same reduced stage-1 result, still in Y0
   struct Step { int64_t lo, I, hi; int Ru, Rc, core, side; };
   std::vector<Step> steps;
 };
@@ -47,6 +48,7 @@ struct tr_als_ctx {
   std::vector<double*> user_cores;
   hipStream_t stream = nullptr;
   hipStream_t stream2 = nullptr;             // coefficient-matrix branch (default priority)
+  hipStream_t cap_stream = nullptr;          // private stream the sweep graphs are captured on
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   double* Sinv = nullptr;
   double* rdiag = nullptr;                   // reciprocal pivots of the Cholesky factor
@@ -62,6 +64,7 @@ struct tr_als_ctx {
   int64_t qpart_elems = 0;
   // captured sweeps, one per (precision, refinement steps)
   hipGraphExec_t graphs[4][5] = {{nullptr}};
+  std::string graph_note;   // why the last sweep capture was abandoned (empty if none)
   bool graphs_ok = true;
   double* cores[TR_MAXN] = {nullptr};
   double* gram[TR_MAXN] = {nullptr};
@@ -529,10 +532,34 @@ int ensure_shadow(tr_als_ctx* c, int prec) {
 // built from the sweep releases the contraction before the branch.
 using Hook = std::function<int()>;
 
+// Stage 2: absorb the remaining cores into the reduced stage-1 result `cur`
+// (Y0), ping-ponging through Y1 / Y0, the last step writing M.
+int absorb_steps(tr_als_ctx* c, const Plan& p, double* cur, double* Mout, hipStream_t s) {
+  for (size_t q = 0; q < p.steps.size(); ++q) {
+    const Plan::Step& st = p.steps[q];
+    const bool last = q + 1 == p.steps.size();
+    double* nxt = last ? Mout : (cur == c->Y0 ? c->Y1 : c->Y0);
+    HIPCHK(c, launch_absorb(cur, st.lo, st.I, st.hi, st.Ru, st.Rc, c->cores[st.core], c->R[st.core],
+                            c->R[st.core + 1], st.side, last ? 1 : 0, nxt, (double*)c->partial, c->partial_bytes,
+                            s));
+    cur = nxt;
+  }
+  return TR_OK;
+}
+
 int compute_mttsp_two_stage(tr_als_ctx* c, int m, int prec, double* Mout, bool in_sweep, const Hook& after_main) {
   hipStream_t s = c->stream;
   const Plan& p = c->plan[m];
   const bool reuse = in_sweep && p.reuse_prev && prec != TR_FP8;
+  if (reuse && p.reuse_y) {
+    // the previous mode contracted X with this same group table and left the
+    // reduced result in Y0 (identical bits): only the absorptions differ
+    if (after_main) {
+      const int hr = after_main();
+      if (hr) return hr;
+    }
+    return absorb_steps(c, p, c->Y0, Mout, s);
+  }
   // groups of one or two cores: operand table straight from the cores
   const bool direct = prec != TR_FP8 && (p.gcores.size() == 1 || p.gcores.size() == 2) && c->R[p.gcores[0]] <= 24;
   int rc = (reuse || direct) ? TR_OK : build_table(c, p.gcores, 1, c->F1);
@@ -587,16 +614,7 @@ int compute_mttsp_two_stage(tr_als_ctx* c, int m, int prec, double* Mout, bool i
     HIPCHK(c, launch_bond_to_M(cur, p.I, p.gRu, p.gRc, Mout, s));
     return TR_OK;
   }
-  for (size_t q = 0; q < p.steps.size(); ++q) {
-    const Plan::Step& st = p.steps[q];
-    const bool last = q + 1 == p.steps.size();
-    double* nxt = last ? Mout : (cur == c->Y0 ? c->Y1 : c->Y0);
-    HIPCHK(c, launch_absorb(cur, st.lo, st.I, st.hi, st.Ru, st.Rc, c->cores[st.core], c->R[st.core],
-                            c->R[st.core + 1], st.side, last ? 1 : 0, nxt, (double*)c->partial, c->partial_bytes,
-                            s));
-    cur = nxt;
-  }
-  return TR_OK;
+  return absorb_steps(c, p, cur, Mout, s);
 }
 
 // M_n = X_[n] G^{!=n}_[2] for the context's current cores (tables + X stream +
@@ -897,7 +915,7 @@ int tr_als_destroy(tr_als_ctx* ctx) {
     delete ctx;
     return TR_OK;
   }
-  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  (void)hipStreamSynchronize(ctx->stream);   // the caller's stream, possibly the default one
   for (auto& e : ctx->evs) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
   for (auto& row : ctx->graphs)
     for (auto& g : row)
@@ -906,6 +924,7 @@ int tr_als_destroy(tr_als_ctx* ctx) {
     (void)hipStreamSynchronize(ctx->stream2);
     if (ctx->own_stream2) (void)hipStreamDestroy(ctx->stream2);
   }
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
   if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
   if (ctx->canary) check_guards(ctx);
@@ -964,6 +983,10 @@ int trx_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ranks,
     Plan& b = c->plan[m];
     b.reuse_prev = a.regime == 1 && b.regime == 1 && a.gcores == b.gcores &&
                    std::find(b.gcores.begin(), b.gcores.end(), m - 1) == b.gcores.end();
+    // X and the table being the same, so is the stage-1 result: mode m-1
+    // leaves it in Y0 when its absorptions take at most two steps (the first
+    // writes Y1 or M, the second M)
+    b.reuse_y = b.reuse_prev && !a.steps.empty() && a.steps.size() <= 2 && !b.steps.empty();
   }
 
   // workspace sizes
@@ -1288,21 +1311,34 @@ static hipGraphExec_t sweep_graph(tr_als_ctx* c, int prec, int refine) {
   if (!c->graphs_ok || c->prof || prec == TR_FP8 || c->variant != TR_NE) return nullptr;
   if (c->graphs[prec][refine]) return c->graphs[prec][refine];
   if (ensure_shadow(c, prec) != TR_OK) return nullptr;
-  hipGraph_t g = nullptr;
-  if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+  // The caller's stream may be the legacy default stream, which cannot be
+  // captured: capture on a private stream instead (capturing runs nothing)
+  // and launch the graph onto the caller's stream.
+  hipError_t e = hipSuccess;
+  if (!c->cap_stream) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) {
     (void)hipGetLastError();
     c->graphs_ok = false;
+    c->graph_note = std::string("begin capture: ") + hipGetErrorString(e);
     return nullptr;
   }
+  hipGraph_t g = nullptr;
+  hipStream_t user = c->stream;
+  c->stream = c->cap_stream;
   int rc = TR_OK;
   for (int m = 0; m < c->N && rc == TR_OK; ++m) rc = update_mode(c, m, prec, refine, true);
-  hipError_t e = hipStreamEndCapture(c->stream, &g);
+  const std::string mode_err = c->err;
+  c->stream = user;
+  e = hipStreamEndCapture(c->cap_stream, &g);
   hipGraphExec_t ex = nullptr;
   if (rc == TR_OK && e == hipSuccess && g) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
   if (g) (void)hipGraphDestroy(g);
   if (rc != TR_OK || e != hipSuccess || !ex) {
     (void)hipGetLastError();
     c->graphs_ok = false;
+    c->graph_note = rc != TR_OK ? "mode update under capture: " + mode_err
+                                : std::string("end capture / instantiate: ") + hipGetErrorString(e);
     c->err.clear();
     return nullptr;
   }
@@ -1439,6 +1475,19 @@ const char* trx_status_text(int st) {
 extern "C" {
 
 int tr_als_debug_overruns(void) { return g_overruns.load(); }
+
+int tr_als_debug_graphs(const tr_als_ctx* c, char* note, int note_len) {
+  if (!valid_ctx(c)) return TR_EINVAL;
+  if (note && note_len > 0) {
+    const size_t k = std::min((size_t)(note_len - 1), c->graph_note.size());
+    std::memcpy(note, c->graph_note.data(), k);
+    note[k] = 0;
+  }
+  int count = 0;
+  for (const auto& row : c->graphs)
+    for (hipGraphExec_t ex : row) count += ex != nullptr;
+  return count;
+}
 
 int tr_als_profile_enable(tr_als_ctx* c, int enable) {
   if (!valid_ctx(c)) return TR_EINVAL;

@@ -85,6 +85,30 @@ def test_mttsp(dims, ranks, prec, xdt, tol, force_regime):
     ctx.close()
 
 
+# ranks whose products R_nR_{n+1} give coefficient matrices of 1 to 8 blocks of
+# 16 (n = 12..128, ragged and full last blocks) for the in-register inverse
+INV_SHAPES = [
+    ((20, 24, 30), (4, 8, 16)),    # n = 32, 128, 64
+    ((26, 22, 18), (3, 11, 5)),    # n = 33, 55, 15
+    ((30, 26, 22), (8, 9, 4)),     # n = 72, 36, 32
+    ((30, 28, 26), (9, 9, 10)),    # n = 81, 90, 90
+    ((24, 40, 28), (2, 6, 10)),    # n = 12, 60, 20
+]
+
+
+@pytest.mark.parametrize("dims,ranks", INV_SHAPES, ids=[str(s[1]) for s in INV_SHAPES])
+def test_update_f64_every_inverse_block_count(dims, ranks):
+    say(f"[update f64, inverse sizes] dims={dims} ranks={ranks}")
+    X, init = _data(dims, ranks, 5)
+    ctx, dev = _ctx(to_dev_flat(X), init, dims, ranks)
+    ref, _ = O.tr_als(X, init, 2)
+    ctx.sweep(2, "f64", refine=1)
+    got = cores_from_dev(dev, dims, ranks)
+    for a, b in zip(got, ref):
+        assert rel(a, b) <= 1e-10
+    ctx.close()
+
+
 @pytest.mark.parametrize("dims,ranks", SHAPES[:4], ids=[str(s[0]) for s in SHAPES[:4]])
 def test_update_f64_matches_regular_als(dims, ranks):
     say(f"[update f64] dims={dims} ranks={ranks}")
@@ -196,6 +220,9 @@ def test_graph_replays_match_eager(monkeypatch):
             b = cores_from_dev(dg, w.dims, w.ranks)
             for x, y in zip(a, b):
                 assert np.array_equal(x, y), (prec, rep)
+    assert eager.graphs()[0] == 0
+    n, note = graph.graphs()
+    assert n == 2 and note == "", (n, note)   # f32 and bf16 sweeps were captured, not run eagerly
     eager.close()
     graph.close()
 
