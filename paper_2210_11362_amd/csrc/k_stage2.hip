@@ -15,7 +15,7 @@ namespace {
 // order).  A workgroup takes a block of 64 rows x 16 columns of one tile:
 // partial rows are read as 16-column runs (row-major tiles), summed,
 // transposed through LDS and written as 64-row runs of the column-major Y.
-// Each thread has four elements, all their loads in flight together.
+// Each thread has four elements.
 template <int P>
 __global__ __launch_bounds__(256) void xg_reduce_kernel(XgArgs g, int MT, double out_scale, double* Y, int* status) {
   using part_t = typename std::conditional<P == TR_F64, double, float>::type;
@@ -30,32 +30,29 @@ __global__ __launch_bounds__(256) void xg_reduce_kernel(XgArgs g, int MT, double
   const int mt = (int)(tile % g.n_mt), nt = (int)(tile / g.n_mt);
   const part_t* base = reinterpret_cast<const part_t*>(g.partial) + tile * tsz + (int64_t)rb * NT + cb;
   const size_t ss = (size_t)(ntile * tsz);
-  double acc[4][4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-#pragma unroll
-    for (int u = 0; u < 4; ++u) acc[q][u] = 0.0;
-  int sp = 0;
-  for (; sp + 4 <= g.nsplit; sp += 4) {
+  // up to SB splits of all four elements in flight at once (clamped indices:
+  // the surplus loads repeat the last split and are not summed), summed in
+  // split order
+  constexpr int SB = 12;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int sp0 = 0; sp0 < g.nsplit; sp0 += SB) {
+    part_t v[4][SB];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = threadIdx.x + 256 * q, row = e >> 4, col = e & 15;
       const part_t* p = base + (int64_t)row * NT + col;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc[q][u] += (double)p[(sp + u) * ss];
+      for (int u = 0; u < SB; ++u) v[q][u] = p[(size_t)min(sp0 + u, g.nsplit - 1) * ss];
     }
-  }
-  for (; sp < g.nsplit; ++sp) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = threadIdx.x + 256 * q, row = e >> 4, col = e & 15;
-      acc[q][0] += (double)base[(int64_t)row * NT + col + sp * ss];
-    }
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int u = 0; u < SB; ++u) acc[q] += sp0 + u < g.nsplit ? (double)v[q][u] : 0.0;
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int e = threadIdx.x + 256 * q, row = e >> 4, col = e & 15;
-    tl[col][row] = ((acc[q][0] + acc[q][1]) + (acc[q][2] + acc[q][3])) * out_scale;
+    tl[col][row] = acc[q] * out_scale;
   }
   __syncthreads();
   bool bad = false;
@@ -91,47 +88,53 @@ __global__ void table_to_bt_kernel(const double* T, int64_t K, int C, int Crows,
 // Operand table of a group of one or two cores straight from the cores (no
 // FP64 table in between): entry k = j + I0*i of the partial subchain
 // G0(:, j, :) G1(:, i, :) (one core: G0(:, k, :)), column r + Rl*c, written
-// transposed and zero-padded like table_to_bt_kernel.  A thread forms the Rl
-// entries (r, c) of one k from one column of G1 and the slice G0(:, j, :),
-// summing over the inner bond in increasing order in FP64; blockIdx.y = c,
-// and the last y row writes the padding rows C..Crows-1.
-template <typename O, int RB>
+// transposed and zero-padded like table_to_bt_kernel.  A workgroup forms the
+// Rl x 64 entries (r, k) of one c and 64 consecutive k, summing over the
+// inner bond in increasing order in FP64, with r fastest across lanes so that
+// the reads of G0 (r fastest in memory) are contiguous; the tile goes through
+// LDS and is stored with k fastest.  blockIdx.y = c; the last y row writes the
+// padding rows C..Crows-1.
+constexpr int GBT_K = 64;
+template <typename O>
 __global__ __launch_bounds__(256) void group_bt_kernel(const double* G0, int Rl, int64_t I0, int Rm,
                                                        const double* G1, int64_t I1, int two, int64_t K, int C,
                                                        int Crows, int64_t ldb, O* Bt) {
-  const int c = blockIdx.y, Rc = C / Rl;
+  extern __shared__ double tile[];   // [Rl][GBT_K + 1]
+  const int c = blockIdx.y, Rc = C / Rl, tid = threadIdx.x;
+  const int64_t k0 = (int64_t)blockIdx.x * GBT_K;
   auto put = [&](int col, int64_t k, double v) {
     if constexpr (std::is_same<O, __bf16>::value) Bt[col * ldb + k] = (__bf16)(float)v;
     else Bt[col * ldb + k] = (O)v;
   };
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ldb; k += (int64_t)gridDim.x * blockDim.x) {
-    if (c == Rc) {   // padding rows
-      for (int col = C; col < Crows; ++col) put(col, k, 0.0);
-      continue;
+  if (c == Rc) {   // padding rows
+    for (int e = tid; e < (Crows - C) * GBT_K; e += 256) {
+      const int col = C + e / GBT_K, kk = e % GBT_K;
+      if (k0 + kk < ldb) put(col, k0 + kk, 0.0);
     }
-    double acc[RB];
-#pragma unroll
-    for (int r = 0; r < RB; ++r) acc[r] = 0.0;
+    return;
+  }
+  for (int e = tid; e < Rl * GBT_K; e += 256) {
+    const int r = e % Rl, kk = e / Rl;
+    const int64_t k = k0 + kk;
+    double acc = 0.0;
     if (k < K) {
       if (two) {
         const int64_t j = k % I0, i = k / I0;
+        const double* g0 = G0 + r + (int64_t)Rl * j;
         const double* g1 = G1 + (int64_t)Rm * (i + I1 * c);
-        const double* g0 = G0 + (int64_t)Rl * j;
-#pragma unroll 5
-        for (int m = 0; m < Rm; ++m) {   // unrolled: the loads of several m in flight together
-          const double b = g1[m];
-          const double* g0m = g0 + (int64_t)Rl * I0 * m;
-#pragma unroll
-          for (int r = 0; r < RB; ++r) acc[r] = fma(g0m[r < Rl ? r : 0], b, acc[r]);
-        }
+        const int64_t st = (int64_t)Rl * I0;
+#pragma unroll 10
+        for (int m = 0; m < Rm; ++m) acc = fma(g0[st * m], g1[m], acc);
       } else {
-#pragma unroll
-        for (int r = 0; r < RB; ++r) acc[r] = G0[(r < Rl ? r : 0) + (int64_t)Rl * (k + I0 * c)];
+        acc = G0[r + (int64_t)Rl * (k + I0 * c)];
       }
     }
-#pragma unroll
-    for (int r = 0; r < RB; ++r)
-      if (r < Rl) put(r + Rl * c, k, acc[r]);
+    tile[r * (GBT_K + 1) + kk] = acc;
+  }
+  __syncthreads();
+  for (int e = tid; e < Rl * GBT_K; e += 256) {
+    const int r = e / GBT_K, kk = e % GBT_K;
+    if (k0 + kk < ldb) put(r + Rl * c, k0 + kk, tile[r * (GBT_K + 1) + kk]);
   }
 }
 
@@ -444,22 +447,21 @@ hipError_t launch_table_to_bt(const double* T, int64_t K, int C, int Crows, int6
 hipError_t launch_group_bt(const double* G0, int Rl, int64_t I0, int Rm, const double* G1, int64_t I1, int two,
                            int64_t K, int C, int Crows, int64_t ldb, int prec, void* Bt, hipStream_t s) {
   if (Rl > 24) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)std::min<int64_t>(cdiv(ldb, 256), 1024), (unsigned)(C / Rl + 1));
-  auto go = [&](auto* out, auto rb) {
-    constexpr int RB = decltype(rb)::value;
-    using O = std::remove_pointer_t<decltype(out)>;
-    hipLaunchKernelGGL((group_bt_kernel<O, RB>), grid, dim3(256), 0, s, G0, Rl, I0, Rm, G1, I1, two, K, C, Crows, ldb,
-                       out);
-  };
-  auto by_rank = [&](auto* out) {
-    if (Rl <= 8) go(out, std::integral_constant<int, 8>());
-    else if (Rl <= 16) go(out, std::integral_constant<int, 16>());
-    else go(out, std::integral_constant<int, 24>());
-  };
+  const dim3 grid((unsigned)cdiv(ldb, GBT_K), (unsigned)(C / Rl + 1));
+  const size_t lds = (size_t)Rl * (GBT_K + 1) * sizeof(double);
   switch (prec) {
-    case TR_F64: by_rank((double*)Bt); break;
-    case TR_F32: by_rank((float*)Bt); break;
-    case TR_BF16: by_rank((__bf16*)Bt); break;
+    case TR_F64:
+      hipLaunchKernelGGL(group_bt_kernel<double>, grid, dim3(256), lds, s, G0, Rl, I0, Rm, G1, I1, two, K, C, Crows, ldb,
+                         (double*)Bt);
+      break;
+    case TR_F32:
+      hipLaunchKernelGGL(group_bt_kernel<float>, grid, dim3(256), lds, s, G0, Rl, I0, Rm, G1, I1, two, K, C, Crows, ldb,
+                         (float*)Bt);
+      break;
+    case TR_BF16:
+      hipLaunchKernelGGL(group_bt_kernel<__bf16>, grid, dim3(256), lds, s, G0, Rl, I0, Rm, G1, I1, two, K, C, Crows,
+                         ldb, (__bf16*)Bt);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
