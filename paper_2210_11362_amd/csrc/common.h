@@ -92,6 +92,9 @@ hipError_t launch_gemm64(int64_t M, int64_t N, int64_t K, double alpha, MatView 
                          const double* Cin, int64_t ldcin, double* C, int64_t ldc, hipStream_t s,
                          int* finite_status = nullptr);
 hipError_t launch_realign_S(MatView W, int Ra, int Rb, double* S, hipStream_t s);
+// The last ring GEMM W = A B (Rb^2 x Ra^2, inner K) stored straight into S_n<2>
+// with launch_realign_S's map.
+hipError_t launch_gemm64_realign(int64_t K, MatView A, MatView B, int Ra, int Rb, double* S, hipStream_t s);
 hipError_t launch_chol(const double* S, int n, double* L, double* LT, double* work, int* status, hipStream_t s);
 bool solve_in_lds(int n);
 // S^{-1} of an SPD matrix with n <= 128 by the symmetric sweep operator (one

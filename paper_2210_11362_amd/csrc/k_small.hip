@@ -227,9 +227,11 @@ __device__ __forceinline__ double view_at(const MatView& v, int64_t r, int64_t c
   return v.p[(b + Rl * cc) + (int64_t)Rl * Rr * (b2 + Rl * c2)];
 }
 
+// With Ra > 0 the result W (Rb^2 x Ra^2) is stored realigned as S_n<2>
+// (realign_S_kernel's map) instead of column-major with ldc.
 __global__ __launch_bounds__(256) void gemm64_kernel(int64_t M, int64_t N, int64_t K, double alpha, MatView A,
                                                      MatView B, double beta, const double* Cin, int64_t ldcin,
-                                                     double* C, int64_t ldc, int* finite_status) {
+                                                     double* C, int64_t ldc, int* finite_status, int Ra, int Rb) {
   // one 16x16 block of C per workgroup; the 4 waves split the K range
   __shared__ double red[4][64][4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -255,7 +257,12 @@ __global__ __launch_bounds__(256) void gemm64_kernel(int64_t M, int64_t N, int64
       if (row < M && col < N) {
         double x = alpha * ((red[0][lane][v] + red[1][lane][v]) + (red[2][lane][v] + red[3][lane][v]));
         if (beta != 0.0) x += beta * Cin[row + ldcin * col];
-        C[row + ldc * col] = x;
+        if (Ra > 0) {   // W(b + Rb*b2, a + Ra*a2) -> S(a + Ra*b, a2 + Ra*b2)
+          const int64_t b = row % Rb, b2 = row / Rb, a = col % Ra, a2 = col / Ra, RR = (int64_t)Ra * Rb;
+          C[(a + Ra * b) + RR * (a2 + Ra * b2)] = x;
+        } else {
+          C[row + ldc * col] = x;
+        }
         if (finite_status && !isfinite(x)) atomicOr(finite_status, ST_NONFINITE);
       }
     }
@@ -710,7 +717,15 @@ hipError_t launch_gemm64(int64_t M, int64_t N, int64_t K, double alpha, MatView 
                          int* finite_status) {
   const int64_t nblk = cdiv(M, 16) * cdiv(N, 16);
   hipLaunchKernelGGL(gemm64_kernel, dim3((unsigned)nblk), dim3(256), 0, s, M, N, K, alpha, A, B, beta, Cin, ldcin, C,
-                     ldc, finite_status);
+                     ldc, finite_status, 0, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm64_realign(int64_t K, MatView A, MatView B, int Ra, int Rb, double* S, hipStream_t s) {
+  const int64_t M = (int64_t)Rb * Rb, N = (int64_t)Ra * Ra;
+  const int64_t nblk = cdiv(M, 16) * cdiv(N, 16);
+  hipLaunchKernelGGL(gemm64_kernel, dim3((unsigned)nblk), dim3(256), 0, s, M, N, K, 1.0, A, B, 0.0,
+                     (const double*)nullptr, (int64_t)0, S, M, (int*)nullptr, Ra, Rb);
   return hipGetLastError();
 }
 

@@ -680,8 +680,9 @@ int compute_mttsp(tr_als_ctx* c, int m, int prec, double* Mout, bool in_sweep = 
 // order >= 4 the prefix K_{m+1} ... K_{m-2} (it excludes the cores of modes
 // m-1 and m) is formed by the previous mode's branch (ring_prefix), so only
 // the last factor, refreshed by that mode, is multiplied here.
+// With S_out the last GEMM stores its result realigned into S_out (mode m).
 int ring_gemms(tr_als_ctx* c, const std::vector<int>& chain, MatView W, int64_t rows, double* last_out,
-               hipStream_t s) {
+               hipStream_t s, double* S_out = nullptr, int m = 0) {
   auto gview = [&](int k) {
     MatView v;
     v.p = c->gram[k]; v.ld = 0; v.kind = 1; v.Rl = c->R[k]; v.Rr = c->R[k + 1];
@@ -693,7 +694,12 @@ int ring_gemms(tr_als_ctx* c, const std::vector<int>& chain, MatView W, int64_t 
     const int k = chain[q];
     const int64_t inner = (int64_t)c->R[k] * c->R[k];
     const int64_t cols = (int64_t)c->R[k + 1] * c->R[k + 1];
-    double* out = (q + 1 == chain.size() && last_out) ? last_out : bufs[cur];
+    const bool last = q + 1 == chain.size();
+    if (last && S_out) {   // W (R_{m+1}^2 x R_m^2) straight into S_m<2>
+      HIPCHK(c, launch_gemm64_realign(inner, W, gview(k), c->R[m], c->R[m + 1], S_out, s));
+      break;
+    }
+    double* out = (last && last_out) ? last_out : bufs[cur];
     if (rows * cols > c->w_cap) return fail(c, TR_EINVAL, "internal: ring workspace too small");
     HIPCHK(c, launch_gemm64(rows, cols, inner, 1.0, W, gview(k), 0.0, nullptr, 0, out, rows, s));
     W.p = out; W.ld = rows; W.kind = 0;
@@ -720,15 +726,8 @@ int compute_coef(tr_als_ctx* c, int m, double* Sout, hipStream_t s, bool use_pre
     W = ring_first(c, (m + 1) % N);
     for (int k = 2; k < N; ++k) rest.push_back((m + k) % N);
   }
-  int rc = ring_gemms(c, rest, W, rows, nullptr, s);
-  if (rc) return rc;
-  MatView Wf;
-  if (rest.empty()) Wf = W;
-  else {
-    Wf.p = (rest.size() & 1) ? c->W0 : c->W1;
-    Wf.ld = rows; Wf.kind = 0; Wf.Rl = 0; Wf.Rr = 0;
-  }
-  HIPCHK(c, launch_realign_S(Wf, c->R[m], c->R[m + 1], Sout, s));
+  if (!rest.empty()) return ring_gemms(c, rest, W, rows, nullptr, s, Sout, m);   // last GEMM realigns
+  HIPCHK(c, launch_realign_S(W, c->R[m], c->R[m + 1], Sout, s));
   return TR_OK;
 }
 
