@@ -198,18 +198,28 @@ def main():
     print(json.dumps(out))
 
 
+def xgemm_source_sha():
+    """sha256 of the X-contraction kernel source and of the code that picks its
+    launch configuration (xg_config: tiles, split-K count, grid)."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2210_11362_amd", "csrc")
+    kern = open(os.path.join(csrc, "k_xgemm.hip"), "rb").read()
+    host = open(os.path.join(csrc, "tr_als.hip"), "rb").read()
+    a = host.index(b"XgArgs xg_config(")
+    b = host.index(b"\n}\n", a)
+    return hashlib.sha256(kern + host[a:b]).hexdigest()
+
+
 def measured_traffic():
     """HBM bytes per launch of the BF16 X-contraction kernel on this workload,
     from the committed FETCH_SIZE / WRITE_SIZE counter summary (copy-calibrated);
-    None when the kernel source changed since the counters were taken."""
-    import hashlib
+    None when the kernel or its launch configuration changed since the counters
+    were taken."""
     prof = os.path.join(ROOT, "profiles", "xgemm_bf16_100x4_R10_hbm_counters.md")
-    src = os.path.join(ROOT, "paper_2210_11362_amd", "csrc", "k_xgemm.hip")
     try:
         fields = dict(l.split(":", 1) for l in open(prof) if l.startswith(("traffic_bytes_per_launch:",
                                                                             "kernel_source_sha256:")))
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        if fields["kernel_source_sha256"].strip() != sha:
+        if fields["kernel_source_sha256"].strip() != xgemm_source_sha():
             return None
         return float(fields["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):

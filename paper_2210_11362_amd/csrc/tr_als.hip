@@ -431,13 +431,15 @@ XgArgs xg_config(const tr_als_ctx* c, int m, int prec, const void* X, int esize,
   // group) or columns (slowest-modes group, BF16 row-vector loads)
   g.vec_ok = ((((g.nn ? p.gM : p.gK) * esize) % 16 == 0) && (((uintptr_t)X) % 16 == 0)) ? 1 : 0;
   // Row tile and split-K target (workgroups per launch); measured best on the
-  // 100^4 rank-10 workload: 128 rows, ~640 workgroups for BF16 (HBM-bound),
-  // ~1024 for FP32 (MFMA-bound).  TR_ALS_XG_MT / TR_ALS_XG_WGS override.
+  // 100^4 rank-10 workload with X streamed from HBM (not the last-level
+  // cache): 128 rows, ~448 workgroups for BF16 (6 splits: 59.7 us against
+  // 65-75 us for 5 or 7-13 splits), ~1024 for FP32 (MFMA-bound).
+  // TR_ALS_XG_MT / TR_ALS_XG_WGS override.
   g.MT = p.gM > 8192 ? 128 : 64;
   static const int env_mt = getenv("TR_ALS_XG_MT") ? atoi(getenv("TR_ALS_XG_MT")) : 0;
   static const int env_wgs = getenv("TR_ALS_XG_WGS") ? atoi(getenv("TR_ALS_XG_WGS")) : 0;
   if (env_mt == 64 || env_mt == 128) g.MT = env_mt;
-  const int64_t target_wgs = env_wgs > 0 ? env_wgs : ((prec == TR_F32 || prec == TR_F64) ? 1024 : 640);
+  const int64_t target_wgs = env_wgs > 0 ? env_wgs : ((prec == TR_F32 || prec == TR_F64) ? 1024 : 448);
   g.n_mt = (int)((p.gM + g.MT - 1) / g.MT);
   if (p.gC <= 128) { g.NT = (p.gC + 15) / 16 * 16; g.n_nt = 1; }
   else { g.NT = 128; g.n_nt = (p.gC + 127) / 128; }
