@@ -128,7 +128,7 @@ __global__ __launch_bounds__(256) void commit_gram_kernel(const double* G, int64
 // Normal-equation apply with iterative refinement (Alg. 2 solve step): for a
 // block of NE_APPLY_ROWS rows of M, G = M S^{-1}, then per refinement step
 // R = M - G S and G += R S^{-1}; the row blocks stay in LDS (k-major) between
-// the products, the n x n operands are read from L2 (8 values of k in flight
+// the products, the n x n operands are read from L2 (32 values of k in flight
 // per thread).  RG row groups split the 256 threads so that small n keeps
 // every thread busy.  A non-finite entry of the final G latches ST_NONFINITE.
 // (Staging the operand in LDS and 8- or 16-row blocks measured slower.)
@@ -140,7 +140,7 @@ __global__ __launch_bounds__(256) void ne_apply_kernel(const double* __restrict_
                                                        const double* __restrict__ S,
                                                        const double* __restrict__ Sinv, int refine,
                                                        double* __restrict__ G, int* status) {
-  constexpr int RB = NE_APPLY_ROWS, RPT = RB / RG, CT = 256 / RG, KB = 8;
+  constexpr int RB = NE_APPLY_ROWS, RPT = RB / RG, CT = 256 / RG, KB = 32;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* Ms = reinterpret_cast<double*>(smem_raw);
   double* Gs = Ms + RB * n;
