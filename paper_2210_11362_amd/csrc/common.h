@@ -95,6 +95,23 @@ hipError_t launch_realign_S(MatView W, int Ra, int Rb, double* S, hipStream_t s)
 // The last ring GEMM W = A B (Rb^2 x Ra^2, inner K) stored straight into S_n<2>
 // with launch_realign_S's map.
 hipError_t launch_gemm64_realign(int64_t K, MatView A, MatView B, int Ra, int Rb, double* S, hipStream_t s);
+// One FP64 product C = alpha A B + beta Cin (M x N, inner K); Ra > 0 stores it
+// realigned as S_n<2> (Ra = R_n, Rb = R_{n+1}, M = Rb^2, N = Ra^2).
+struct Gemm64Desc {
+  int64_t M, N, K;
+  double alpha;
+  MatView A, B;
+  double beta;
+  const double* Cin;
+  int64_t ldcin;
+  double* C;
+  int64_t ldc;
+  int Ra, Rb;
+};
+inline int64_t gemm64_blocks(const Gemm64Desc& g) { return ((g.M + 15) / 16) * ((g.N + 15) / 16); }
+Gemm64Desc gemm64_realign_desc(int64_t K, MatView A, MatView B, int Ra, int Rb, double* S);
+// Two independent products in one launch.
+hipError_t launch_gemm64_pair(const Gemm64Desc& g0, const Gemm64Desc& g1, hipStream_t s);
 hipError_t launch_chol(const double* S, int n, double* L, double* LT, double* work, int* status, hipStream_t s);
 bool solve_in_lds(int n);
 // S^{-1} of an SPD matrix with n <= 128 by the symmetric sweep operator (one

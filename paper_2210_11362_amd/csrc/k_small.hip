@@ -227,16 +227,15 @@ __device__ __forceinline__ double view_at(const MatView& v, int64_t r, int64_t c
   return v.p[(b + Rl * cc) + (int64_t)Rl * Rr * (b2 + Rl * c2)];
 }
 
-// With Ra > 0 the result W (Rb^2 x Ra^2) is stored realigned as S_n<2>
-// (realign_S_kernel's map) instead of column-major with ldc.
-__global__ __launch_bounds__(256) void gemm64_kernel(int64_t M, int64_t N, int64_t K, double alpha, MatView A,
-                                                     MatView B, double beta, const double* Cin, int64_t ldcin,
-                                                     double* C, int64_t ldc, int* finite_status, int Ra, int Rb) {
-  // one 16x16 block of C per workgroup; the 4 waves split the K range
+// C = alpha A B + beta Cin, one 16x16 block of C per workgroup (block blk),
+// the 4 waves splitting the K range.  With Ra > 0 the result W (Rb^2 x Ra^2)
+// is stored realigned as S_n<2> (realign_S_kernel's map) instead of
+// column-major with ldc.
+__device__ __forceinline__ void gemm64_block(const Gemm64Desc& g, int64_t blk, int* finite_status) {
   __shared__ double red[4][64][4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t M = g.M, N = g.N, K = g.K;
   const int64_t nbm = (M + 15) / 16;
-  const int64_t blk = blockIdx.x;
   const int64_t bm = blk % nbm, bn = blk / nbm;
   const int64_t r = bm * 16 + (lane & 15), c = bn * 16 + (lane & 15);
   const int64_t nst = (K + 3) / 4;
@@ -245,28 +244,40 @@ __global__ __launch_bounds__(256) void gemm64_kernel(int64_t M, int64_t N, int64
 #pragma unroll 4
   for (int64_t st = s0; st < s1; ++st) {
     const int64_t k = st * 4 + (lane >> 4);
-    const double av = (r < M && k < K) ? view_at(A, r, k) : 0.0;
-    const double bv = (k < K && c < N) ? view_at(B, k, c) : 0.0;
+    const double av = (r < M && k < K) ? view_at(g.A, r, k) : 0.0;
+    const double bv = (k < K && c < N) ? view_at(g.B, k, c) : 0.0;
     mma64(acc, av, bv);
   }
   for (int v = 0; v < 4; ++v) red[wave][lane][v] = acc[v];
   __syncthreads();
   if (wave == 0) {
+    const int Ra = g.Ra, Rb = g.Rb;
     for (int v = 0; v < 4; ++v) {
       const int64_t row = bm * 16 + (lane >> 4) + 4 * v, col = bn * 16 + (lane & 15);
       if (row < M && col < N) {
-        double x = alpha * ((red[0][lane][v] + red[1][lane][v]) + (red[2][lane][v] + red[3][lane][v]));
-        if (beta != 0.0) x += beta * Cin[row + ldcin * col];
+        double x = g.alpha * ((red[0][lane][v] + red[1][lane][v]) + (red[2][lane][v] + red[3][lane][v]));
+        if (g.beta != 0.0) x += g.beta * g.Cin[row + g.ldcin * col];
         if (Ra > 0) {   // W(b + Rb*b2, a + Ra*a2) -> S(a + Ra*b, a2 + Ra*b2)
           const int64_t b = row % Rb, b2 = row / Rb, a = col % Ra, a2 = col / Ra, RR = (int64_t)Ra * Rb;
-          C[(a + Ra * b) + RR * (a2 + Ra * b2)] = x;
+          g.C[(a + Ra * b) + RR * (a2 + Ra * b2)] = x;
         } else {
-          C[row + ldc * col] = x;
+          g.C[row + g.ldc * col] = x;
         }
         if (finite_status && !isfinite(x)) atomicOr(finite_status, ST_NONFINITE);
       }
     }
   }
+}
+
+__global__ __launch_bounds__(256) void gemm64_kernel(Gemm64Desc g, int* finite_status) {
+  gemm64_block(g, blockIdx.x, finite_status);
+}
+
+// Two independent products in one launch: blocks [0, nblk0) form g0, the rest g1.
+__global__ __launch_bounds__(256) void gemm64_pair_kernel(Gemm64Desc g0, Gemm64Desc g1, int64_t nblk0) {
+  const int64_t blk = blockIdx.x;
+  if (blk < nblk0) gemm64_block(g0, blk, nullptr);
+  else gemm64_block(g1, blk - nblk0, nullptr);
 }
 
 // S[(a + Ra*b), (a' + Ra*b')] = W[(b + Rb*b'), (a + Ra*a')]  (S_n<2> from the
@@ -715,17 +726,25 @@ hipError_t launch_gram(const double* core, int Rl, int64_t I, int Rr, double* E,
 hipError_t launch_gemm64(int64_t M, int64_t N, int64_t K, double alpha, MatView A, MatView B, double beta,
                          const double* Cin, int64_t ldcin, double* C, int64_t ldc, hipStream_t s,
                          int* finite_status) {
-  const int64_t nblk = cdiv(M, 16) * cdiv(N, 16);
-  hipLaunchKernelGGL(gemm64_kernel, dim3((unsigned)nblk), dim3(256), 0, s, M, N, K, alpha, A, B, beta, Cin, ldcin, C,
-                     ldc, finite_status, 0, 0);
+  const Gemm64Desc g{M, N, K, alpha, A, B, beta, Cin, ldcin, C, ldc, 0, 0};
+  hipLaunchKernelGGL(gemm64_kernel, dim3((unsigned)gemm64_blocks(g)), dim3(256), 0, s, g, finite_status);
   return hipGetLastError();
 }
 
-hipError_t launch_gemm64_realign(int64_t K, MatView A, MatView B, int Ra, int Rb, double* S, hipStream_t s) {
+Gemm64Desc gemm64_realign_desc(int64_t K, MatView A, MatView B, int Ra, int Rb, double* S) {
   const int64_t M = (int64_t)Rb * Rb, N = (int64_t)Ra * Ra;
-  const int64_t nblk = cdiv(M, 16) * cdiv(N, 16);
-  hipLaunchKernelGGL(gemm64_kernel, dim3((unsigned)nblk), dim3(256), 0, s, M, N, K, 1.0, A, B, 0.0,
-                     (const double*)nullptr, (int64_t)0, S, M, (int*)nullptr, Ra, Rb);
+  return Gemm64Desc{M, N, K, 1.0, A, B, 0.0, nullptr, 0, S, M, Ra, Rb};
+}
+
+hipError_t launch_gemm64_realign(int64_t K, MatView A, MatView B, int Ra, int Rb, double* S, hipStream_t s) {
+  const Gemm64Desc g = gemm64_realign_desc(K, A, B, Ra, Rb, S);
+  hipLaunchKernelGGL(gemm64_kernel, dim3((unsigned)gemm64_blocks(g)), dim3(256), 0, s, g, (int*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm64_pair(const Gemm64Desc& g0, const Gemm64Desc& g1, hipStream_t s) {
+  const int64_t n0 = gemm64_blocks(g0), n1 = gemm64_blocks(g1);
+  hipLaunchKernelGGL(gemm64_pair_kernel, dim3((unsigned)(n0 + n1)), dim3(256), 0, s, g0, g1, n0);
   return hipGetLastError();
 }
 

@@ -79,7 +79,7 @@ struct tr_als_ctx {
   bool bf16_ready = false, fp8_ready = false;
   double *F1 = nullptr, *F2 = nullptr, *T0 = nullptr, *T1 = nullptr;
   double *M = nullptr, *S = nullptr, *W0 = nullptr, *W1 = nullptr, *Lf = nullptr, *LTf = nullptr, *cholw = nullptr;
-  double* Wpre = nullptr;   // ring prefix of the next mode within a sweep (order >= 4)
+  double* Wpre[2] = {nullptr, nullptr};   // ring prefix of mode m in Wpre[m & 1] within a sweep (order >= 4)
   int64_t w_cap = 0;        // elements of W0, W1 and Wpre
   // TR_ALS_CANARY=1: every workspace buffer is followed by a guard band filled
   // with a byte pattern, checked when the context is destroyed
@@ -682,9 +682,10 @@ int compute_mttsp(tr_als_ctx* c, int m, int prec, double* Mout, bool in_sweep = 
 // order >= 4 the prefix K_{m+1} ... K_{m-2} (it excludes the cores of modes
 // m-1 and m) is formed by the previous mode's branch (ring_prefix), so only
 // the last factor, refreshed by that mode, is multiplied here.
-// With S_out the last GEMM stores its result realigned into S_out (mode m).
+// With S_out the last GEMM stores its result realigned into S_out (mode m),
+// in one launch with the independent product *pair when one is given.
 int ring_gemms(tr_als_ctx* c, const std::vector<int>& chain, MatView W, int64_t rows, double* last_out,
-               hipStream_t s, double* S_out = nullptr, int m = 0) {
+               hipStream_t s, double* S_out = nullptr, int m = 0, const Gemm64Desc* pair = nullptr) {
   auto gview = [&](int k) {
     MatView v;
     v.p = c->gram[k]; v.ld = 0; v.kind = 1; v.Rl = c->R[k]; v.Rr = c->R[k + 1];
@@ -698,7 +699,9 @@ int ring_gemms(tr_als_ctx* c, const std::vector<int>& chain, MatView W, int64_t 
     const int64_t cols = (int64_t)c->R[k + 1] * c->R[k + 1];
     const bool last = q + 1 == chain.size();
     if (last && S_out) {   // W (R_{m+1}^2 x R_m^2) straight into S_m<2>
-      HIPCHK(c, launch_gemm64_realign(inner, W, gview(k), c->R[m], c->R[m + 1], S_out, s));
+      if (pair) HIPCHK(c, launch_gemm64_pair(gemm64_realign_desc(inner, W, gview(k), c->R[m], c->R[m + 1], S_out),
+                                             *pair, s));
+      else HIPCHK(c, launch_gemm64_realign(inner, W, gview(k), c->R[m], c->R[m + 1], S_out, s));
       break;
     }
     double* out = (last && last_out) ? last_out : bufs[cur];
@@ -716,30 +719,46 @@ MatView ring_first(const tr_als_ctx* c, int k) {
   return v;
 }
 
-int compute_coef(tr_als_ctx* c, int m, double* Sout, hipStream_t s, bool use_prefix = false) {
+int compute_coef(tr_als_ctx* c, int m, double* Sout, hipStream_t s, bool use_prefix = false,
+                 const Gemm64Desc* pair = nullptr) {
   const int N = c->N;
   const int64_t rows = (int64_t)c->R[(m + 1) % N] * c->R[(m + 1) % N];
   MatView W;
   std::vector<int> rest;
-  if (use_prefix) {   // Wpre = K_{m+1} ... K_{m-2}
-    W.p = c->Wpre; W.ld = rows; W.kind = 0; W.Rl = 0; W.Rr = 0;
+  if (use_prefix) {   // Wpre[m & 1] = K_{m+1} ... K_{m-2}
+    W.p = c->Wpre[m & 1]; W.ld = rows; W.kind = 0; W.Rl = 0; W.Rr = 0;
     rest.push_back((m + N - 1) % N);
   } else {
     W = ring_first(c, (m + 1) % N);
     for (int k = 2; k < N; ++k) rest.push_back((m + k) % N);
   }
-  if (!rest.empty()) return ring_gemms(c, rest, W, rows, nullptr, s, Sout, m);   // last GEMM realigns
+  if (!rest.empty()) return ring_gemms(c, rest, W, rows, nullptr, s, Sout, m, pair);   // last GEMM realigns
   HIPCHK(c, launch_realign_S(W, c->R[m], c->R[m + 1], Sout, s));
   return TR_OK;
 }
 
-// Prefix K_{m+1} ... K_{m-2} of mode m's ring, into Wpre (order >= 4).
+// Prefix K_{m+1} ... K_{m-2} of mode m's ring, into Wpre[m & 1] (order >= 4).
 int ring_prefix(tr_als_ctx* c, int m, hipStream_t s) {
   const int N = c->N;
   const int64_t rows = (int64_t)c->R[(m + 1) % N] * c->R[(m + 1) % N];
   std::vector<int> rest;
   for (int k = 2; k <= N - 2; ++k) rest.push_back((m + k) % N);
-  return ring_gemms(c, rest, ring_first(c, (m + 1) % N), rows, c->Wpre, s);
+  return ring_gemms(c, rest, ring_first(c, (m + 1) % N), rows, c->Wpre[m & 1], s);
+}
+
+// Order 4: mode m's prefix is the one product K_{m+1} K_{m+2}; its descriptor
+// (false when it is more than one product or does not fit the workspace).
+bool ring_prefix_single(const tr_als_ctx* c, int m, Gemm64Desc* d) {
+  const int N = c->N;
+  if (N != 4) return false;
+  const int k0 = (m + 1) % N, k1 = (m + 2) % N;
+  const int64_t rows = (int64_t)c->R[k0] * c->R[k0], inner = (int64_t)c->R[k1] * c->R[k1];
+  const int64_t cols = (int64_t)c->R[k1 + 1] * c->R[k1 + 1];
+  if (rows * cols > c->w_cap) return false;
+  MatView B;
+  B.p = c->gram[k1]; B.ld = 0; B.kind = 1; B.Rl = c->R[k1]; B.Rr = c->R[k1 + 1];
+  *d = Gemm64Desc{rows, cols, inner, 1.0, ring_first(c, k0), B, 0.0, nullptr, 0, c->Wpre[m & 1], rows, 0, 0};
+  return true;
 }
 
 // One NE mode update.  The coefficient branch (Gram ring -> S_n -> Cholesky ->
@@ -758,7 +777,12 @@ int update_mode_ne(tr_als_ctx* c, int m, int prec, int refine, bool in_sweep) {
   const bool prefix = in_sweep && c->N >= 4;
   auto branch = [&]() -> int {
     HIPCHK(c, hipStreamWaitEvent(s2, c->ev_fork, 0));
-    const int r = compute_coef(c, m, c->S, s2, prefix && m > 0);
+    // order 4: the next mode's prefix K_{m+2} K_{m+3} is one product of Grams
+    // that are final here; it goes into the same launch as this mode's last
+    // ring GEMM (its ring has at least one GEMM at order 4)
+    Gemm64Desc pd;
+    const bool pair = prefix && m + 1 < c->N && ring_prefix_single(c, m + 1, &pd);
+    const int r = compute_coef(c, m, c->S, s2, prefix && m > 0, pair ? &pd : nullptr);
     if (r) return r;
     if (spd_inverse_fits(n)) {
       HIPCHK(c, launch_spd_inverse(c->S, n, c->Sinv, c->status, s2));
@@ -768,7 +792,7 @@ int update_mode_ne(tr_als_ctx* c, int m, int prec, int refine, bool in_sweep) {
     }
     HIPCHK(c, hipEventRecord(c->ev_join, s2));
     // after the join: the next mode's prefix excludes this mode's core
-    if (prefix && m + 1 < c->N) return ring_prefix(c, m + 1, s2);
+    if (prefix && m + 1 < c->N && !pair) return ring_prefix(c, m + 1, s2);
     return TR_OK;
   };
   int rc = compute_mttsp(c, m, prec, c->M, in_sweep, branch);
@@ -1042,7 +1066,10 @@ int trx_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ranks,
   A((void**)&c->Y0, (size_t)maxY * 8);
   A((void**)&c->Y1, (size_t)maxY * 8);
   A((void**)&c->W1, (size_t)maxW * 8);
-  if (N >= 4) A((void**)&c->Wpre, (size_t)maxW * 8);
+  if (N >= 4) {
+    A((void**)&c->Wpre[0], (size_t)maxW * 8);
+    A((void**)&c->Wpre[1], (size_t)maxW * 8);
+  }
   c->w_cap = maxW;
   A((void**)&c->dpart, (size_t)c->nred * 8);
   A((void**)&c->fpart, (size_t)c->nred * 4);
