@@ -222,9 +222,11 @@ __global__ __launch_bounds__(256) void ne_apply_kernel(const double* __restrict_
 __device__ __forceinline__ double view_at(const MatView& v, int64_t r, int64_t c) {
   if (v.kind == 0) return v.p[r + v.ld * c];
   if (v.kind == 2) return v.p[c + v.ld * r];
-  const int Rl = v.Rl, Rr = v.Rr;
-  const int64_t b = r % Rl, b2 = r / Rl, cc = c % Rr, c2 = c / Rr;
-  return v.p[(b + Rl * cc) + (int64_t)Rl * Rr * (b2 + Rl * c2)];
+  // Gram view: r < Rl^2 and c < Rr^2 fit 32 bits (64-bit division is a long
+  // software sequence on the GPU)
+  const unsigned Rl = (unsigned)v.Rl, Rr = (unsigned)v.Rr, r32 = (unsigned)r, c32 = (unsigned)c;
+  const unsigned b = r32 % Rl, b2 = r32 / Rl, cc = c32 % Rr, c2 = c32 / Rr;
+  return v.p[(b + Rl * cc) + (size_t)Rl * Rr * (b2 + Rl * c2)];
 }
 
 // C = alpha A B + beta Cin, one 16x16 block of C per workgroup (block blk),
@@ -241,12 +243,28 @@ __device__ __forceinline__ void gemm64_block(const Gemm64Desc& g, int64_t blk, i
   const int64_t nst = (K + 3) / 4;
   const int64_t s0 = nst * wave / 4, s1 = nst * (wave + 1) / 4;
   f64x4 acc = {0, 0, 0, 0};
+  const int64_t rc = min(r, M - 1), cc = min(c, N - 1);
+  if (s1 - s0 <= 8) {   // all of this wave's operand pairs in flight at once (clamped, masked)
+    double av[8], bv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t k = (s0 + u) * 4 + (lane >> 4);
+      const bool ok = s0 + u < s1 && k < K;
+      const int64_t kc = ok ? k : 0;
+      const double a = view_at(g.A, rc, kc), b = view_at(g.B, kc, cc);
+      av[u] = (ok && r < M) ? a : 0.0;
+      bv[u] = (ok && c < N) ? b : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) mma64(acc, av[u], bv[u]);
+  } else {
 #pragma unroll 4
-  for (int64_t st = s0; st < s1; ++st) {
-    const int64_t k = st * 4 + (lane >> 4);
-    const double av = (r < M && k < K) ? view_at(g.A, r, k) : 0.0;
-    const double bv = (k < K && c < N) ? view_at(g.B, k, c) : 0.0;
-    mma64(acc, av, bv);
+    for (int64_t st = s0; st < s1; ++st) {
+      const int64_t k = st * 4 + (lane >> 4);
+      const double av = (r < M && k < K) ? view_at(g.A, r, k) : 0.0;
+      const double bv = (k < K && c < N) ? view_at(g.B, k, c) : 0.0;
+      mma64(acc, av, bv);
+    }
   }
   for (int v = 0; v < 4; ++v) red[wave][lane][v] = acc[v];
   __syncthreads();
