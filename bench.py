@@ -81,21 +81,27 @@ def main():
         return TRContext(X, dims, ranks, dev, variant=variant), dev
 
     # ---- timed steps: K sweeps in the chosen precision --------------------
+    # Throughput: the K sweeps issued as one tr_als_sweep call, the way a
+    # decomposition job runs them (every sweep executed in full; the library
+    # synchronises once at the end to read its status word).
     ctx, dev = fresh()
     ctx.sweep(args.warmup, args.prec, refine=1)
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.sweep(args.steps, args.prec, refine=1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    ms_per_step = 1000.0 * wall / args.steps
+    # Latency: K single-sweep calls, each ending with the status synchronisation.
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
     for e0, e1 in evs:
         e0.record()
         ctx.sweep(1, args.prec, refine=1)
         e1.record()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    wall = t1 - t0
     per = sorted(e0.elapsed_time(e1) for e0, e1 in evs)
-    ms_per_step = 1000.0 * wall / args.steps
     p50 = per[len(per) // 2]
     p99 = per[min(len(per) - 1, int(round(0.99 * (len(per) - 1))))]
 
@@ -181,6 +187,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 4),
+        "timing": "value/ms_per_step: the K sweeps as one tr_als_sweep call (one status sync); "
+                  "sweep_ms_p50/p99: K single-sweep calls, each with its status sync",
         "sweep_ms_p50": round(p50, 4),
         "sweep_ms_p99": round(p99, 4),
         "higher_is_better": True,
