@@ -37,6 +37,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-schedules", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-qr", action="store_true")
     ap.add_argument("--serving-jobs", type=int, default=400)
     ap.add_argument("--serving-only", action="store_true",
                     help="only run the serving stream and print its JSON (the bench runs it in a child process)")
@@ -157,6 +158,24 @@ def main():
         sched["fit_delta"] = abs(sched["mixed"]["fit"] - sched["plain"]["fit"])
         sched["speedup_mixed_vs_plain"] = round(sched["plain"]["seconds"] / sched["mixed"]["seconds"], 3)
         extra["schedules_20_sweeps"] = sched
+
+    # ---- the QR-stabilised variant (Alg. 3) on the same workload ------------
+    if not args.no_qr:
+        try:
+            qr = {}
+            for p in ("f32", args.prec):
+                ctx, dev = fresh("qr")
+                ctx.sweep(1, p, refine=1)
+                torch.cuda.synchronize()
+                ta = time.perf_counter()
+                ctx.sweep(3, p, refine=1)
+                tb = time.perf_counter()
+                qr[f"{p}_ms_per_sweep"] = round(1000 * (tb - ta) / 3, 4)
+                qr[f"{p}_fit_after_4_sweeps"] = ctx.fit()
+                ctx.close()
+            extra["qr_variant"] = qr
+        except Exception as e:   # reported, never fatal to the bench line
+            extra["qr_variant"] = {"error": str(e)[:200]}
 
     # ---- serving: a Poisson stream of small jobs through the request loop ---
     if not args.no_serving and args.serving_jobs > 0:

@@ -185,6 +185,47 @@ __global__ void ttm_fp8_kernel(const uint8_t* in, int64_t L, int64_t I, int64_t 
   }
 }
 
+// The same mode product, register-blocked: a workgroup takes TRB consecutive
+// r (their columns of Q staged in LDS) and a thread one (l, t) pair, so each
+// input element is read once per TRB outputs instead of once per output.
+// Summation over i in increasing order, as in ttm_kernel.
+constexpr int TRB = 16;
+template <typename Tin>
+__device__ __forceinline__ double ttm_in(const Tin* p) { return (double)*p; }
+template <>
+__device__ __forceinline__ double ttm_in<uint8_t>(const uint8_t* p) {
+  return (double)__builtin_amdgcn_cvt_f32_fp8((int)*p, 0);
+}
+template <typename Tin>
+__global__ __launch_bounds__(256) void ttm_rb_kernel(const Tin* in, int64_t L, int64_t I, int64_t T, const double* Q,
+                                                     int R, double scale, double* out) {
+  extern __shared__ double qs[];   // [I][TRB]: Q(i, r0 + rr)
+  const int tid = threadIdx.x, r0 = blockIdx.y * TRB;
+  for (int64_t e = tid; e < I * TRB; e += 256) {
+    const int64_t i = e % I;
+    const int rr = (int)(e / I);
+    qs[i * TRB + rr] = r0 + rr < R ? Q[i + I * (r0 + rr)] : 0.0;
+  }
+  __syncthreads();
+  const int64_t LT = L * T;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + tid; e < LT; e += (int64_t)gridDim.x * 256) {
+    const int64_t l = e % L, t = e / L;
+    const Tin* x = in + l + L * I * t;
+    double acc[TRB];
+#pragma unroll
+    for (int rr = 0; rr < TRB; ++rr) acc[rr] = 0.0;
+    for (int64_t i = 0; i < I; ++i) {
+      const double xv = ttm_in(x + L * i);
+      const double* q = qs + i * TRB;
+#pragma unroll
+      for (int rr = 0; rr < TRB; ++rr) acc[rr] = fma(xv, q[rr], acc[rr]);
+    }
+#pragma unroll
+    for (int rr = 0; rr < TRB; ++rr)
+      if (r0 + rr < R) out[l + L * (r0 + rr) + L * (int64_t)R * t] = acc[rr] * scale;
+  }
+}
+
 __global__ void transpose_kernel(const double* A, int64_t rows, int64_t cols, double* At) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= rows * cols) return;
@@ -260,6 +301,17 @@ hipError_t launch_tall_atb(const double* A, int64_t lda, const double* B, int64_
 
 hipError_t launch_ttm(const void* in, int in_type, int64_t L, int64_t I, int64_t T, const double* Q, int R,
                       double scale, double* out, hipStream_t s) {
+  const size_t lds = (size_t)I * TRB * sizeof(double);
+  if (lds <= 64 * 1024) {
+    const dim3 grid((unsigned)std::min<int64_t>(cdiv(L * T, 256), 16384), (unsigned)cdiv(R, TRB));
+    switch (in_type) {
+      case TR_F64: hipLaunchKernelGGL(ttm_rb_kernel<double>, grid, dim3(256), lds, s, (const double*)in, L, I, T, Q, R, scale, out); break;
+      case TR_F32: hipLaunchKernelGGL(ttm_rb_kernel<float>, grid, dim3(256), lds, s, (const float*)in, L, I, T, Q, R, scale, out); break;
+      case TR_BF16: hipLaunchKernelGGL(ttm_rb_kernel<__bf16>, grid, dim3(256), lds, s, (const __bf16*)in, L, I, T, Q, R, scale, out); break;
+      default: hipLaunchKernelGGL(ttm_rb_kernel<uint8_t>, grid, dim3(256), lds, s, (const uint8_t*)in, L, I, T, Q, R, scale, out); break;
+    }
+    return hipGetLastError();
+  }
   const int64_t n = L * R * T;
   const int64_t grid = std::min<int64_t>(cdiv(n, 256), 65536);
   switch (in_type) {
