@@ -142,12 +142,184 @@ __global__ __launch_bounds__(256) void tall_atb_kernel(TallArgs g) {
   }
 }
 
-__global__ void sum_chunks_kernel(const double* part, int nchunk, int64_t n, double* C) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
+// The same product, register-blocked: a wave owns 16-row blocks of C and
+// keeps all NBQ of its 16-column tiles in accumulators, so each A fragment
+// is loaded once per k-step; four k-steps of (clamped) operand loads are in
+// flight together.  Per tile the sum over k runs in increasing k, as in
+// tall_atb_kernel.
+template <int NBQ>
+__global__ __launch_bounds__(256) void tall_atb_rb_kernel(TallArgs g) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nbp = (g.P + 15) / 16;
+  const int64_t k0 = (int64_t)blockIdx.x * g.kc;
+  const int64_t k1 = min(g.K, k0 + g.kc);
+  double* out = g.part + (size_t)blockIdx.x * g.P * g.Q;
+  constexpr int KU = 4;
+  for (int bp = wave; bp < nbp; bp += 4) {
+    const int p = bp * 16 + (lane & 15), pc = min(p, g.P - 1);
+    f64x4 acc[NBQ];
+#pragma unroll
+    for (int bq = 0; bq < NBQ; ++bq) acc[bq] = f64x4{0, 0, 0, 0};
+    for (int64_t kb = k0; kb < k1; kb += 4 * KU) {
+      double av[KU], bv[KU][NBQ];
+#pragma unroll
+      for (int u = 0; u < KU; ++u) {
+        const int64_t k = kb + 4 * u + (lane >> 4);
+        const bool kin = k < k1;
+        const int64_t kc = kin ? k : k0;
+        double a;
+        if (g.mode == 0) {
+          a = g.A[kc + g.lda * pc];
+        } else {
+          const int64_t t = kc % g.T, l = kc / g.T;
+          a = g.A[l + g.L * (pc + g.Ip * t)];
+        }
+        av[u] = (kin && p < g.P) ? a : 0.0;
+#pragma unroll
+        for (int bq = 0; bq < NBQ; ++bq) {
+          const int q = bq * 16 + (lane & 15);
+          const double b = g.B[kc + g.ldb * min(q, g.Q - 1)];
+          bv[u][bq] = (kin && q < g.Q) ? b : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < KU; ++u)
+#pragma unroll
+        for (int bq = 0; bq < NBQ; ++bq) mma64(acc[bq], av[u], bv[u][bq]);
+    }
+#pragma unroll
+    for (int bq = 0; bq < NBQ; ++bq)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = bp * 16 + (lane >> 4) + 4 * v, col = bq * 16 + (lane & 15);
+        if (row < g.P && col < g.Q) out[row + (int64_t)g.P * col] = acc[bq][v];
+      }
+  }
+}
+
+// The same product with the operands staged through LDS: each k-slab of
+// GKS rows is read with lanes along k (coalesced for column-major operands),
+// stored as [column][k] and consumed by the four waves, which split the
+// 16x16 output tiles between them.  Element (k, p) of A sits at
+// base(k) + sp * p: base(k) = k, sp = lda in the plain layout, and
+// base(k) = l + L*Ip*t, sp = L in the Multi-TTM layout (t = k mod T,
+// l = k div T).  With A == B (a Gram matrix) only the tiles on or above the
+// diagonal are formed and each is written to both halves, so the result is
+// exactly symmetric.  Within a slab, MFMA step (j, e) takes from lane group
+// kq the row k = 8j + 2kq + e for both operands.
+constexpr int GKS = 32, GST = GKS + 2, GLD = 256 / GKS;
+
+// NB: 16-row blocks held per operand (rows past P or Q are zero); GRAM: A is
+// B.  Waves whose tile count is below TMAX repeat tile 0 and drop the result.
+template <int NB, bool GRAM>
+__global__ __launch_bounds__(256) void tall_atb_lds_kernel(TallArgs g) {
+  constexpr int NT = GRAM ? NB * (NB + 1) / 2 : NB * NB, TMAX = (NT + 3) / 4, NR = NB * 16 / GLD;
+  extern __shared__ __align__(16) double gsm[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int kk = tid % GKS, pg = tid / GKS;
+  const int nbp = (g.P + 15) / 16, nbq = (g.Q + 15) / 16;
+  double* As = gsm;
+  double* Bs = GRAM ? gsm : gsm + NB * 16 * GST;
+  const int64_t k0 = (int64_t)blockIdx.x * g.kc;
+  const int64_t k1 = min(g.K, k0 + g.kc);
+  const int64_t sp = g.mode == 0 ? g.lda : g.L;
+  const int ntile = GRAM ? nbp * (nbp + 1) / 2 : nbp * nbq;
+  int offa[TMAX], offb[TMAX], tbp[TMAX], tbq[TMAX];
+  int nt = 0;
+#pragma unroll
+  for (int s = 0; s < TMAX; ++s) {
+    const int i = wave + 4 * s;
+    int bp = 0, bq = 0;
+    if (i < ntile) {
+      ++nt;
+      if (GRAM) {
+        int r = i;
+        while (r > bq) { r -= bq + 1; ++bq; }
+        bp = r;
+      } else {
+        bp = i % nbp; bq = i / nbp;
+      }
+    }
+    tbp[s] = bp; tbq[s] = bq;
+    offa[s] = (bp * 16 + (lane & 15)) * GST + 2 * (lane >> 4);
+    offb[s] = (bq * 16 + (lane & 15)) * GST + 2 * (lane >> 4);
+  }
+  f64x4 acc[TMAX];
+#pragma unroll
+  for (int s = 0; s < TMAX; ++s) acc[s] = f64x4{0, 0, 0, 0};
+  double ra[NR], rb[NR];
+  auto load = [&](int64_t ks) {
+    const int64_t k = ks + kk;
+    const bool kin = k < k1;
+    const int64_t kc = kin ? k : k0;
+    int64_t base = kc;
+    if (g.mode != 0) { const int64_t t = kc % g.T, l = kc / g.T; base = l + g.L * g.Ip * t; }
+    const double* pa = g.A + base;
+    const double* pb = g.B + kc;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      const int p = pg + GLD * i;
+      const double va = pa[sp * min(p, g.P - 1)];
+      ra[i] = (kin && p < g.P) ? va : 0.0;
+      if (!GRAM) {
+        const double vb = pb[g.ldb * min(p, g.Q - 1)];
+        rb[i] = (kin && p < g.Q) ? vb : 0.0;
+      }
+    }
+  };
+  if (k0 < k1) load(k0);
+  for (int64_t ks = k0; ks < k1; ks += GKS) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      const int p = pg + GLD * i;
+      As[p * GST + kk] = ra[i];
+      if (!GRAM) Bs[p * GST + kk] = rb[i];
+    }
+    __syncthreads();
+    if (ks + GKS < k1) load(ks + GKS);
+#pragma unroll
+    for (int j = 0; j < GKS / 8; ++j) {
+      double2 a[TMAX], b[TMAX];
+#pragma unroll
+      for (int s = 0; s < TMAX; ++s) {
+        a[s] = *reinterpret_cast<const double2*>(As + offa[s] + 8 * j);
+        b[s] = *reinterpret_cast<const double2*>(Bs + offb[s] + 8 * j);
+      }
+#pragma unroll
+      for (int s = 0; s < TMAX; ++s) mma64(acc[s], a[s].x, b[s].x);
+#pragma unroll
+      for (int s = 0; s < TMAX; ++s) mma64(acc[s], a[s].y, b[s].y);
+    }
+  }
+  double* out = g.part + (size_t)blockIdx.x * g.P * g.Q;
+#pragma unroll
+  for (int s = 0; s < TMAX; ++s)
+    if (s < nt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = tbp[s] * 16 + (lane >> 4) + 4 * v, col = tbq[s] * 16 + (lane & 15);
+        if (row < g.P && col < g.Q) {
+          out[row + (int64_t)g.P * col] = acc[s][v];
+          if (GRAM && tbp[s] != tbq[s]) out[col + (int64_t)g.P * row] = acc[s][v];
+        }
+      }
+}
+
+// C = sum over chunks; a block takes 64 outputs, its four waves each sum a
+// contiguous quarter of the chunks, and the quarters are added in order.
+__global__ __launch_bounds__(256) void sum_chunks_kernel(const double* part, int nchunk, int64_t n, double* C) {
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t e = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t ec = e < n ? e : n - 1;
+  const int per = (nchunk + 3) / 4, c0 = wave * per, c1 = min(nchunk, c0 + per);
   double s = 0.0;
-  for (int c = 0; c < nchunk; ++c) s += part[(size_t)c * n + e];
-  C[e] = s;
+#pragma unroll 8
+  for (int c = c0; c < c1; ++c) s += part[(size_t)c * n + ec];
+  red[wave][lane] = s;
+  __syncthreads();
+  if (wave == 0 && e < n) C[e] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 
 // Mode product: out(l, r, t) = scale * sum_i in(l + L*(i + I*t)) Q(i + I*r).
@@ -291,11 +463,37 @@ hipError_t launch_tall_atb(const double* A, int64_t lda, const double* B, int64_
   g.L = L; g.Ip = Ip; g.T = T; g.part = part;
   int64_t nchunk = std::min<int64_t>(512, std::max<int64_t>(1, part_elems / ((int64_t)P * Q)));
   nchunk = std::min<int64_t>(nchunk, cdiv(K, 64));
+  const bool gram = mode == 0 && A == B && lda == ldb && P == Q;
+  const int nb = std::max((P + 15) / 16, (Q + 15) / 16);
+  const size_t lds = (size_t)(gram ? 1 : 2) * nb * 16 * GST * sizeof(double);
+  if (nb <= 8 && lds <= 64 * 1024) {   // LDS-staged slabs
+    g.kc = cdiv(cdiv(K, nchunk), GKS) * GKS;
+    nchunk = cdiv(K, g.kc);
+    const dim3 grid((unsigned)nchunk);
+    switch (nb * 2 + (gram ? 1 : 0)) {
+#define TALL_LDS(B) \
+  case 2 * B: hipLaunchKernelGGL((tall_atb_lds_kernel<B, false>), grid, dim3(256), lds, s, g); break; \
+  case 2 * B + 1: hipLaunchKernelGGL((tall_atb_lds_kernel<B, true>), grid, dim3(256), lds, s, g); break;
+      TALL_LDS(1) TALL_LDS(2) TALL_LDS(3) TALL_LDS(4) TALL_LDS(5) TALL_LDS(6) TALL_LDS(7)
+      case 17: hipLaunchKernelGGL((tall_atb_lds_kernel<8, true>), grid, dim3(256), lds, s, g); break;
+#undef TALL_LDS
+      default: return hipErrorInvalidValue;
+    }
+    const int64_t n = (int64_t)P * Q;
+    hipLaunchKernelGGL(sum_chunks_kernel, dim3(cdiv(n, 64)), dim3(256), 0, s, (const double*)part, (int)nchunk, n, C);
+    return hipGetLastError();
+  }
   g.kc = cdiv(cdiv(K, nchunk), 4) * 4;
   nchunk = cdiv(K, g.kc);
-  hipLaunchKernelGGL(tall_atb_kernel, dim3((unsigned)nchunk), dim3(256), 0, s, g);
+  switch ((Q + 15) / 16) {   // register-blocked for Q <= 128
+#define TALL_CASE(B) \
+  case B: hipLaunchKernelGGL(tall_atb_rb_kernel<B>, dim3((unsigned)nchunk), dim3(256), 0, s, g); break;
+    TALL_CASE(1) TALL_CASE(2) TALL_CASE(3) TALL_CASE(4) TALL_CASE(5) TALL_CASE(6) TALL_CASE(7) TALL_CASE(8)
+#undef TALL_CASE
+    default: hipLaunchKernelGGL(tall_atb_kernel, dim3((unsigned)nchunk), dim3(256), 0, s, g); break;
+  }
   const int64_t n = (int64_t)P * Q;
-  hipLaunchKernelGGL(sum_chunks_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, (const double*)part, (int)nchunk, n, C);
+  hipLaunchKernelGGL(sum_chunks_kernel, dim3(cdiv(n, 64)), dim3(256), 0, s, (const double*)part, (int)nchunk, n, C);
   return hipGetLastError();
 }
 
