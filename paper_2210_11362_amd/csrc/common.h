@@ -130,6 +130,9 @@ hipError_t launch_tall_atb(const double* A, int64_t lda, const double* B, int64_
 hipError_t launch_ttm(const void* in, int in_type, int64_t L, int64_t I, int64_t T, const double* Q, int R,
                       double scale, double* out, hipStream_t s);
 hipError_t launch_transpose(const double* A, int64_t rows, int64_t cols, double* At, hipStream_t s);
+// C = A B for a tall column-major A (M x K) and a small B (K x N), K, N <= 112.
+hipError_t launch_tall_gemm(const double* A, int64_t lda, int64_t M, int K, const double* B, int ldb, int N,
+                            double* C, int64_t ldc, hipStream_t s);
 hipError_t launch_table_to_v2(const double* T, int64_t J, int Ra, int Rb, double* V2, hipStream_t s);
 hipError_t launch_shift_and_add(double* G, int n, int64_t m, double* sbuf, hipStream_t s);
 hipError_t launch_core_fold(const double* G2, int64_t I, int Ra, int Rb, double* core, hipStream_t s);

@@ -416,6 +416,102 @@ __global__ void table_to_v2_kernel(const double* T, int64_t J, int Ra, int Rb, d
   V2[e] = T[k * C + b + Rb * a];
 }
 
+// The same reordering through LDS: a block moves V2T_ROWS table rows (read
+// whole and contiguous) and writes each output column as one contiguous run.
+constexpr int V2T_ROWS = 32;
+__global__ __launch_bounds__(256) void table_to_v2_tiled_kernel(const double* T, int64_t J, int Ra, int Rb,
+                                                                 double* V2) {
+  extern __shared__ __align__(16) double vsm[];
+  const int C = Ra * Rb, pitch = C + 1;
+  const int64_t k0 = (int64_t)blockIdx.x * V2T_ROWS;
+  const int nk = (int)min<int64_t>(V2T_ROWS, J - k0);
+  for (int e = threadIdx.x; e < nk * C; e += 256) vsm[(e / C) * pitch + e % C] = T[k0 * C + e];
+  __syncthreads();
+  for (int e = threadIdx.x; e < V2T_ROWS * C; e += 256) {
+    const int kl = e % V2T_ROWS, col = e / V2T_ROWS;
+    const int a = col % Ra, b = col / Ra;
+    if (kl < nk) V2[k0 + kl + J * col] = vsm[kl * pitch + b + Rb * a];
+  }
+}
+
+// C = A B for a tall A (M x K, column-major, ld lda) and a small B (K x N,
+// ld ldb), K, N <= 16*NB.  Each wave keeps its 16-column tiles of B as MFMA
+// fragments in registers for the whole launch; blocks stride over 64-row
+// slabs of A, staged through LDS with lanes along the rows.  The MFMA forms
+// C^T = B^T A^T so each store covers 16 consecutive rows of a column.  Step
+// (j, e) takes from lane group kq the inner index k = 8j + 2kq + e.
+constexpr int TG_ROWS = 64;
+template <int NB>
+__global__ __launch_bounds__(256) void tall_gemm_kernel(const double* A, int64_t lda, int64_t M, int K,
+                                                        const double* B, int ldb, int N, double* C, int64_t ldc) {
+  constexpr int KJ = 2 * NB, CT = (NB + 3) / 4, AP = 16 * NB + 2, NL = 16 * NB / 4;
+  extern __shared__ __align__(16) double tsm[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nbn = (N + 15) / 16;
+  double2 bf[CT][KJ];
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+    for (int j = 0; j < KJ; ++j) {
+      const int n = (wave + 4 * ct) * 16 + (lane & 15), k = 8 * j + 2 * (lane >> 4);
+      const bool nin = n < N;
+      const double* bp = B + (int64_t)ldb * min(n, N - 1);
+      bf[ct][j].x = (nin && k < K) ? bp[min(k, K - 1)] : 0.0;
+      bf[ct][j].y = (nin && k + 1 < K) ? bp[min(k + 1, K - 1)] : 0.0;
+    }
+  const int m = tid & 63, kg = tid >> 6;
+  double ra[NL];
+  auto load = [&](int64_t r0) {
+    const int64_t r = r0 + m;
+    const bool rin = r < M;
+    const double* ap = A + (rin ? r : M - 1);
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      const int k = kg + 4 * i;
+      const double v = ap[lda * min(k, K - 1)];
+      ra[i] = (rin && k < K) ? v : 0.0;
+    }
+  };
+  const int64_t nslab = (M + TG_ROWS - 1) / TG_ROWS;
+  int64_t slab = blockIdx.x;
+  if (slab < nslab) load(slab * TG_ROWS);
+  for (; slab < nslab; slab += gridDim.x) {
+    const int64_t r0 = slab * TG_ROWS;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NL; ++i) tsm[m * AP + kg + 4 * i] = ra[i];
+    __syncthreads();
+    if (slab + gridDim.x < nslab) load((slab + gridDim.x) * TG_ROWS);
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      const int c = wave + 4 * ct;
+      if (c >= nbn) continue;
+      f64x4 acc[4];
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt) acc[rt] = f64x4{0, 0, 0, 0};
+#pragma unroll
+      for (int j = 0; j < KJ; ++j) {
+        double2 av[4];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+          av[rt] = *reinterpret_cast<const double2*>(tsm + (rt * 16 + (lane & 15)) * AP + 8 * j + 2 * (lane >> 4));
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) mma64(acc[rt], bf[ct][j].x, av[rt].x);
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) mma64(acc[rt], bf[ct][j].y, av[rt].y);
+      }
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t r = r0 + rt * 16 + (lane & 15);
+          const int n = c * 16 + (lane >> 4) + 4 * v;
+          if (r < M && n < N) C[r + ldc * n] = acc[rt][v];
+        }
+    }
+  }
+}
+
 // core[a + Ra*(i + I*b)] = G2[i + I*(a + Ra*b)]  (inverse of the mode-2 unfolding)
 __global__ void core_fold_kernel(const double* G2, int64_t I, int Ra, int Rb, double* core) {
   const int64_t n = I * Ra * Rb;
@@ -527,6 +623,11 @@ hipError_t launch_transpose(const double* A, int64_t rows, int64_t cols, double*
 }
 
 hipError_t launch_table_to_v2(const double* T, int64_t J, int Ra, int Rb, double* V2, hipStream_t s) {
+  const size_t lds = (size_t)V2T_ROWS * (Ra * Rb + 1) * sizeof(double);
+  if (lds <= 64 * 1024) {
+    hipLaunchKernelGGL(table_to_v2_tiled_kernel, dim3((unsigned)cdiv(J, V2T_ROWS)), dim3(256), lds, s, T, J, Ra, Rb, V2);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(table_to_v2_kernel, dim3(cdiv(J * Ra * Rb, 256)), dim3(256), 0, s, T, J, Ra, Rb, V2);
   return hipGetLastError();
 }
@@ -539,5 +640,20 @@ hipError_t launch_core_fold(const double* G2, int64_t I, int Ra, int Rb, double*
 hipError_t launch_shift_and_add(double* G, int n, int64_t m, double* sbuf, hipStream_t s) {
   hipLaunchKernelGGL(shift_kernel, dim3(1), dim3(64), 0, s, (const double*)G, n, m, sbuf);
   hipLaunchKernelGGL(add_diag_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, G, n, (const double*)sbuf);
+  return hipGetLastError();
+}
+
+hipError_t launch_tall_gemm(const double* A, int64_t lda, int64_t M, int K, const double* B, int ldb, int N,
+                            double* C, int64_t ldc, hipStream_t s) {
+  const int nb = std::max((K + 15) / 16, (N + 15) / 16);
+  if (M <= 0 || K <= 0 || N <= 0 || nb > 7) return hipErrorInvalidValue;
+  const size_t lds = (size_t)TG_ROWS * (16 * nb + 2) * sizeof(double);
+  const dim3 grid((unsigned)std::min<int64_t>(cdiv(M, TG_ROWS), 512));
+  switch (nb) {
+#define TG_CASE(NBV) \
+  case NBV: hipLaunchKernelGGL(tall_gemm_kernel<NBV>, grid, dim3(256), lds, s, A, lda, M, K, B, ldb, N, C, ldc); break;
+    TG_CASE(1) TG_CASE(2) TG_CASE(3) TG_CASE(4) TG_CASE(5) TG_CASE(6) TG_CASE(7)
+#undef TG_CASE
+  }
   return hipGetLastError();
 }

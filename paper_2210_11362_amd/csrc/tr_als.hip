@@ -840,8 +840,12 @@ int update_mode_qr(tr_als_ctx* c, int m, int prec) {
     if (it == 0) HIPCHK(c, launch_shift_and_add(c->qG, n, Jp, c->qshift, s));
     HIPCHK(c, launch_chol_lds(c->qG, n, c->qL[it], c->qLT, c->rdiag, c->status, s));
     HIPCHK(c, launch_trsm_rhs(c->qL[it], c->rdiag, n, nullptr, n, c->qRi, 0, c->status, s, 1));
-    MatView Av{A, Jp, 0, 0, 0}, Ri{c->qRi, n, 0, 0, 0};
-    HIPCHK(c, launch_gemm64(Jp, n, n, 1.0, Av, Ri, 0.0, nullptr, 0, bufs[it & 1], Jp, s));
+    if (n <= 112) {
+      HIPCHK(c, launch_tall_gemm(A, Jp, Jp, n, c->qRi, n, n, bufs[it & 1], Jp, s));
+    } else {
+      MatView Av{A, Jp, 0, 0, 0}, Ri{c->qRi, n, 0, 0, 0};
+      HIPCHK(c, launch_gemm64(Jp, n, n, 1.0, Av, Ri, 0.0, nullptr, 0, bufs[it & 1], Jp, s));
+    }
     A = bufs[it & 1];
   }
   {
