@@ -16,6 +16,13 @@ __device__ __forceinline__ void mma64(f64x4& c, double a, double b) {
   c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+template <typename Tin>
+__device__ __forceinline__ double ttm_in(const Tin* p) { return (double)*p; }
+template <>
+__device__ __forceinline__ double ttm_in<uint8_t>(const uint8_t* p) {
+  return (double)__builtin_amdgcn_cvt_f32_fp8((int)*p, 0);
+}
+
 __device__ double block_sum(double v, double* red) {
   const int tid = threadIdx.x;
   red[tid] = v;
@@ -363,12 +370,6 @@ __global__ void ttm_fp8_kernel(const uint8_t* in, int64_t L, int64_t I, int64_t 
 // Summation over i in increasing order, as in ttm_kernel.
 constexpr int TRB = 16;
 template <typename Tin>
-__device__ __forceinline__ double ttm_in(const Tin* p) { return (double)*p; }
-template <>
-__device__ __forceinline__ double ttm_in<uint8_t>(const uint8_t* p) {
-  return (double)__builtin_amdgcn_cvt_f32_fp8((int)*p, 0);
-}
-template <typename Tin>
 __global__ __launch_bounds__(256) void ttm_rb_kernel(const Tin* in, int64_t L, int64_t I, int64_t T, const double* Q,
                                                      int R, double scale, double* out) {
   extern __shared__ double qs[];   // [I][TRB]: Q(i, r0 + rr)
@@ -434,19 +435,29 @@ __global__ __launch_bounds__(256) void table_to_v2_tiled_kernel(const double* T,
   }
 }
 
-// C = A B for a tall A (M x K, column-major, ld lda) and a small B (K x N,
-// ld ldb), K, N <= 16*NB.  Each wave keeps its 16-column tiles of B as MFMA
-// fragments in registers for the whole launch; blocks stride over 64-row
-// slabs of A, staged through LDS with lanes along the rows.  The MFMA forms
-// C^T = B^T A^T so each store covers 16 consecutive rows of a column.  Step
-// (j, e) takes from lane group kq the inner index k = 8j + 2kq + e.
+
+// Batched C_b = scale * A_b B for tall A_b (M x K) and a small B (K x N, ld
+// ldb), K, N <= 16*NB.  Element (m, k) of A_b sits at A[b*sa + m*rs + k*ks]
+// and (m, n) of C_b at C[b*sc + m*crs + n*cns]: a column-major matrix, one
+// t-slice of a mode product, or the row-major first-mode product.  Each wave
+// keeps its 16-column tiles of B as MFMA fragments in registers for the whole
+// launch; blocks stride over 64-row slabs, staged through LDS with lanes
+// along the rows (KFAST: along k, for row-major slabs).  The MFMA forms
+// C^T = B^T A^T so a store covers 16 consecutive rows.  Step (j, e) takes
+// from lane group kq the inner index k = 8j + 2kq + e.
+struct TGArgs {
+  const void* A; int64_t rs, ks, sa, M; int K;
+  const double* B; int ldb, N;
+  double* C; int64_t crs, cns, sc, nbatch;
+  double scale;
+};
 constexpr int TG_ROWS = 64;
-template <int NB>
-__global__ __launch_bounds__(256) void tall_gemm_kernel(const double* A, int64_t lda, int64_t M, int K,
-                                                        const double* B, int ldb, int N, double* C, int64_t ldc) {
+template <int NB, bool KFAST, typename Tin>
+__global__ __launch_bounds__(256) void tall_gemm_kernel(TGArgs g) {
   constexpr int KJ = 2 * NB, CT = (NB + 3) / 4, AP = 16 * NB + 2, NL = 16 * NB / 4;
   extern __shared__ __align__(16) double tsm[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int K = g.K, N = g.N;
   const int nbn = (N + 15) / 16;
   double2 bf[CT][KJ];
 #pragma unroll
@@ -455,33 +466,41 @@ __global__ __launch_bounds__(256) void tall_gemm_kernel(const double* A, int64_t
     for (int j = 0; j < KJ; ++j) {
       const int n = (wave + 4 * ct) * 16 + (lane & 15), k = 8 * j + 2 * (lane >> 4);
       const bool nin = n < N;
-      const double* bp = B + (int64_t)ldb * min(n, N - 1);
+      const double* bp = g.B + (int64_t)g.ldb * min(n, N - 1);
       bf[ct][j].x = (nin && k < K) ? bp[min(k, K - 1)] : 0.0;
       bf[ct][j].y = (nin && k + 1 < K) ? bp[min(k + 1, K - 1)] : 0.0;
     }
-  const int m = tid & 63, kg = tid >> 6;
+  const Tin* A = static_cast<const Tin*>(g.A);
   double ra[NL];
-  auto load = [&](int64_t r0) {
-    const int64_t r = r0 + m;
-    const bool rin = r < M;
-    const double* ap = A + (rin ? r : M - 1);
+  const int64_t spb = (g.M + TG_ROWS - 1) / TG_ROWS, nslab = spb * g.nbatch;
+  auto load = [&](int64_t slab) {
+    const int64_t b = slab / spb, r0 = (slab % spb) * TG_ROWS;
+    const Tin* ab = A + b * g.sa;
 #pragma unroll
     for (int i = 0; i < NL; ++i) {
-      const int k = kg + 4 * i;
-      const double v = ap[lda * min(k, K - 1)];
-      ra[i] = (rin && k < K) ? v : 0.0;
+      const int e = tid + 256 * i;
+      const int m = KFAST ? e / (16 * NB) : e % TG_ROWS;
+      const int k = KFAST ? e % (16 * NB) : e / TG_ROWS;
+      const int64_t r = r0 + m;
+      const double v = ttm_in(ab + g.rs * (r < g.M ? r : g.M - 1) + g.ks * min(k, K - 1));
+      ra[i] = (r < g.M && k < K) ? v : 0.0;
     }
   };
-  const int64_t nslab = (M + TG_ROWS - 1) / TG_ROWS;
   int64_t slab = blockIdx.x;
-  if (slab < nslab) load(slab * TG_ROWS);
+  if (slab < nslab) load(slab);
   for (; slab < nslab; slab += gridDim.x) {
-    const int64_t r0 = slab * TG_ROWS;
+    const int64_t b = slab / spb, r0 = (slab % spb) * TG_ROWS;
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < NL; ++i) tsm[m * AP + kg + 4 * i] = ra[i];
+    for (int i = 0; i < NL; ++i) {
+      const int e = tid + 256 * i;
+      const int m = KFAST ? e / (16 * NB) : e % TG_ROWS;
+      const int k = KFAST ? e % (16 * NB) : e / TG_ROWS;
+      tsm[m * AP + k] = ra[i];
+    }
     __syncthreads();
-    if (slab + gridDim.x < nslab) load((slab + gridDim.x) * TG_ROWS);
+    if (slab + gridDim.x < nslab) load(slab + gridDim.x);
+    double* cb = g.C + b * g.sc;
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
       const int c = wave + 4 * ct;
@@ -506,10 +525,28 @@ __global__ __launch_bounds__(256) void tall_gemm_kernel(const double* A, int64_t
         for (int v = 0; v < 4; ++v) {
           const int64_t r = r0 + rt * 16 + (lane & 15);
           const int n = c * 16 + (lane >> 4) + 4 * v;
-          if (r < M && n < N) C[r + ldc * n] = acc[rt][v];
+          if (r < g.M && n < N) cb[r * g.crs + (int64_t)n * g.cns] = g.scale * acc[rt][v];
         }
     }
   }
+}
+
+template <typename Tin>
+hipError_t launch_tg(const TGArgs& g, hipStream_t s) {
+  const int nb = max((g.K + 15) / 16, (g.N + 15) / 16);
+  const bool kfast = g.rs != 1 && g.ks == 1;
+  if (g.M <= 0 || g.K <= 0 || g.N <= 0 || g.nbatch <= 0 || nb > 7) return hipErrorInvalidValue;
+  const size_t lds = (size_t)TG_ROWS * (16 * nb + 2) * sizeof(double);
+  const int64_t nslab = (g.M + TG_ROWS - 1) / TG_ROWS * g.nbatch;
+  const dim3 grid((unsigned)std::min<int64_t>(nslab, 512));
+  switch (nb * 2 + (kfast ? 1 : 0)) {
+#define TG_CASE(NBV) \
+  case 2 * NBV: hipLaunchKernelGGL((tall_gemm_kernel<NBV, false, Tin>), grid, dim3(256), lds, s, g); break; \
+  case 2 * NBV + 1: hipLaunchKernelGGL((tall_gemm_kernel<NBV, true, Tin>), grid, dim3(256), lds, s, g); break;
+    TG_CASE(1) TG_CASE(2) TG_CASE(3) TG_CASE(4) TG_CASE(5) TG_CASE(6) TG_CASE(7)
+#undef TG_CASE
+  }
+  return hipGetLastError();
 }
 
 // core[a + Ra*(i + I*b)] = G2[i + I*(a + Ra*b)]  (inverse of the mode-2 unfolding)
@@ -595,6 +632,17 @@ hipError_t launch_tall_atb(const double* A, int64_t lda, const double* B, int64_
 
 hipError_t launch_ttm(const void* in, int in_type, int64_t L, int64_t I, int64_t T, const double* Q, int R,
                       double scale, double* out, hipStream_t s) {
+  if (I <= 112 && R <= 112 && (L == 1 || L >= TG_ROWS)) {   // MFMA slabs
+    TGArgs g;
+    if (L == 1) g = TGArgs{in, I, 1, 0, T, (int)I, Q, (int)I, R, out, R, 1, 0, 1, scale};
+    else g = TGArgs{in, 1, L, L * I, L, (int)I, Q, (int)I, R, out, 1, L, L * R, T, scale};
+    switch (in_type) {
+      case TR_F64: return launch_tg<double>(g, s);
+      case TR_F32: return launch_tg<float>(g, s);
+      case TR_BF16: return launch_tg<__bf16>(g, s);
+      default: return launch_tg<uint8_t>(g, s);
+    }
+  }
   const size_t lds = (size_t)I * TRB * sizeof(double);
   if (lds <= 64 * 1024) {
     const dim3 grid((unsigned)std::min<int64_t>(cdiv(L * T, 256), 16384), (unsigned)cdiv(R, TRB));
@@ -645,15 +693,6 @@ hipError_t launch_shift_and_add(double* G, int n, int64_t m, double* sbuf, hipSt
 
 hipError_t launch_tall_gemm(const double* A, int64_t lda, int64_t M, int K, const double* B, int ldb, int N,
                             double* C, int64_t ldc, hipStream_t s) {
-  const int nb = std::max((K + 15) / 16, (N + 15) / 16);
-  if (M <= 0 || K <= 0 || N <= 0 || nb > 7) return hipErrorInvalidValue;
-  const size_t lds = (size_t)TG_ROWS * (16 * nb + 2) * sizeof(double);
-  const dim3 grid((unsigned)std::min<int64_t>(cdiv(M, TG_ROWS), 512));
-  switch (nb) {
-#define TG_CASE(NBV) \
-  case NBV: hipLaunchKernelGGL(tall_gemm_kernel<NBV>, grid, dim3(256), lds, s, A, lda, M, K, B, ldb, N, C, ldc); break;
-    TG_CASE(1) TG_CASE(2) TG_CASE(3) TG_CASE(4) TG_CASE(5) TG_CASE(6) TG_CASE(7)
-#undef TG_CASE
-  }
-  return hipGetLastError();
+  TGArgs g{A, 1, lda, 0, M, K, B, ldb, N, C, 1, ldc, 0, 1, 1.0};
+  return launch_tg<double>(g, s);
 }
