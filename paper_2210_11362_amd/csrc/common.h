@@ -133,7 +133,7 @@ hipError_t launch_transpose(const double* A, int64_t rows, int64_t cols, double*
 // C = A B for a tall column-major A (M x K) and a small B (K x N), K, N <= 112.
 hipError_t launch_tall_gemm(const double* A, int64_t lda, int64_t M, int K, const double* B, int ldb, int N,
                             double* C, int64_t ldc, hipStream_t s);
-hipError_t launch_table_to_v2(const double* T, int64_t J, int Ra, int Rb, double* V2, hipStream_t s);
+hipError_t launch_table_to_v2(const double* T, int64_t J, int64_t L, int Ra, int Rb, double* V2, hipStream_t s);
 hipError_t launch_shift_and_add(double* G, int n, int64_t m, double* sbuf, hipStream_t s);
 hipError_t launch_core_fold(const double* G2, int64_t I, int Ra, int Rb, double* core, hipStream_t s);
 hipError_t launch_chol_inv(const double* S, int n, double* L, double* LT, double* LinvT, double* work, int* status,

@@ -106,7 +106,8 @@ __global__ __launch_bounds__(1024) void householder_qr_kernel(double* A, int64_t
 
 // C_part[chunk] = A^T B over rows [chunk*kc, ...): A is K x P, B is K x Q,
 // both column-major (lda, ldb).  Mode 1 reads A through the Multi-TTM layout:
-// A(k, p) = Y[l + L*(p + Ip*t)] with the cyclic row index k = t + T*l.
+// A(k, p) = Y[l + L*(p + Ip*t)] with the row index k = l + L*t, the order in
+// which Y is stored (B's rows come in the same order).
 struct TallArgs {
   const double* A; int64_t lda;
   const double* B; int64_t ldb;
@@ -134,7 +135,7 @@ __global__ __launch_bounds__(256) void tall_atb_kernel(TallArgs g) {
         if (p < g.P) {
           if (g.mode == 0) av = g.A[k + g.lda * p];
           else {
-            const int64_t t = k % g.T, l = k / g.T;
+            const int64_t l = k % g.L, t = k / g.L;
             av = g.A[l + g.L * (p + g.Ip * t)];
           }
         }
@@ -178,7 +179,7 @@ __global__ __launch_bounds__(256) void tall_atb_rb_kernel(TallArgs g) {
         if (g.mode == 0) {
           a = g.A[kc + g.lda * pc];
         } else {
-          const int64_t t = kc % g.T, l = kc / g.T;
+          const int64_t l = kc % g.L, t = kc / g.L;
           a = g.A[l + g.L * (pc + g.Ip * t)];
         }
         av[u] = (kin && p < g.P) ? a : 0.0;
@@ -209,8 +210,8 @@ __global__ __launch_bounds__(256) void tall_atb_rb_kernel(TallArgs g) {
 // stored as [column][k] and consumed by the four waves, which split the
 // 16x16 output tiles between them.  Element (k, p) of A sits at
 // base(k) + sp * p: base(k) = k, sp = lda in the plain layout, and
-// base(k) = l + L*Ip*t, sp = L in the Multi-TTM layout (t = k mod T,
-// l = k div T).  With A == B (a Gram matrix) only the tiles on or above the
+// base(k) = l + L*Ip*t, sp = L in the Multi-TTM layout (l = k mod L,
+// t = k div L).  With A == B (a Gram matrix) only the tiles on or above the
 // diagonal are formed and each is written to both halves, so the result is
 // exactly symmetric.  Within a slab, MFMA step (j, e) takes from lane group
 // kq the row k = 8j + 2kq + e for both operands.
@@ -260,7 +261,7 @@ __global__ __launch_bounds__(256) void tall_atb_lds_kernel(TallArgs g) {
     const bool kin = k < k1;
     const int64_t kc = kin ? k : k0;
     int64_t base = kc;
-    if (g.mode != 0) { const int64_t t = kc % g.T, l = kc / g.T; base = l + g.L * g.Ip * t; }
+    if (g.mode != 0) { const int64_t l = kc % g.L, t = kc / g.L; base = l + g.L * g.Ip * t; }
     const double* pa = g.A + base;
     const double* pb = g.B + kc;
 #pragma unroll
@@ -406,27 +407,37 @@ __global__ void transpose_kernel(const double* A, int64_t rows, int64_t cols, do
   At[j + cols * i] = A[e];
 }
 
-// V2[k + J*(a + Ra*b)] = T[k*C + b + Rb*a] (bond order of the subchain table
-// turned into the column order a + R_n*b of G_n(2)).
-__global__ void table_to_v2_kernel(const double* T, int64_t J, int Ra, int Rb, double* V2) {
+// V2[k' + J*(a + Ra*b)] = T[k*C + b + Rb*a]: the bond order of the subchain
+// table turned into the column order a + R_n*b of G_n(2), and the rows
+// reordered from the chain's cyclic index k = t + (J/L)*l (t over the modes
+// after n, l over those before it) to k' = l + L*t, the order in which the
+// Multi-TTM result stores them.  A row permutation leaves the Gram matrix,
+// the triangular factor and W_n = Y_[n]^T Q_0 unchanged.
+__device__ __forceinline__ int64_t v2_src_row(int64_t kp, int64_t J, int64_t L) {
+  return kp / L + (J / L) * (kp % L);
+}
+__global__ void table_to_v2_kernel(const double* T, int64_t J, int64_t L, int Ra, int Rb, double* V2) {
   const int64_t C = (int64_t)Ra * Rb;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= J * C) return;
-  const int64_t k = e % J, col = e / J;
+  const int64_t kp = e % J, col = e / J;
   const int64_t a = col % Ra, b = col / Ra;
-  V2[e] = T[k * C + b + Rb * a];
+  V2[e] = T[v2_src_row(kp, J, L) * C + b + Rb * a];
 }
 
-// The same reordering through LDS: a block moves V2T_ROWS table rows (read
-// whole and contiguous) and writes each output column as one contiguous run.
+// The same reordering through LDS: a block gathers V2T_ROWS table rows (each
+// read whole and contiguous) and writes each output column as one run.
 constexpr int V2T_ROWS = 32;
-__global__ __launch_bounds__(256) void table_to_v2_tiled_kernel(const double* T, int64_t J, int Ra, int Rb,
-                                                                 double* V2) {
+__global__ __launch_bounds__(256) void table_to_v2_tiled_kernel(const double* T, int64_t J, int64_t L, int Ra,
+                                                                 int Rb, double* V2) {
   extern __shared__ __align__(16) double vsm[];
   const int C = Ra * Rb, pitch = C + 1;
   const int64_t k0 = (int64_t)blockIdx.x * V2T_ROWS;
   const int nk = (int)min<int64_t>(V2T_ROWS, J - k0);
-  for (int e = threadIdx.x; e < nk * C; e += 256) vsm[(e / C) * pitch + e % C] = T[k0 * C + e];
+  for (int e = threadIdx.x; e < nk * C; e += 256) {
+    const int kl = e / C, c = e % C;
+    vsm[kl * pitch + c] = T[v2_src_row(k0 + kl, J, L) * C + c];
+  }
   __syncthreads();
   for (int e = threadIdx.x; e < V2T_ROWS * C; e += 256) {
     const int kl = e % V2T_ROWS, col = e / V2T_ROWS;
@@ -434,7 +445,6 @@ __global__ __launch_bounds__(256) void table_to_v2_tiled_kernel(const double* T,
     if (kl < nk) V2[k0 + kl + J * col] = vsm[kl * pitch + b + Rb * a];
   }
 }
-
 
 // Batched C_b = scale * A_b B for tall A_b (M x K) and a small B (K x N, ld
 // ldb), K, N <= 16*NB.  Element (m, k) of A_b sits at A[b*sa + m*rs + k*ks]
@@ -670,13 +680,15 @@ hipError_t launch_transpose(const double* A, int64_t rows, int64_t cols, double*
   return hipGetLastError();
 }
 
-hipError_t launch_table_to_v2(const double* T, int64_t J, int Ra, int Rb, double* V2, hipStream_t s) {
+hipError_t launch_table_to_v2(const double* T, int64_t J, int64_t L, int Ra, int Rb, double* V2, hipStream_t s) {
+  if (L <= 0 || J % L != 0) return hipErrorInvalidValue;
   const size_t lds = (size_t)V2T_ROWS * (Ra * Rb + 1) * sizeof(double);
   if (lds <= 64 * 1024) {
-    hipLaunchKernelGGL(table_to_v2_tiled_kernel, dim3((unsigned)cdiv(J, V2T_ROWS)), dim3(256), lds, s, T, J, Ra, Rb, V2);
+    hipLaunchKernelGGL(table_to_v2_tiled_kernel, dim3((unsigned)cdiv(J, V2T_ROWS)), dim3(256), lds, s, T, J, L, Ra, Rb,
+                       V2);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(table_to_v2_kernel, dim3(cdiv(J * Ra * Rb, 256)), dim3(256), 0, s, T, J, Ra, Rb, V2);
+  hipLaunchKernelGGL(table_to_v2_kernel, dim3(cdiv(J * Ra * Rb, 256)), dim3(256), 0, s, T, J, L, Ra, Rb, V2);
   return hipGetLastError();
 }
 

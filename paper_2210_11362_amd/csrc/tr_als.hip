@@ -831,7 +831,10 @@ int update_mode_qr(tr_als_ctx* c, int m, int prec) {
   // V_n[2] (J' x n)
   int rc = build_table_ex(c, chain, Rb, c->qT, c->qR, c->qr_r, c->qY0, c->qY1);
   if (rc) return rc;
-  HIPCHK(c, launch_table_to_v2(c->qT, Jp, Ra, Rb, c->qV2, s));
+  // rows of V_n[2] (and Q_0) in the order of the Multi-TTM result below
+  int64_t Lrows = 1;
+  for (int j = 0; j < m; ++j) Lrows *= c->qr_r[j];
+  HIPCHK(c, launch_table_to_v2(c->qT, Jp, Lrows, Ra, Rb, c->qV2, s));
   // shifted Cholesky-QR: three passes A <- A L^{-T}, R^T = L1 L2 L3
   double* A = c->qV2;
   double* bufs[2] = {c->qQa, c->qQb};
