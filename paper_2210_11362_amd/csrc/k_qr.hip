@@ -104,6 +104,142 @@ __global__ __launch_bounds__(1024) void householder_qr_kernel(double* A, int64_t
   }
 }
 
+// Sum over the 64 lanes of a wave; the butterfly leaves the same bits in every lane.
+__device__ __forceinline__ double wave_sum64(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// The same factorization for small unfoldings (m <= 64*RT, n <= 16*CW, the
+// reflectors fitting in LDS).  Wave w keeps columns j = w + 16c in registers,
+// rows across lanes (i = lane + 64t).  Step k: the wave owning column k forms
+// the reflector from its registers and stores it in LDS; after one barrier
+// every wave applies it to its own trailing columns.  Q = H_0 ... H_{r-1}[I_r; 0]
+// then needs no barrier: each wave applies the reflectors to its own columns of
+// Q, skipping H_k for k > j, which leaves e_j unchanged (v_k is zero above row k).
+template <int RT, int CW>
+__global__ __launch_bounds__(1024) void householder_qr_reg_kernel(const double* A, int m, int n, double* Q,
+                                                                  double* R) {
+  extern __shared__ double vs[];   // reflector k at vs[k*m + i], zero for i < k
+  __shared__ double tau_s[16 * CW];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = min(m, n);
+  double a[CW][RT];
+#pragma unroll
+  for (int c = 0; c < CW; ++c)
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const int i = lane + 64 * t, j = wave + 16 * c;
+      a[c][t] = (i < m && j < n) ? A[i + (int64_t)m * j] : 0.0;
+    }
+  for (int k = 0; k < r; ++k) {
+    if (wave == (k & 15)) {
+      const int kc = k >> 4;
+      double col[RT];
+#pragma unroll
+      for (int t = 0; t < RT; ++t) col[t] = 0.0;
+#pragma unroll
+      for (int c = 0; c < CW; ++c)
+        if (c == kc) {
+#pragma unroll
+          for (int t = 0; t < RT; ++t) col[t] = a[c][t];
+        }
+      double s = 0.0, x0p = 0.0;
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        const int i = lane + 64 * t;
+        if (i >= k && i < m) s += col[t] * col[t];
+        if (i == k) x0p = col[t];
+      }
+      const double nrm2 = wave_sum64(s);
+      const double x0 = __shfl(x0p, k & 63);
+      const double nrm = sqrt(nrm2);
+      const double alpha = (x0 >= 0.0) ? -nrm : nrm;
+      const double v0 = x0 - alpha;
+      const double vtv = nrm2 - x0 * x0 + v0 * v0;
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        const int i = lane + 64 * t;
+        if (i < m) vs[(int64_t)k * m + i] = (i < k) ? 0.0 : (i == k ? v0 : col[t]);
+      }
+      if (lane == 0) tau_s[k] = vtv > 0.0 ? 2.0 / vtv : 0.0;
+      // column k is final: R's entries above the diagonal, alpha on it, zeros below
+#pragma unroll
+      for (int c = 0; c < CW; ++c)
+        if (c == kc) {
+#pragma unroll
+          for (int t = 0; t < RT; ++t) {
+            const int i = lane + 64 * t;
+            if (i == k) a[c][t] = alpha;
+            else if (i > k) a[c][t] = 0.0;
+          }
+        }
+    }
+    __syncthreads();
+    const double beta = tau_s[k];
+    double v[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const int i = lane + 64 * t;
+      v[t] = (i < m) ? vs[(int64_t)k * m + i] : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < CW; ++c) {
+      const int j = wave + 16 * c;
+      if (j > k && j < n) {
+        double d = 0.0;
+#pragma unroll
+        for (int t = 0; t < RT; ++t) d += v[t] * a[c][t];
+        const double f = beta * wave_sum64(d);
+#pragma unroll
+        for (int t = 0; t < RT; ++t) a[c][t] -= f * v[t];
+      }
+    }
+  }
+  // R (r x n): the upper part of the first r rows
+#pragma unroll
+  for (int c = 0; c < CW; ++c)
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const int i = lane + 64 * t, j = wave + 16 * c;
+      if (i < r && j < n) R[i + (int64_t)r * j] = (i <= j) ? a[c][t] : 0.0;
+    }
+  // Q (m x r); the last step's barrier made every reflector visible
+#pragma unroll
+  for (int c = 0; c < CW; ++c)
+#pragma unroll
+    for (int t = 0; t < RT; ++t) a[c][t] = (lane + 64 * t == wave + 16 * c) ? 1.0 : 0.0;
+  const int jmax = min(r - 1, wave + 16 * (CW - 1));
+  for (int k = jmax; k >= 0; --k) {
+    const double beta = tau_s[k];
+    double v[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const int i = lane + 64 * t;
+      v[t] = (i < m) ? vs[(int64_t)k * m + i] : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < CW; ++c) {
+      const int j = wave + 16 * c;
+      if (j >= k && j < r) {
+        double d = 0.0;
+#pragma unroll
+        for (int t = 0; t < RT; ++t) d += v[t] * a[c][t];
+        const double f = beta * wave_sum64(d);
+#pragma unroll
+        for (int t = 0; t < RT; ++t) a[c][t] -= f * v[t];
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < CW; ++c)
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const int i = lane + 64 * t, j = wave + 16 * c;
+      if (i < m && j < r) Q[i + (int64_t)m * j] = a[c][t];
+    }
+}
+
 // C_part[chunk] = A^T B over rows [chunk*kc, ...): A is K x P, B is K x Q,
 // both column-major (lda, ldb).  Mode 1 reads A through the Multi-TTM layout:
 // A(k, p) = Y[l + L*(p + Ip*t)] with the row index k = l + L*t, the order in
@@ -593,6 +729,21 @@ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 hipError_t launch_householder_qr(double* A, int64_t m, int n, double* V, double* tau, double* Q, double* R,
                                  hipStream_t s) {
+  const int64_t r = std::min<int64_t>(m, n);
+  const size_t lds = (size_t)(m * r) * sizeof(double);
+  if (m <= 256 && n <= 128 && lds <= 128 * 1024) {   // registers + reflectors in LDS
+    const void* k = m <= 64    ? (const void*)householder_qr_reg_kernel<1, 8>
+                    : m <= 128 ? (const void*)householder_qr_reg_kernel<2, 8>
+                               : (const void*)householder_qr_reg_kernel<4, 8>;
+    if (lds > 64 * 1024) {
+      const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    const double* Ac = A;
+    const int mi = (int)m;
+    void* args[] = {(void*)&Ac, (void*)&mi, (void*)&n, (void*)&Q, (void*)&R};
+    return hipLaunchKernel(k, dim3(1), dim3(1024), args, lds, s);
+  }
   hipLaunchKernelGGL(householder_qr_kernel, dim3(1), dim3(1024), 0, s, A, m, n, V, tau, Q, R);
   return hipGetLastError();
 }

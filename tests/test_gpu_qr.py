@@ -15,6 +15,9 @@ QR_SHAPES = [
     ((3, 8, 9, 7), (2, 2, 3, 2)),          # core 1: I = 3 < R_1 R_2 = 4 (square Q, trapezoidal R)
     ((6, 7, 5, 8, 6), (2, 3, 2, 2, 3)),
     ((40, 36, 30), (5, 6, 4)),
+    ((100, 12, 10), (3, 4, 2)),            # core QR with 65..128 rows per column
+    ((150, 20, 12), (2, 3, 2)),            # 129..256 rows
+    ((300, 8, 6), (2, 2, 3)),              # more than 256 rows: the global-memory factorization
 ]
 
 
