@@ -452,6 +452,104 @@ __global__ __launch_bounds__(256) void tall_atb_lds_kernel(TallArgs g) {
 
 // C = sum over chunks; a block takes 64 outputs, its four waves each sum a
 // contiguous quarter of the chunks, and the quarters are added in order.
+// Gram C = A^T A of a tall column-major A (K x P, P <= 112) with no LDS
+// staging.  The MFMA fragment of a 16-column block (lane: column lane&15, rows
+// 4*(lane>>4) .. +3 of a 16-row group) is the same for both operands, so each
+// wave loads every block once per 16 rows and accumulates all NB(NB+1)/2 tiles
+// of the block upper triangle, prefetching the next group while the MFMAs run.
+// Waves take interleaved 16-row groups of the workgroup's chunk; their sums are
+// added in LDS in wave order, so the result does not depend on timing.
+template <int NB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void gram_frag_kernel(
+    const double* A, int64_t lda, int64_t K, int P, int64_t kc, double* part) {
+  constexpr int NT = NB * (NB + 1) / 2;
+  extern __shared__ __align__(16) double gred[];   // NT * 256 doubles
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int cl = lane & 15, kq = lane >> 4;
+  const int64_t k0 = (int64_t)blockIdx.x * kc;
+  const int64_t k1 = min(K, k0 + kc);
+  const double* pc[NB];
+  bool cin[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int c = b * 16 + cl;
+    cin[b] = c < P;
+    pc[b] = A + lda * (int64_t)min(c, P - 1);
+  }
+  f64x4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = f64x4{0, 0, 0, 0};
+  double2 f[NB][2], nx[NB][2];
+  auto load = [&](int64_t g, double2 (&d)[NB][2]) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int64_t k = g + 4 * kq + 2 * h;
+        if (cin[b] && k + 1 < k1) {
+          d[b][h] = *reinterpret_cast<const double2*>(pc[b] + k);
+        } else {
+          d[b][h].x = (cin[b] && k < k1) ? pc[b][k] : 0.0;
+          d[b][h].y = 0.0;
+        }
+      }
+  };
+  int64_t g = k0 + 16 * wave;
+  if (g < k1) load(g, f);
+  for (; g < k1; g += 64) {
+    const bool more = g + 64 < k1;
+    if (more) load(g + 64, nx);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      int t = 0;
+#pragma unroll
+      for (int bq = 0; bq < NB; ++bq)
+#pragma unroll
+        for (int bp = 0; bp <= bq; ++bp, ++t) mma64(acc[t], f[bp][h].x, f[bq][h].x);
+      t = 0;
+#pragma unroll
+      for (int bq = 0; bq < NB; ++bq)
+#pragma unroll
+        for (int bp = 0; bp <= bq; ++bp, ++t) mma64(acc[t], f[bp][h].y, f[bq][h].y);
+    }
+    if (more) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        f[b][0] = nx[b][0];
+        f[b][1] = nx[b][1];
+      }
+    }
+  }
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          double* p = gred + (t * 64 + lane) * 4 + v;
+          *p = (w == 0) ? acc[t][v] : *p + acc[t][v];
+        }
+    }
+    __syncthreads();
+  }
+  double* out = part + (size_t)blockIdx.x * P * P;
+  for (int e = threadIdx.x; e < NT * 64; e += 256) {
+    const int t = e >> 6, l = e & 63;
+    int bq = 0, r = t;
+    while (r > bq) { r -= bq + 1; ++bq; }
+    const int bp = r;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = bp * 16 + (l >> 4) + 4 * v, col = bq * 16 + (l & 15);
+      if (row < P && col < P) {
+        const double x = gred[e * 4 + v];
+        out[row + (int64_t)P * col] = x;
+        if (bp != bq) out[col + (int64_t)P * row] = x;
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void sum_chunks_kernel(const double* part, int nchunk, int64_t n, double* C) {
   __shared__ double red[4][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -759,6 +857,23 @@ hipError_t launch_tall_atb(const double* A, int64_t lda, const double* B, int64_
   nchunk = std::min<int64_t>(nchunk, cdiv(K, 64));
   const bool gram = mode == 0 && A == B && lda == ldb && P == Q;
   const int nb = std::max((P + 15) / 16, (Q + 15) / 16);
+  if (gram && nb <= 7 && lda % 2 == 0 && (reinterpret_cast<uintptr_t>(A) & 15) == 0) {   // fragments in registers
+    nchunk = std::min<int64_t>(nchunk, 256);
+    const int64_t kc = cdiv(cdiv(K, nchunk), 64) * 64;
+    nchunk = cdiv(K, kc);
+    const size_t lds = (size_t)(nb * (nb + 1) / 2) * 256 * sizeof(double);
+    const dim3 grid((unsigned)nchunk);
+    switch (nb) {
+#define GRAM_FRAG(B) \
+  case B: hipLaunchKernelGGL(gram_frag_kernel<B>, grid, dim3(256), lds, s, A, lda, K, P, kc, part); break;
+      GRAM_FRAG(1) GRAM_FRAG(2) GRAM_FRAG(3) GRAM_FRAG(4) GRAM_FRAG(5) GRAM_FRAG(6) GRAM_FRAG(7)
+#undef GRAM_FRAG
+      default: return hipErrorInvalidValue;
+    }
+    const int64_t n = (int64_t)P * Q;
+    hipLaunchKernelGGL(sum_chunks_kernel, dim3(cdiv(n, 64)), dim3(256), 0, s, (const double*)part, (int)nchunk, n, C);
+    return hipGetLastError();
+  }
   const size_t lds = (size_t)(gram ? 1 : 2) * nb * 16 * GST * sizeof(double);
   if (nb <= 8 && lds <= 64 * 1024) {   // LDS-staged slabs
     g.kc = cdiv(cdiv(K, nchunk), GKS) * GKS;
