@@ -18,6 +18,9 @@ QR_SHAPES = [
     ((100, 12, 10), (3, 4, 2)),            # core QR with 65..128 rows per column
     ((150, 20, 12), (2, 3, 2)),            # 129..256 rows
     ((300, 8, 6), (2, 2, 3)),              # more than 256 rows: the global-memory factorization
+    ((11, 13, 9), (3, 3, 3)),              # odd V_n[2] height: the LDS-staged Gram
+    ((60, 60, 60), (7, 7, 7)),             # odd height, four 16-column blocks
+    ((110, 110, 110), (10, 10, 10)),       # even height, seven blocks: the register-fragment Gram
 ]
 
 
