@@ -456,7 +456,7 @@ __global__ __launch_bounds__(256) void tall_atb_lds_kernel(TallArgs g) {
 // staging.  The MFMA fragment of a 16-column block (lane: column lane&15, rows
 // 4*(lane>>4) .. +3 of a 16-row group) is the same for both operands, so each
 // wave loads every block once per 16 rows and accumulates all NB(NB+1)/2 tiles
-// of the block upper triangle, prefetching the next group while the MFMAs run.
+// of the block upper triangle, loading the next group while the MFMAs run.
 // Waves take interleaved 16-row groups of the workgroup's chunk; their sums are
 // added in LDS in wave order, so the result does not depend on timing.
 template <int NB>
@@ -479,46 +479,45 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   f64x4 acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = f64x4{0, 0, 0, 0};
-  double2 f[NB][2], nx[NB][2];
-  auto load = [&](int64_t g, double2 (&d)[NB][2]) {
+  double2 f[NB][2];
+  // half h of the fragments of the 16-row group at g: rows g + 4kq + 2h, +1
+  auto load = [&](int64_t g, int h) {
 #pragma unroll
-    for (int b = 0; b < NB; ++b)
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int64_t k = g + 4 * kq + 2 * h;
-        if (cin[b] && k + 1 < k1) {
-          d[b][h] = *reinterpret_cast<const double2*>(pc[b] + k);
-        } else {
-          d[b][h].x = (cin[b] && k < k1) ? pc[b][k] : 0.0;
-          d[b][h].y = 0.0;
-        }
+    for (int b = 0; b < NB; ++b) {
+      const int64_t k = g + 4 * kq + 2 * h;
+      if (cin[b] && k + 1 < k1) {
+        f[b][h] = *reinterpret_cast<const double2*>(pc[b] + k);
+      } else {
+        f[b][h].x = (cin[b] && k < k1) ? pc[b][k] : 0.0;
+        f[b][h].y = 0.0;
       }
+    }
   };
+  auto mfma = [&](int h) {
+    int t = 0;
+#pragma unroll
+    for (int bq = 0; bq < NB; ++bq)
+#pragma unroll
+      for (int bp = 0; bp <= bq; ++bp, ++t) mma64(acc[t], f[bp][h].x, f[bq][h].x);
+    t = 0;
+#pragma unroll
+    for (int bq = 0; bq < NB; ++bq)
+#pragma unroll
+      for (int bp = 0; bp <= bq; ++bp, ++t) mma64(acc[t], f[bp][h].y, f[bq][h].y);
+  };
+  // each half is reloaded for the next group as soon as its MFMAs are issued,
+  // so the loads overlap the other half's MFMAs without a second buffer
   int64_t g = k0 + 16 * wave;
-  if (g < k1) load(g, f);
+  if (g < k1) {
+    load(g, 0);
+    load(g, 1);
+  }
   for (; g < k1; g += 64) {
     const bool more = g + 64 < k1;
-    if (more) load(g + 64, nx);
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      int t = 0;
-#pragma unroll
-      for (int bq = 0; bq < NB; ++bq)
-#pragma unroll
-        for (int bp = 0; bp <= bq; ++bp, ++t) mma64(acc[t], f[bp][h].x, f[bq][h].x);
-      t = 0;
-#pragma unroll
-      for (int bq = 0; bq < NB; ++bq)
-#pragma unroll
-        for (int bp = 0; bp <= bq; ++bp, ++t) mma64(acc[t], f[bp][h].y, f[bq][h].y);
-    }
-    if (more) {
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        f[b][0] = nx[b][0];
-        f[b][1] = nx[b][1];
-      }
-    }
+    mfma(0);
+    if (more) load(g + 64, 0);
+    mfma(1);
+    if (more) load(g + 64, 1);
   }
   for (int w = 0; w < 4; ++w) {
     if (wave == w) {
