@@ -12,7 +12,12 @@ to match the paper's notation.
 Parity status of each function (pins live in tests/test_oracle_pins.py):
   tr_entry, tr_full_bruteforce ... pinned: they ARE the trace definition (Sec. 1),
                                    cross-checked against an exact integer case
-  unfold_*, subchain*, tr_full ... pinned by brute-force trace evaluation
+  unfold_mode, fold_mode,
+  unfold_classical, unfold_n ..... pinned entry by entry against the index maps
+                                   of their definitions (Sec. 2)
+  subchain*, tr_full ............. pinned by brute-force trace evaluation
+  regular_objective .............. pinned by the brute-force residual norm, the
+                                   same for every mode, = rel_error * ||X||
   ttm, multi_ttm ................. pinned by Prop. 2.1 (Kronecker form) and loops
   subchain_product ............... pinned by Prop. 2.2 and by slice products
   gram_tensor, general_contract,

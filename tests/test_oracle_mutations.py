@@ -18,6 +18,9 @@ PINS = [
     P.test_cheap_fit_identities,
     P.test_variants_equivalent,
     P.test_tr_inner_product_and_printed_form,
+    P.test_unfold_classical_by_definition,
+    P.test_unfold_n_by_definition,
+    P.test_regular_objective_is_the_residual_norm,
 ]
 
 
@@ -71,7 +74,26 @@ def _contract_wrong(A, B):
     return np.einsum("ijrk,kljs->ilrs", A, B, optimize=True)
 
 
+def _unfold_classical_cyclic(X, n):
+    return T.unfold_mode(X, n)
+
+
+def _unfold_n_c_order(X, n):
+    rows = int(np.prod(X.shape[:n]))
+    return np.ascontiguousarray(X).reshape((rows, -1), order="C")
+
+
+def _objective_wrong_core(X, cores, n):
+    N = len(cores)
+    A = T.subchain_unfold2(cores, n)
+    G = cores[n % N] if cores[n % N].shape == cores[n - 1].shape else 2.0 * cores[n - 1]
+    return float(np.linalg.norm(T.unfold_mode(X, n) - T.core_unfold2(G) @ A.T))
+
+
 MUTATIONS = [
+    ("unfold_classical", _unfold_classical_cyclic),
+    ("unfold_n", _unfold_n_c_order),
+    ("regular_objective", _objective_wrong_core),
     ("_chain_order", _reversed_chain),
     ("core_unfold2", _core_unfold2_swapped),
     ("subchain_unfold2", _subchain_unfold2_swapped),

@@ -94,6 +94,47 @@ def test_unfold_mode_by_definition():
         np.testing.assert_array_equal(O.fold_mode(Xn, n, DIMS), X)
 
 
+def _col_classical(idx, dims, n):
+    """Column of X_(n) by the definition: indices i_1..i_{n-1}, i_{n+1}..i_N,
+    first fastest."""
+    col, stride = 0, 1
+    for k in range(len(dims)):
+        if k == n - 1:
+            continue
+        col += idx[k] * stride
+        stride *= dims[k]
+    return col
+
+
+def test_unfold_classical_by_definition():
+    """Classical mode-n unfolding (Sec. 2, its definition) entry by entry."""
+    g = np.random.default_rng(21)
+    X = np.asfortranarray(g.standard_normal(DIMS))
+    for n in range(1, 5):
+        Xc = O.unfold_classical(X, n)
+        assert Xc.shape == (DIMS[n - 1], int(np.prod(DIMS)) // DIMS[n - 1])
+        for idx in itertools.product(*[range(d) for d in DIMS]):
+            assert Xc[idx[n - 1], _col_classical(idx, DIMS, n)] == X[idx]
+    # mode 1 and mode N: the classical and the cyclic unfoldings coincide
+    np.testing.assert_array_equal(O.unfold_classical(X, 1), O.unfold_mode(X, 1))
+    # for n = N the cyclic order (i_1..i_{N-1}) is also the classical one
+    np.testing.assert_array_equal(O.unfold_classical(X, 4), O.unfold_mode(X, 4))
+
+
+def test_unfold_n_by_definition():
+    """n-unfolding (Sec. 2, its definition): rows (i_1..i_n), columns
+    (i_{n+1}..i_N), first index fastest on both sides."""
+    g = np.random.default_rng(22)
+    X = np.asfortranarray(g.standard_normal(DIMS))
+    for n in range(1, 4):
+        Xu = O.unfold_n(X, n)
+        assert Xu.shape == (int(np.prod(DIMS[:n])), int(np.prod(DIMS[n:])))
+        for idx in itertools.product(*[range(d) for d in DIMS]):
+            row = sum(idx[k] * int(np.prod(DIMS[:k])) for k in range(n))
+            col = sum(idx[k] * int(np.prod(DIMS[n:k])) for k in range(n, 4))
+            assert Xu[row, col] == X[idx]
+
+
 def test_reconstruction_every_mode():
     cores = rand_cores(DIMS, RANKS, 3)
     Xb = O.tr_full_bruteforce(cores)
@@ -371,6 +412,23 @@ def test_tr_inner_product_and_printed_form():
     T = O.general_contract(O.general_contract(Ps[2], Ps[1]), Ps[0])
     printed = float(np.trace(T.reshape((T.shape[0] * T.shape[1], -1), order="F")))
     assert abs(printed - truth) > 1e-6 * abs(truth)
+
+
+def test_regular_objective_is_the_residual_norm():
+    """The LS objective of any mode equals ||X - TR(G)||_F with TR(G) built by the
+    brute-force trace (Sec. 1), so it is the same number for every n and equals
+    rel_error * ||X||_F."""
+    dims, ranks = (3, 4, 2, 3), (2, 3, 2, 2)
+    g = np.random.default_rng(38)
+    X = np.asfortranarray(g.standard_normal(dims))
+    cores = rand_cores(dims, ranks, 39)
+    truth = float(np.sqrt(np.sum((X - O.tr_full_bruteforce(cores)) ** 2)))
+    for n in range(1, 5):
+        assert O.regular_objective(X, cores, n) == pytest.approx(truth, rel=1e-13)
+    assert O.rel_error(X, cores) * float(np.linalg.norm(X)) == pytest.approx(truth, rel=1e-13)
+    # at the true cores of a noiseless planted tensor the objective vanishes
+    Xp = O.tr_full_bruteforce(cores)
+    assert O.regular_objective(Xp, cores, 2) <= 1e-12 * float(np.linalg.norm(Xp))
 
 
 def test_cheap_fit_identities():
