@@ -479,6 +479,7 @@ void tiny_fill(TinyJob* j, int N, const int64_t* dims, const int64_t* ranks, con
 }
 
 hipError_t launch_tiny_als(const TinyJob* d_jobs, int njobs, hipStream_t s) {
+  if (njobs < 1) return hipErrorInvalidValue;
   hipLaunchKernelGGL(tiny_als_kernel, dim3((unsigned)njobs), dim3(TT), 0, s, d_jobs);
   return hipGetLastError();
 }

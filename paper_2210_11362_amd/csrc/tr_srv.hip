@@ -318,9 +318,11 @@ void admit(tr_srv* srv, std::vector<int>* started, std::vector<int>* lanes_start
         forming = -1;
         for (size_t k = 0; k < srv->lanes.size(); ++k)
           if (srv->lanes[k].jobs.empty()) { forming = (int)k; break; }
-        if (forming >= 0) lanes_started->push_back(forming);
       }
       if (forming < 0 || !srv->arena.alloc(j->footprint, &off)) { ++q; continue; }
+      // a lane is started only once it holds a job: an idle lane picked while
+      // memory is full must not be launched with an empty batch
+      if (srv->lanes[forming].jobs.empty()) lanes_started->push_back(forming);
       j->off = off;
       j->slot = forming;
       j->state = TR_JOB_RUNNING;
@@ -363,6 +365,7 @@ void admit(tr_srv* srv, std::vector<int>* started, std::vector<int>* lanes_start
 // results to pinned memory, completion event.
 int start_batch(tr_srv* srv, Lane& ln) {
   hipStream_t s = ln.s;
+  if (ln.jobs.empty()) return TR_OK;
   size_t need = 0;
   for (const Job* j : ln.jobs) {
     need += PIN_HEAD;

@@ -7,6 +7,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# Guard bands behind every workspace buffer of every context the tests create
+# (read once, at the library's first context): the last GPU test asserts that
+# none was written.
+os.environ.setdefault("TR_ALS_CANARY", "1")
+
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")

@@ -114,10 +114,6 @@ def _mix_jobs():
     return jobs
 
 
-@pytest.mark.skip(reason="one run of this case ended in a host-side segmentation fault (no GPU fault reported) while "
-                         "the 1-slot server ran its jobs alone; the host code of the serving loop is clean under "
-                         "ASan and TSan on a CPU stand-in of the runtime, so no cause is shown yet and the case "
-                         "stays off the GPU until one is")
 def test_results_identical_alone_and_in_mix():
     jobs = _mix_jobs()
     kw = dict(eta=0.01, prec_mixed="bf16", nsweeps_mixed=4, prec_fin="f32", nsweeps_fin=2)

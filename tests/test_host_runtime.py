@@ -1,0 +1,138 @@
+"""Host code of the library on a CPU stand-in of the HIP runtime.
+
+The library's objects are linked against ``tests/hostrt/stand_in_hip.cpp``
+(no GPU needed, kernels not executed), and the C ABI is driven with the shapes
+of the GPU tests and with serving streams.  The stand-in checks every launch
+(grid, block, dynamic LDS, pointer arguments inside live allocations, operand
+extents of the modelled kernels), every copy and fill, graph captures (no
+fill, allocation, free or synchronisation while one is open) and which host
+threads call the runtime while a server is alive.
+"""
+import pytest
+
+from tests.hostrt import replay as R
+from tests.test_gpu_parity import INV_SHAPES, SHAPES
+from tests.test_gpu_qr import QR_SHAPES
+from tests.test_gpu_serving import LANE_JOBS, _mix_jobs
+
+GB = 1 << 30
+KW = dict(eta=0.01, prec_mixed="bf16", nsweeps_mixed=4, prec_fin="f32", nsweeps_fin=2)
+
+
+@pytest.fixture(scope="module")
+def host():
+    h = R.Host(R.build_host_lib())
+    h.L.fakehip_set_delay_us(0)
+    return h
+
+
+def _clean(h, what):
+    v = h.violations()
+    assert not v, f"{what}: {len(v)} problems, first: {v[:3]}"
+
+
+@pytest.mark.parametrize("dims,ranks", SHAPES + INV_SHAPES, ids=[f"{d}-{r}" for d, r in SHAPES + INV_SHAPES])
+def test_ne_contexts_stay_inside_their_buffers(host, dims, ranks):
+    host.reset()
+    codes = R.run_context(host, dims, ranks, precs=("f64", "f32", "bf16", "fp8"), xdt="f32")
+    assert all(rc == 0 for _, rc in codes), codes
+    _clean(host, f"NE {dims} {ranks}")
+    if len(dims) >= 3:   # order 2: the ring is one Gram, realigned without a product
+        assert host.L.fakehip_launches(b"gemm64_kernel") + host.L.fakehip_launches(b"gemm64_pair_kernel") > 0
+
+
+@pytest.mark.parametrize("dims,ranks", QR_SHAPES, ids=[f"{d}-{r}" for d, r in QR_SHAPES])
+def test_qr_contexts_stay_inside_their_buffers(host, dims, ranks):
+    host.reset()
+    codes = R.run_context(host, dims, ranks, variant="qr", precs=("f64", "bf16"), xdt="f64")
+    assert all(rc == 0 for _, rc in codes), codes
+    _clean(host, f"QR {dims} {ranks}")
+
+
+def test_ring_intermediates_exceed_one_gram_when_ranks_alternate(host):
+    """The ring's intermediates are R_{m+1}^2 x R_j^2: with alternating ranks
+    they exceed max_k (R_k R_{k+1})^2, the size the ring workspaces once had
+    (the launches of this shape then wrote 360 bytes past a 288-byte buffer).
+    The workspaces are now sized over the ring (previous test: in bounds)."""
+    dims, ranks = (6, 7, 5, 8, 6), (2, 3, 2, 2, 3)
+    host.reset()
+    R.run_context(host, dims, ranks, precs=("f64",), xdt="f64", sweeps=1)
+    one_gram = max((ranks[k] * ranks[(k + 1) % 5]) ** 2 for k in range(5))
+    ring = [m * n for m, n, realign, _ in host.gemm_log() if not realign]
+    assert max(ring) == 81 and one_gram == 36
+    _clean(host, "ring")
+
+
+def test_serving_alone_and_in_mix_host_side(host):
+    host.reset()
+    host.L.fakehip_set_delay_us(200)
+    jobs = _mix_jobs()
+    s = R.Server(host, 4 * GB, 1)
+    for j in jobs:
+        rc, jid = s.submit(j["dims"], j["ranks"], seed=j["seed"], **KW)
+        assert rc == 0
+        assert s.wait(jid).state == 2, s.error(jid)
+    assert s.close() == 1                      # only the executor thread called the runtime
+    host.L.fakehip_set_delay_us(10000)         # jobs in flight overlap the 2 ms arrivals
+    s = R.Server(host, 4 * GB, 6)
+    for k, j in enumerate(jobs):
+        assert s.submit(j["dims"], j["ranks"], seed=j["seed"], t_arrival=0.002 * k, **KW)[0] == 0
+    s.drain()
+    st = s.stats()
+    assert st["done"] == len(jobs) and st["failed"] == 0 and st["max_running"] >= 2
+    assert s.close() == 1
+    host.L.fakehip_set_delay_us(0)
+    _clean(host, "serving mix")
+
+
+def test_admission_under_a_tight_budget_host_side(host):
+    host.reset()
+    host.L.fakehip_set_delay_us(500)
+    dims, ranks = (40, 40, 40, 40), (5, 5, 5, 5)
+    s = R.Server(host, 4 * GB, 1)
+    rc, jid = s.submit(dims, ranks, seed=1, **KW)
+    F = s.wait(jid).footprint
+    s.close()
+    s = R.Server(host, int(2.5 * F), 8)
+    ids = [s.submit(dims, ranks, seed=10 + k, **KW)[1] for k in range(6)]
+    assert s.submit((60, 60, 60, 60), ranks, seed=2, **KW)[0] != 0      # can never fit
+    s.drain()
+    st = s.stats()
+    assert st["done"] == 6 and st["max_running"] == 2 and st["peak_in_use"] <= st["arena_bytes"]
+    adm = [s.poll(j).t_admit for j in ids]
+    assert adm == sorted(adm)
+    assert s.close() == 1
+    host.L.fakehip_set_delay_us(0)
+    _clean(host, "admission")
+
+
+def test_batch_lane_waiting_for_memory_launches_no_empty_batch(host):
+    """Small jobs that do not fit while the other lane runs leave the idle lane
+    unlaunched (an empty batch would be a zero-size grid)."""
+    host.reset()
+    host.L.fakehip_set_delay_us(3000)
+    s = R.Server(host, 3 << 20, 2, batch=True)
+    ids = [s.submit(d, r, seed=k, **KW)[1] for k, (d, r) in enumerate(LANE_JOBS * 4)]
+    s.drain()
+    assert all(s.poll(j).state == 2 and s.poll(j).batched for j in ids)
+    assert s.close() == 1
+    host.L.fakehip_set_delay_us(0)
+    _clean(host, "lanes")
+    assert host.L.fakehip_launches(b"tiny_als_kernel") > 1
+
+
+def test_serving_stream_host_side(host):
+    """300 Poisson arrivals, orders 3-5, modes 16-128, ranks 2-12, lanes on."""
+    host.reset()
+    host.L.fakehip_set_delay_us(300)
+    s = R.Server(host, 64 * GB, 8, batch=True)
+    res = [s.submit(j["dims"], j["ranks"], seed=j["seed"], t_arrival=j["t_arrival"], prec_mixed="bf16",
+                    nsweeps_mixed=8, prec_fin="f32", nsweeps_fin=2) for j in R.serving_stream(300)]
+    s.drain()
+    st = s.stats()
+    ok = sum(1 for rc, _ in res if rc == 0)
+    assert st["done"] == ok and st["failed"] == 0 and ok >= 280
+    assert s.close() == 1
+    host.L.fakehip_set_delay_us(0)
+    _clean(host, "stream")
+    assert host.L.fakehip_live_allocations() == 0
