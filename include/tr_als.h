@@ -162,6 +162,18 @@ int tr_als_debug_overruns(void);
 // last capture was abandoned (empty if none was); sweeps then launch eagerly.
 int tr_als_debug_graphs(const tr_als_ctx* ctx, char* note /*host, may be NULL*/, int note_len);
 
+// Introspection of the low-precision shadows of X that the contraction reads
+// (mixed precision; not a passage of the paper).  prec = TR_BF16 (BF16, round
+// to nearest even from the FP32 value of each entry) or TR_FP8 (OCP E4M3 of
+// float32(x) * s, one scale per tensor s = 448 / max|x|, round to nearest
+// even).  transposed = 0: the shadow in X's layout, numel entries; 1: the
+// transposed shadow, out[k + K r] = shadow(X[r + M k]) with K = *split_k and
+// M = numel / K (TR_EINVAL when the context keeps none).  Builds the shadow if
+// needed, copies it to `out` (device, numel * 2 or numel bytes, caller-owned),
+// synchronises the context's stream; *scale (host) receives s (1 for BF16).
+int tr_als_debug_shadow(tr_als_ctx* ctx, int prec, int transposed, void* out, float* scale /*host*/,
+                        int64_t* split_k /*host, may be NULL*/);
+
 /* ------------------------------------------------------------------------ *
  * Planted test tensors generated on the device.
  *

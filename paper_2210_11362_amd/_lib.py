@@ -41,6 +41,8 @@ _SIGS = {
     "tr_als_debug_overruns": (ctypes.c_int, []),
     "tr_als_debug_graphs": (ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.c_int]),
     "tr_als_profile_read": (ctypes.c_int, [_vp, _dp, _i64p, _dp]),
+    "tr_als_debug_shadow": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_float),
+                                           _i64p]),
 }
 
 

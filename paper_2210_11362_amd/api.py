@@ -117,6 +117,20 @@ class TRContext:
             C.check(r, self._h, "tr_als_debug_graphs")
         return r, buf.value.decode()
 
+    def shadow(self, prec: str, transposed: bool = False):
+        """(raw shadow bytes as a flat CUDA uint8 tensor, scale, split K) of
+        the BF16 or FP8 copy of X the contraction reads."""
+        import torch
+        numel = 1
+        for d in self.dims:
+            numel *= d
+        out = torch.empty(numel * (2 if prec == "bf16" else 1), dtype=torch.uint8, device=self.X.device)
+        sc, k = ctypes.c_float(), ctypes.c_int64()
+        C.check(C.lib().tr_als_debug_shadow(self._h, C.PREC[prec], 1 if transposed else 0,
+                                            ctypes.c_void_p(out.data_ptr()), ctypes.byref(sc), ctypes.byref(k)),
+                self._h, "tr_als_debug_shadow")
+        return out, sc.value, k.value
+
     def close(self):
         if getattr(self, "_h", None):
             C.lib().tr_als_destroy(self._h)

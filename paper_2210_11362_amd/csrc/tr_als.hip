@@ -422,7 +422,8 @@ XsCfg xs_config(const tr_als_ctx* c, int m, int prec) {
   return x;
 }
 
-XgArgs xg_config(const tr_als_ctx* c, int m, int prec, const void* X, int esize, bool transposed = false) {
+XgArgs xg_config(const tr_als_ctx* c, int m, int prec, const void* X, int esize, bool transposed = false,
+                 int mt_override = 0) {
   const Plan& p = c->plan[m];
   XgArgs g;
   g.X = X;
@@ -434,11 +435,13 @@ XgArgs xg_config(const tr_als_ctx* c, int m, int prec, const void* X, int esize,
   // 100^4 rank-10 workload with X streamed from HBM (not the last-level
   // cache): 128 rows, ~448 workgroups for BF16 (6 splits: 59.7 us against
   // 65-75 us for 5 or 7-13 splits), ~1024 for FP32 (MFMA-bound).
-  // TR_ALS_XG_MT / TR_ALS_XG_WGS override.
+  // TR_ALS_XG_MT / TR_ALS_XG_WGS override (read at every call, so a test can
+  // run the 128-row tiles on a small shape; the buffers are sized for both).
   g.MT = p.gM > 8192 ? 128 : 64;
-  static const int env_mt = getenv("TR_ALS_XG_MT") ? atoi(getenv("TR_ALS_XG_MT")) : 0;
-  static const int env_wgs = getenv("TR_ALS_XG_WGS") ? atoi(getenv("TR_ALS_XG_WGS")) : 0;
+  const int env_mt = getenv("TR_ALS_XG_MT") ? atoi(getenv("TR_ALS_XG_MT")) : 0;
+  const int env_wgs = getenv("TR_ALS_XG_WGS") ? atoi(getenv("TR_ALS_XG_WGS")) : 0;
   if (env_mt == 64 || env_mt == 128) g.MT = env_mt;
+  if (mt_override) g.MT = mt_override;
   const int64_t target_wgs = env_wgs > 0 ? env_wgs : ((prec == TR_F32 || prec == TR_F64) ? 1024 : 448);
   g.n_mt = (int)((p.gM + g.MT - 1) / g.MT);
   if (p.gC <= 128) { g.NT = (p.gC + 15) / 16 * 16; g.n_nt = 1; }
@@ -1089,9 +1092,11 @@ int trx_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ranks,
     for (int prec = TR_F64; prec <= TR_FP8; ++prec) {
       if (c->plan[m].regime == 1) {
         const int es = prec == TR_BF16 ? 2 : prec == TR_FP8 ? 1 : (x_dtype == TR_F64 ? 8 : 4);
-        XgArgs g = xg_config(c, m, prec, X, es);
-        pbytes = std::max(pbytes, xg_partial_bytes(g, prec));
-        btb = std::max(btb, xg_bt_bytes(g, prec));
+        for (int mt : {64, 128}) {
+          XgArgs g = xg_config(c, m, prec, X, es, false, mt);
+          pbytes = std::max(pbytes, xg_partial_bytes(g, prec));
+          btb = std::max(btb, xg_bt_bytes(g, prec));
+        }
       } else {
         XsCfg x = xs_config(c, m, prec);
         pbytes = std::max(pbytes, partial_bytes_needed(x, prec));
@@ -1522,6 +1527,21 @@ int tr_als_debug_graphs(const tr_als_ctx* c, char* note, int note_len) {
   for (const auto& row : c->graphs)
     for (hipGraphExec_t ex : row) count += ex != nullptr;
   return count;
+}
+
+int tr_als_debug_shadow(tr_als_ctx* c, int prec, int transposed, void* out, float* scale, int64_t* split_k) {
+  if (!valid_ctx(c) || !out || !scale || (prec != TR_BF16 && prec != TR_FP8))
+    return c ? fail(c, TR_EINVAL, "bad arguments") : TR_EINVAL;
+  int rc = ensure_shadow(c, prec);
+  if (rc) return rc;
+  const void* src = prec == TR_BF16 ? (transposed ? c->xbf16t : c->xbf16) : (transposed ? c->xfp8t : c->xfp8);
+  if (!src) return fail(c, TR_EINVAL, "the context keeps no such shadow");
+  HIPCHK(c, hipMemcpyAsync(out, src, (size_t)c->numel * (prec == TR_BF16 ? 2 : 1), hipMemcpyDeviceToDevice,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  *scale = prec == TR_FP8 ? c->fp8_scale : 1.0f;
+  if (split_k) *split_k = transposed ? c->t_gK : 0;
+  return TR_OK;
 }
 
 int tr_als_profile_enable(tr_als_ctx* c, int enable) {

@@ -440,3 +440,49 @@ def test_cheap_fit_identities():
     ip, nrm2 = O.cheap_fit_terms(X, cores)
     assert ip == pytest.approx(float(np.sum(X * Xh)), rel=1e-12)
     assert nrm2 == pytest.approx(float(np.sum(Xh * Xh)), rel=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Narrow formats of the X shadows: encoders written from the format
+# definitions, pinned by values the definitions fix.
+# ---------------------------------------------------------------------------
+def test_bf16_encoder_fixed_values():
+    from oracle.lowp_formats import bf16_bits, bf16_value
+    cases = {1.0: 0x3F80, -2.0: 0xC000, 0.0: 0x0000, 1.0 + 2.0 ** -8: 0x3F80,     # tie, even stays
+             1.0 + 3 * 2.0 ** -8: 0x3F82,                                         # tie, odd rounds up
+             1.0 + 2.0 ** -8 + 2.0 ** -20: 0x3F81,                                # above the tie
+             float(np.finfo(np.float32).max): 0x7F80}                             # rounds to infinity
+    for x, want in cases.items():
+        assert int(bf16_bits(np.float32(x))) == want, (x, hex(int(bf16_bits(np.float32(x)))))
+    assert int(bf16_bits(np.float32(-0.0))) == 0x8000
+    allb = np.arange(1 << 16, dtype=np.uint32).astype(np.uint16)
+    vals = bf16_value(allb).astype(np.float32)
+    ok = ~np.isnan(vals)
+    assert np.array_equal(bf16_bits(vals[ok]), allb[ok])                 # exact values round-trip
+
+
+def test_fp8_e4m3_encoder_fixed_values():
+    from oracle.lowp_formats import fp8_e4m3_bits, fp8_e4m3_value
+    cases = {1.0: 0x38, 448.0: 0x7E, -448.0: 0xFE, 2.0 ** -6: 0x08, 2.0 ** -9: 0x01, 2.0 ** -10: 0x00,
+             3 * 2.0 ** -10: 0x02, 7.5 * 2.0 ** -9: 0x08, 1.0 + 1 / 16: 0x38, 1.0 + 3 / 16: 0x3A,
+             1.0 + 15 / 16: 0x40, 0.0: 0x00, 240.0: 0x77, 0.875 * 2.0 ** -6: 0x07}
+    for x, want in cases.items():
+        got = int(fp8_e4m3_bits(np.float32(x)))
+        assert got == want, (x, hex(got), hex(want))
+    assert int(fp8_e4m3_bits(np.float32(-0.0))) == 0x80
+    codes = np.array([b for b in range(256) if (b & 0x7F) != 0x7F], dtype=np.uint8)
+    vals = fp8_e4m3_value(codes)
+    assert np.nanmax(np.abs(fp8_e4m3_value(np.arange(256, dtype=np.uint8)))) == 448.0
+    back = fp8_e4m3_bits(vals.astype(np.float32))
+    assert np.array_equal(back[vals != 0], codes[vals != 0])
+    assert int(fp8_e4m3_bits(np.float32(464.0))) == 0x7E      # tie between 448 and 480: the even fraction
+    with pytest.raises(ValueError):
+        fp8_e4m3_bits(np.float32(465.0))                      # nearer to 480, which E4M3 cannot hold
+    # nearest: a value between two codes goes to the closer one
+    g = np.random.default_rng(3)
+    x = (g.standard_normal(20000) * 30).astype(np.float32)
+    q = fp8_e4m3_value(fp8_e4m3_bits(x))
+    fin = np.sort(np.unique(np.abs(vals)))
+    for xv, qv in zip(x[:2000], q[:2000]):
+        d = np.abs(fin - abs(float(xv)))
+        assert abs(abs(qv) - abs(float(xv))) <= d.min() + 1e-12
