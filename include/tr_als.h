@@ -201,6 +201,24 @@ int tr_als_debug_shadow(tr_als_ctx* ctx, int prec, int transposed, void* out, fl
 int tr_gen_planted(int N, const int64_t* dims, const int64_t* ranks, uint64_t seed, double eta, void* X,
                    int x_dtype, double* const* true_cores, double* const* init_cores, void* hip_stream);
 
+/*
+ * tr_gen_planted_noalloc -- the same generator for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): identical arguments and results, bit for
+ * bit, but its workspace is a device array of TR_GEN_SCRATCH_MAX bytes inside
+ * the library (one per GPU, held until the process ends), and it neither
+ * allocates, frees nor synchronises: the work is only enqueued on hip_stream
+ * (the caller synchronises before reading X or the cores).  Returns TR_ENOMEM,
+ * without enqueuing anything, when the job's workspace exceeds
+ * TR_GEN_SCRATCH_MAX (tr_gen_planted then serves it).  All calls on one GPU
+ * share the array: calls that can overlap on that GPU (different streams, or
+ * different host threads) race and must be serialised by the caller;
+ * consecutive calls on one stream are ordered and safe.
+ */
+#define TR_GEN_SCRATCH_MAX ((size_t)64 << 20)
+int tr_gen_planted_noalloc(int N, const int64_t* dims, const int64_t* ranks, uint64_t seed, double eta, void* X,
+                           int x_dtype, double* const* true_cores, double* const* init_cores, void* hip_stream);
+
 /* ------------------------------------------------------------------------ *
  * Serving: a request loop that runs many decomposition jobs on one GPU.
  *

@@ -75,6 +75,8 @@ TR_SRV_BATCH = 1
 _SIGS.update({
     "tr_gen_planted": (ctypes.c_int, [ctypes.c_int, _i64p, _i64p, ctypes.c_uint64, ctypes.c_double, _vp,
                                       ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp]),
+    "tr_gen_planted_noalloc": (ctypes.c_int, [ctypes.c_int, _i64p, _i64p, ctypes.c_uint64, ctypes.c_double, _vp,
+                                              ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp]),
     "tr_srv_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_size_t, ctypes.c_int, ctypes.c_int]),
     "tr_srv_submit": (ctypes.c_int, [_vp, ctypes.POINTER(JobDesc), ctypes.POINTER(ctypes.c_uint64)]),
     "tr_srv_poll": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(JobInfo)]),

@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1333,6 +1334,55 @@ int tr_gen_planted(int N, const int64_t* dims, const int64_t* ranks, uint64_t se
   (void)hipFree(buf);
   if (rc == TR_OK && e != hipSuccess) rc = TR_EHIP;
   return rc;
+}
+
+// Allocation-free variant of the generator: its workspace lives in `scratch`,
+// a device array of TR_GEN_SCRATCH_MAX bytes that every GPU the library runs
+// on holds for the life of the process.  Host code never uses the array's
+// name as an address: its device address is looked up once per device
+// (hipGetSymbolAddress, with that device current) and kept in scratch_dev.
+static __device__ __align__(256) char scratch[TR_GEN_SCRATCH_MAX];
+
+namespace {
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex scratch_mu;
+char* scratch_dev[SCRATCH_DEVICES] = {nullptr};
+
+int scratch_address(char** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return TR_EHIP;
+  }
+  if (dev < 0 || dev >= SCRATCH_DEVICES) return TR_EINVAL;
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (!scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return TR_EHIP;
+    }
+    scratch_dev[dev] = static_cast<char*>(p);
+  }
+  *out = scratch_dev[dev];
+  return TR_OK;
+}
+}  // namespace
+
+int tr_gen_planted_noalloc(int N, const int64_t* dims, const int64_t* ranks, uint64_t seed, double eta, void* X,
+                           int x_dtype, double* const* true_cores, double* const* init_cores, void* hip_stream) {
+  if (N < 2 || N > TR_MAXN || !dims || !ranks || !X) return TR_EINVAL;
+  const size_t ws = trx_gen_workspace(N, dims, ranks, true_cores == nullptr);
+  if (ws == 0) return TR_EINVAL;
+  if (ws > TR_GEN_SCRATCH_MAX) return TR_ENOMEM;
+  char* buf = nullptr;
+  const int rc = scratch_address(&buf);
+  if (rc) return rc;
+  // every byte of the workspace the kernels read is written by them first
+  // (cores, tables, per-block partial sums), so nothing needs clearing
+  return trx_gen(N, dims, ranks, seed, eta, X, x_dtype, true_cores, init_cores, buf, ws,
+                 (hipStream_t)hip_stream, nullptr);
 }
 
 }  // extern "C"

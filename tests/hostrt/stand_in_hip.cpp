@@ -65,13 +65,18 @@ struct Op {                   // one captured launch: its name and the ranges it
   std::vector<Range> ranges;
 };
 
-struct Alloc { size_t size; bool mapped; bool host; };
+struct Alloc { size_t size; bool mapped; bool host; bool var = false; };
 
 std::recursive_mutex& mu() {   // built on first use, like names()
   static auto* m = new std::recursive_mutex();
   return *m;
 }
-std::map<uintptr_t, Alloc> g_allocs;                  // start -> allocation
+// start -> allocation; built on first use (device variables are registered by
+// the library's constructors, possibly before this file's globals exist)
+std::map<uintptr_t, Alloc>& allocs() {
+  static auto* m = new std::map<uintptr_t, Alloc>();
+  return *m;
+}
 // host stub -> demangled kernel; built on first use, since the library's
 // registration constructors may run before this file's globals exist
 std::unordered_map<const void*, std::string>& names() {
@@ -81,6 +86,11 @@ std::unordered_map<const void*, std::string>& names() {
 std::unordered_map<const void*, int> g_lds_limit;     // raised dynamic-LDS limit
 std::vector<std::string> g_viol;
 std::map<std::string, long> g_launches;
+// allocations, frees, synchronisations (first use may come from a constructor)
+std::map<std::string, long>& calls() {
+  static auto* m = new std::map<std::string, long>();
+  return *m;
+}
 std::vector<std::array<long long, 4>> g_gemm_log;     // M, N, realign, pair member
 int g_open_captures = 0;
 long long g_delay_us = 0;                             // simulated device time of recorded work
@@ -126,8 +136,8 @@ hipError_t ret(hipError_t e) {
 }
 
 const Alloc* find(uintptr_t p, uintptr_t* start) {
-  auto it = g_allocs.upper_bound(p);
-  if (it == g_allocs.begin()) return nullptr;
+  auto it = allocs().upper_bound(p);
+  if (it == allocs().begin()) return nullptr;
   --it;
   if (p >= it->first + std::max<size_t>(it->second.size, 1)) return nullptr;
   *start = it->first;
@@ -407,6 +417,28 @@ void __hipRegisterFunction(void**, const void* hostFunction, char*, const char* 
   std::lock_guard<std::recursive_mutex> lk(mu());
   names()[hostFunction] = demangle(deviceName);
 }
+// device variables: host shadow -> stand-in device allocation of the same size
+static std::unordered_map<const void*, void*>& vars() {
+  static auto* m = new std::unordered_map<const void*, void*>();
+  return *m;
+}
+static hipError_t do_alloc(void** p, size_t bytes, bool host);
+void __hipRegisterVar(void**, void* var, char*, char*, int, size_t size, int, int) {
+  std::lock_guard<std::recursive_mutex> lk(mu());
+  void* p = nullptr;
+  if (do_alloc(&p, size, false) == hipSuccess) {
+    vars()[var] = p;
+    allocs()[(uintptr_t)p].var = true;
+  }
+}
+hipError_t hipGetSymbolAddress(void** devPtr, const void* symbol) {
+  std::lock_guard<std::recursive_mutex> lk(mu());
+  touch();
+  auto it = vars().find(symbol);
+  if (!devPtr || it == vars().end()) return ret(hipErrorInvalidSymbol);
+  *devPtr = it->second;
+  return hipSuccess;
+}
 hipError_t __hipPushCallConfiguration(dim3 g, dim3 b, size_t shm, hipStream_t s) {
   t_cfg.push_back({g, b, shm, s});
   return hipSuccess;
@@ -444,11 +476,12 @@ static hipError_t do_alloc(void** p, size_t bytes, bool host) {
   touch();
   if (!p) return ret(hipErrorInvalidValue);
   if (g_open_captures && !host) viol("hipMalloc of %zu bytes while a stream capture is open", bytes);
+  calls()[host ? "host alloc" : "alloc"]++;
   const size_t sz = std::max<size_t>(bytes, 1);
   const size_t mapped = (sz + 4095) / 4096 * 4096;
   void* m = mmap(nullptr, mapped, PROT_READ | PROT_WRITE, MAP_PRIVATE | MAP_ANONYMOUS | MAP_NORESERVE, -1, 0);
   if (m == MAP_FAILED) { *p = nullptr; return ret(hipErrorOutOfMemory); }
-  g_allocs[(uintptr_t)m] = {bytes, true, host};
+  allocs()[(uintptr_t)m] = {bytes, true, host};
   *p = m;
   return hipSuccess;
 }
@@ -458,13 +491,14 @@ static hipError_t do_free(void* p) {
   touch();
   if (!p) return hipSuccess;
   if (g_open_captures) viol("free while a stream capture is open");
-  auto it = g_allocs.find((uintptr_t)p);
-  if (it == g_allocs.end()) {
+  calls()["free"]++;
+  auto it = allocs().find((uintptr_t)p);
+  if (it == allocs().end()) {
     viol("free of %p, which is not the start of a live allocation", p);
     return ret(hipErrorInvalidValue);
   }
   munmap(p, (std::max<size_t>(it->second.size, 1) + 4095) / 4096 * 4096);
-  g_allocs.erase(it);
+  allocs().erase(it);
   return hipSuccess;
 }
 
@@ -533,6 +567,7 @@ hipError_t hipStreamSynchronize(hipStream_t s) {
   std::lock_guard<std::recursive_mutex> lk(mu());
   touch();
   if (capture_of(s)) viol("synchronisation of a capturing stream");
+  calls()["sync"]++;
   return hipSuccess;
 }
 hipError_t hipStreamWaitEvent(hipStream_t s, hipEvent_t e, unsigned int) {
@@ -661,6 +696,14 @@ void fakehip_reset(void) {
   g_viol.clear();
   g_launches.clear();
   g_gemm_log.clear();
+  calls().clear();
+}
+// allocations ("alloc", "host alloc"), frees ("free") and stream
+// synchronisations ("sync") since the last reset
+long fakehip_calls(const char* what) {
+  std::lock_guard<std::recursive_mutex> lk(mu());
+  auto it = calls().find(what ? what : "");
+  return it == calls().end() ? 0 : it->second;
 }
 long fakehip_launches(const char* kernel) {
   std::lock_guard<std::recursive_mutex> lk(mu());
@@ -681,9 +724,11 @@ int fakehip_gemm_log(long long* out, int cap) {
     for (int q = 0; q < 4; ++q) out[4 * k + q] = g_gemm_log[k][q];
   return n;
 }
-int fakehip_live_allocations(void) {
+int fakehip_live_allocations(void) {   // allocated by calls, not the library's device variables
   std::lock_guard<std::recursive_mutex> lk(mu());
-  return (int)g_allocs.size();
+  int n = 0;
+  for (auto& kv : allocs()) n += kv.second.var ? 0 : 1;
+  return n;
 }
 // completion of recorded work is reported this many microseconds after it
 // was recorded, so that callers polling events see work in flight

@@ -136,3 +136,37 @@ def test_serving_stream_host_side(host):
     host.L.fakehip_set_delay_us(0)
     _clean(host, "stream")
     assert host.L.fakehip_live_allocations() == 0
+
+
+def test_generator_without_allocation_host_side(host):
+    """tr_gen_planted_noalloc: no allocation, free or synchronisation; the
+    kernels' operands lie inside the library's scratch array; an oversized job
+    is refused before anything is enqueued."""
+    import ctypes
+    import numpy as np
+    C = host.C
+    L = host.L
+    L.fakehip_calls.restype = ctypes.c_long
+    L.fakehip_calls.argtypes = [ctypes.c_char_p]
+    f = L.tr_gen_planted_noalloc
+    f.restype = ctypes.c_int
+    f.argtypes = C._SIGS["tr_gen_planted_noalloc"][1]
+    for dims, ranks in (((40, 36, 30), (5, 6, 4)), ((13, 9, 11), (3, 4, 2))):
+        N = len(dims)
+        X = host.alloc(int(np.prod(dims)) * 4)
+        init = [host.alloc(R.core_elems(dims, ranks, k) * 8) for k in range(N)]
+        host.reset()
+        rc = f(N, (ctypes.c_int64 * N)(*dims), (ctypes.c_int64 * N)(*ranks), 7, 0.01, ctypes.c_void_p(X), C.TR_F32,
+               None, (ctypes.c_void_p * N)(*init), None)
+        assert rc == 0
+        assert L.fakehip_launches(None) > 0
+        for what in (b"alloc", b"host alloc", b"free", b"sync"):
+            assert L.fakehip_calls(what) == 0, what
+        _clean(host, f"generator {dims}")
+        for p in init + [X]:
+            host.free(p)
+    dims, ranks = (128, 128, 128, 128), (24, 24, 24, 24)      # tables far beyond the scratch array
+    host.reset()
+    rc = f(4, (ctypes.c_int64 * 4)(*dims), (ctypes.c_int64 * 4)(*ranks), 7, 0.01, ctypes.c_void_p(0x1000),
+           C.TR_F32, None, None, None)
+    assert rc == C.TR_ENOMEM and L.fakehip_launches(None) == 0
