@@ -36,8 +36,9 @@ extern "C" {
 
 typedef struct tr_als_ctx tr_als_ctx;
 
-/* Update variant (Alg. 2 normal equation, Alg. 3 QR). */
-enum { TR_NE = 0, TR_QR = 1 };
+/* Update variant (Alg. 2 normal equation, Alg. 3 QR, Alg. 4 QR + normal
+ * equation). */
+enum { TR_NE = 0, TR_QR = 1, TR_QRNE = 2 };
 
 /* Element types: storage type of X (TR_F64 or TR_F32) and the precision of the
  * X contraction (all four).  The Gram, ring, solve and QR steps are always FP64. */
@@ -66,10 +67,12 @@ enum {
  *   cores    host array of N device pointers to FP64 cores in the layout above.
  *            Read here; overwritten in place at the end of each successful
  *            tr_als_sweep (stream order).  Caller-owned.
- *   variant  TR_NE or TR_QR.
+ *   variant  TR_NE, TR_QR or TR_QRNE.  TR_QR and TR_QRNE need
+ *            R_n R_{n+1} <= 128 for every n (TR_EINVAL otherwise).
  *   hip_stream  hipStream_t for all work of this context.
  * Allocates all workspace (freed by tr_als_destroy), computes ||X||_F^2 and the
- * per-core Grams (NE) or core QRs (QR).  Synchronises the stream once.
+ * per-core Grams (NE), core QRs (QR) or both, the Grams of the R-cores
+ * (QRNE).  Synchronises the stream once.
  */
 int tr_als_init(tr_als_ctx** ctx, int N, const int64_t* dims, const int64_t* ranks,
                 const void* X, int x_dtype, double* const* cores, int variant,
@@ -84,12 +87,33 @@ int tr_als_init(tr_als_ctx** ctx, int N, const int64_t* dims, const int64_t* ran
  *                     of X built on first use (RNE; FP8 E4M3 with one FP32
  *                     scale per tensor) and kept for the context's lifetime.
  *   refine_steps      0..4 iterative-refinement steps of the normal-equation
- *                     solve (NE variant; ignored by TR_QR).
+ *                     solve (NE and QRNE variants; ignored by TR_QR).
  * Synchronises the stream once at the end to read the device status word.
  * On TR_ESINGULAR / TR_ENONFINITE the caller's cores hold the last good mode
  * update and the context stays usable.
  */
 int tr_als_sweep(tr_als_ctx* ctx, int nsweeps, int contraction_prec, int refine_steps);
+
+/*
+ * tr_als_run -- sweeps until the relative error stops improving: after each
+ * sweep the error is estimated from the last mode's intermediates by the
+ * identity ||X - Xhat||^2 = ||X||^2 - 2 <X, Xhat> + ||Xhat||^2 (Sec. 4, error
+ * computation): <X, Xhat> = <M_N, G_N(2)> and ||Xhat||^2 = <S_N<2>, G_N(2)^T
+ * G_N(2)> for TR_NE and TR_QRNE (whose M_N = Y_[N] V_N[2] and R-core Grams
+ * give the same two numbers), <W_N, G_N(2) R_[2]^T> and ||G_N(2) R_[2]^T||^2
+ * for TR_QR; no pass over X.  Stops after the first sweep whose estimate
+ * differs from the previous sweep's by at most tol (>= 0), or after
+ * max_sweeps (>= 1).
+ *   sweeps_done  host out: sweeps run.
+ *   rel_err      host out: the last estimate of ||X - Xhat|| / ||X||.
+ * The estimate subtracts two numbers close to ||X||^2, so it loses about
+ * (||X|| / ||X - Xhat||)^2 units of roundoff of M_N: use it with
+ * contraction_prec = TR_F64 (in lower precisions the contraction error of M_N
+ * dominates it; tr_als_fit stays exact).  Synchronises once per sweep; cores
+ * written back at the end as by tr_als_sweep (also on error).
+ */
+int tr_als_run(tr_als_ctx* ctx, int max_sweeps, int contraction_prec, int refine_steps, double tol,
+               int* sweeps_done /*host*/, double* rel_err /*host*/);
 
 /*
  * tr_als_fit -- relative error ||X - TR(G)||_F / ||X||_F of the current cores
@@ -190,6 +214,29 @@ int tr_als_debug_shadow(tr_als_ctx* ctx, int prec, int transposed, void* out, fl
  * scaled noise is added in FP64 and rounded again.
  * ------------------------------------------------------------------------ */
 
+/* ------------------------------------------------------------------------ *
+ * Inner product and norm of tensors in TR format (Sec. 3.4 by-product).
+ *
+ * For A = TR(G_1..G_N) and B = TR(Z_1..Z_N) with the same dims, the Gram
+ * tensors P_k = sum_i G_k(i)^T o Z_k(i)^T chained by general contractions hold
+ * every product pair; <A, B> is the sum of the chain's entries whose two
+ * left and two right indices agree (the trace of the product of the transfer
+ * matrices T_k[(a,a'),(b,b')] = sum_i G_k(a,i,b) Z_k(a',i,b')).  The
+ * proposition as printed takes the trace of the chain's mode-2 unfolding,
+ * which is another number; this is the reading under which the identity holds.
+ *   dims     host, I_1..I_N (2 <= N <= 8).
+ *   ranksA / ranksB  host, ranks of each (1..24, independent of each other).
+ *   coresA / coresB  host arrays of N device pointers, FP64 cores in the
+ *            layout above; read only.
+ *   inner / norm     host out: <A, B>, or ||A||_F = sqrt(<A, A>).
+ * FP64 throughout (cross Grams on FP64 MFMA).  Allocates and frees a
+ * workspace of O(sum (R_k S_k)^2) doubles; synchronises the stream.
+ */
+int tr_inner(int N, const int64_t* dims, const int64_t* ranksA, double* const* coresA, const int64_t* ranksB,
+             double* const* coresB, double* inner /*host*/, void* hip_stream);
+int tr_norm(int N, const int64_t* dims, const int64_t* ranks, double* const* cores, double* norm /*host*/,
+            void* hip_stream);
+
 /*
  * tr_gen_planted -- write the planted tensor into X (prod(I_n) elements of
  * x_dtype, TR_F32 or TR_F64).  true_cores: host array of N device pointers that
@@ -250,7 +297,7 @@ typedef struct {
   int N;                      /* order, 2..8 */
   int64_t dims[8];            /* I_1..I_N */
   int64_t ranks[8];           /* R_1..R_N, 1..24 */
-  int variant;                /* TR_NE or TR_QR */
+  int variant;                /* TR_NE, TR_QR or TR_QRNE */
   int prec_mixed;             /* contraction precision of the first sweeps */
   int nsweeps_mixed;
   int prec_fin;               /* contraction precision of the finishing sweeps */

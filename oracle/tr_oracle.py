@@ -30,6 +30,8 @@ Parity status of each function (pins live in tests/test_oracle_pins.py):
   tr_als_qr_literal (Alg. 3) ..... pinned by agreement with tr_als from the same
                                    start on well-conditioned data
   tr_als_ne_literal (Alg. 2) ..... same
+  tr_als_qrne_literal (Alg. 4) ... same, and its R-core Grams against the
+                                   cores' Grams (Q_j has orthonormal columns)
   tr_inner ....................... pinned by brute-force <A,B> (corrected reading
                                    of the by-product proposition, Sec. 3.4)
   cheap_fit_terms ................ pinned by the explicit error (Sec. 4 identities)
@@ -48,7 +50,7 @@ __all__ = [
     "subchain_slices_bruteforce", "subchain_unfold2", "tr_full", "mttsp", "gram_tensor",
     "general_contract", "coef_matrix_paper", "coef_matrix_explicit", "solve_ls",
     "als_update", "tr_als", "rel_error", "mode2_qr", "ttm", "multi_ttm",
-    "tr_als_qr_literal", "tr_als_ne_literal", "tr_inner", "cheap_fit_terms",
+    "tr_als_qr_literal", "tr_als_ne_literal", "tr_als_qrne_literal", "tr_inner", "cheap_fit_terms",
     "regular_objective",
 ]
 
@@ -388,6 +390,34 @@ def tr_als_ne_literal(X, cores0, sweeps):
             Gt = sla.cho_solve(c, M.T)                       # S G^T = M^T (S symmetric)
             cores[n - 1] = core_fold2(np.asfortranarray(Gt.T), rr[n - 1], rr[n])
             grams[n - 1] = gram_tensor(cores[n - 1])
+    return cores
+
+
+def tr_als_qrne_literal(X, cores0, sweeps):
+    """TR-ALS-QRNE (Alg. 4, Sec. 3.3) written out: mode-2 QRs of the cores,
+    Gram tensors of the R-cores, and per mode: S_n from the R-core Grams (Prop.
+    3.1 applied to the R-cores), V_n = subchain of the R-cores,
+    Y = X x_{j!=n} Q_j^T, M_n = Y_[n] V_n[2], Cholesky solve of
+    G_n(2) S_n<2> = M_n, re-factor the updated core and refresh its R-core
+    Gram."""
+    X = np.asarray(X, dtype=np.float64)
+    cores = [np.asfortranarray(np.array(c, dtype=np.float64)) for c in cores0]
+    N = len(cores)
+    rr = ring_ranks(cores)
+    qrs = [mode2_qr(G) for G in cores]
+    grams = [gram_tensor(q[1]) for q in qrs]
+    for _ in range(sweeps):
+        for n in range(1, N + 1):
+            Rcores = [q[1] for q in qrs]
+            S = coef_matrix_paper(Rcores, n, grams)
+            V2 = subchain_unfold2(Rcores, n)                 # V_n[2]
+            Y = multi_ttm(X, [q[0].T for q in qrs], skip=n)
+            M = unfold_mode(Y, n) @ V2
+            c = sla.cho_factor(S, lower=True)
+            Gt = sla.cho_solve(c, M.T)                       # S G^T = M^T
+            cores[n - 1] = core_fold2(np.asfortranarray(Gt.T), rr[n - 1], rr[n])
+            qrs[n - 1] = mode2_qr(cores[n - 1])
+            grams[n - 1] = gram_tensor(qrs[n - 1][1])
     return cores
 
 

@@ -11,12 +11,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtrals.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "tr_als.h")
 
-TR_NE, TR_QR = 0, 1
+TR_NE, TR_QR, TR_QRNE = 0, 1, 2
 TR_F64, TR_F32, TR_BF16, TR_FP8 = 0, 1, 2, 3
 TR_OK, TR_EINVAL, TR_ENOMEM, TR_EHIP, TR_ESINGULAR, TR_ENONFINITE = 0, -1, -2, -3, -4, -5
 
 PREC = {"f64": TR_F64, "f32": TR_F32, "bf16": TR_BF16, "fp8": TR_FP8}
-VARIANT = {"ne": TR_NE, "qr": TR_QR}
+VARIANT = {"ne": TR_NE, "qr": TR_QR, "qrne": TR_QRNE}
 
 _vp = ctypes.c_void_p
 _i64p = ctypes.POINTER(ctypes.c_int64)
@@ -41,6 +41,11 @@ _SIGS = {
     "tr_als_debug_overruns": (ctypes.c_int, []),
     "tr_als_debug_graphs": (ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.c_int]),
     "tr_als_profile_read": (ctypes.c_int, [_vp, _dp, _i64p, _dp]),
+    "tr_als_run": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                  ctypes.POINTER(ctypes.c_int), _dp]),
+    "tr_inner": (ctypes.c_int, [ctypes.c_int, _i64p, _i64p, ctypes.POINTER(_vp), _i64p, ctypes.POINTER(_vp), _dp,
+                                _vp]),
+    "tr_norm": (ctypes.c_int, [ctypes.c_int, _i64p, _i64p, ctypes.POINTER(_vp), _dp, _vp]),
     "tr_als_debug_shadow": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_float),
                                            _i64p]),
 }

@@ -51,6 +51,14 @@ class TRContext:
     def sweep(self, nsweeps: int = 1, prec: str = "f32", refine: int = 1):
         return C.check(C.lib().tr_als_sweep(self._h, int(nsweeps), C.PREC[prec], int(refine)), self._h, "tr_als_sweep")
 
+    def run(self, max_sweeps: int, prec: str = "f64", refine: int = 1, tol: float = 0.0):
+        """Sweeps until the in-loop error estimate changes by at most ``tol``
+        (``tr_als_run``): returns (sweeps run, last estimate)."""
+        k, f = ctypes.c_int(), ctypes.c_double()
+        C.check(C.lib().tr_als_run(self._h, int(max_sweeps), C.PREC[prec], int(refine), float(tol), ctypes.byref(k),
+                                   ctypes.byref(f)), self._h, "tr_als_run")
+        return k.value, f.value
+
     def fit(self) -> float:
         v = ctypes.c_double()
         C.check(C.lib().tr_als_fit(self._h, ctypes.byref(v)), self._h, "tr_als_fit")
@@ -288,3 +296,27 @@ class TRServer:
 
     def __exit__(self, *a):
         self.close()
+
+
+def _core_ptrs(cores):
+    return (ctypes.c_void_p * len(cores))(*[c.data_ptr() for c in cores])
+
+
+def tr_inner(dims, ranks_a, cores_a, ranks_b, cores_b, stream=None) -> float:
+    """<A, B> of two tensors in TR format (``tr_inner``); cores are flat CUDA
+    float64 tensors in the core layout."""
+    N = len(dims)
+    v = ctypes.c_double()
+    C.check(C.lib().tr_inner(N, (ctypes.c_int64 * N)(*dims), (ctypes.c_int64 * N)(*ranks_a), _core_ptrs(cores_a),
+                             (ctypes.c_int64 * N)(*ranks_b), _core_ptrs(cores_b), ctypes.byref(v),
+                             _stream_handle(stream)), None, "tr_inner")
+    return v.value
+
+
+def tr_norm(dims, ranks, cores, stream=None) -> float:
+    """||A||_F of a tensor in TR format (``tr_norm``)."""
+    N = len(dims)
+    v = ctypes.c_double()
+    C.check(C.lib().tr_norm(N, (ctypes.c_int64 * N)(*dims), (ctypes.c_int64 * N)(*ranks), _core_ptrs(cores),
+                            ctypes.byref(v), _stream_handle(stream)), None, "tr_norm")
+    return v.value

@@ -163,6 +163,17 @@ hipError_t launch_fit(const void* X, int xdt, int64_t I, int64_t K, const double
                       const double* F2, int64_t d1, int64_t m1, int64_t d2, int64_t m2, int Rb, int Rmid, int Ra,
                       double* partials, int nblk, double* out, hipStream_t s);
 hipError_t launch_table_absmax(const double* T, int64_t n, double* out, hipStream_t s);
+// cheap in-loop error (Sec. 4): rows of A (M_N or W_N) and G = G_N(2) (I x n);
+// mode 0: B = S_N (n x n), mode 1: B = R_[2]^T (lower); out[0] = ||X||^2 - 2a + b,
+// out[1] = a = <X, Xhat>, out[2] = b = ||Xhat||^2.  partials: 2 * cheap_fit_blocks(I)
+int cheap_fit_blocks(int64_t I);
+hipError_t launch_cheap_fit(const double* A, const double* G, const double* B, int mode, int64_t I, int n,
+                            const double* xnorm2, double* partials, double* out, hipStream_t s);
+// TR inner product (Sec. 3.4): cross Gram E (RaRb x SaSb) -> transfer matrix
+// T ((Ra Sa) x (Rb Sb)), and the trace of a square n x n matrix
+hipError_t launch_transfer_from_cross_gram(const double* E, int Ra, int Rb, int Sa, int Sb, double* T,
+                                           hipStream_t s);
+hipError_t launch_trace(const double* P, int64_t n, double* out, hipStream_t s);
 // planted-tensor generator (serving)
 hipError_t launch_philox_normal(double* out, int64_t n, uint64_t seed, uint32_t sid, hipStream_t s);
 hipError_t launch_gen_planted(void* X, int xdt, int64_t I, int64_t K, const double* G0, const double* F1,

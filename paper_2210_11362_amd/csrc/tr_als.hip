@@ -820,6 +820,56 @@ int qr_core(tr_als_ctx* c, int k) {
   return TR_OK;
 }
 
+// Multi-TTM Y = X x_{j!=m} Q_j^T of the QR-based variants (Alg. 3 and 4), the
+// most compressing mode first: the first TTM reads X in the contraction type
+// (the BF16/FP8 shadows), the rest run in FP64 on the compressed tensor.  *Y
+// is one of the ping-pong buffers; cd receives the extents of Y.
+int multi_ttm_y(tr_als_ctx* c, int m, int prec, const double** Y, int64_t* cd) {
+  hipStream_t s = c->stream;
+  const int N = c->N;
+  std::vector<int> order;
+  for (int k = 1; k < N; ++k) order.push_back((m + k) % N);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return (double)c->qr_r[a] / c->dims[a] < (double)c->qr_r[b] / c->dims[b];
+  });
+  for (int j = 0; j < N; ++j) cd[j] = c->dims[j];
+  int rc = ensure_shadow(c, prec);
+  if (rc) return rc;
+  const void* cur = prec == TR_BF16 ? c->xbf16 : prec == TR_FP8 ? c->xfp8 : c->X;
+  int ctype = (prec == TR_BF16 || prec == TR_FP8) ? prec : c->xdt;
+  double scale = prec == TR_FP8 ? 1.0 / (double)c->fp8_scale : 1.0;
+  double* ybuf[2] = {c->qY0, c->qY1};
+  int yi = 0;
+  for (int j : order) {
+    const int64_t L = prod(cd, 0, j), T = prod(cd, j + 1, N);
+    HIPCHK(c, launch_ttm(cur, ctype, L, c->dims[j], T, c->qQ[j], (int)c->qr_r[j], scale, ybuf[yi], s));
+    cd[j] = c->qr_r[j];
+    cur = ybuf[yi];
+    yi ^= 1;
+    ctype = TR_F64;
+    scale = 1.0;
+  }
+  *Y = (const double*)cur;
+  return TR_OK;
+}
+
+// V_n = subchain of the R-cores of the other modes, unfolded as V_n[2]
+// (J' x R_m R_{m+1}, rows in the order of the Multi-TTM result); returns J'.
+int build_v2(tr_als_ctx* c, int m, int64_t* Jp_out) {
+  const int N = c->N;
+  std::vector<int> chain;
+  for (int k = 1; k < N; ++k) chain.push_back((m + k) % N);
+  int64_t Jp = 1;
+  for (int j : chain) Jp *= c->qr_r[j];
+  int rc = build_table_ex(c, chain, c->R[m + 1], c->qT, c->qR, c->qr_r, c->qY0, c->qY1);
+  if (rc) return rc;
+  int64_t Lrows = 1;
+  for (int j = 0; j < m; ++j) Lrows *= c->qr_r[j];
+  HIPCHK(c, launch_table_to_v2(c->qT, Jp, Lrows, c->R[m], c->R[m + 1], c->qV2, c->stream));
+  *Jp_out = Jp;
+  return TR_OK;
+}
+
 // One QR-variant mode update (Alg. 3): V_n = subchain of the R-cores; QR of
 // V_n[2] = Q_0 R_[2] by shifted Cholesky-QR (three passes); Y = X x_{j!=n} Q_j^T
 // (most-compressing mode first); W_n = Y_[n] Q_0; G_n(2) R_[2]^T = W_n by
@@ -828,17 +878,10 @@ int update_mode_qr(tr_als_ctx* c, int m, int prec) {
   hipStream_t s = c->stream;
   const int N = c->N;
   const int Ra = c->R[m], Rb = c->R[m + 1], n = Ra * Rb;
-  std::vector<int> chain;
-  for (int k = 1; k < N; ++k) chain.push_back((m + k) % N);
+  // V_n[2] (J' x n), rows in the order of the Multi-TTM result below
   int64_t Jp = 1;
-  for (int j : chain) Jp *= c->qr_r[j];
-  // V_n[2] (J' x n)
-  int rc = build_table_ex(c, chain, Rb, c->qT, c->qR, c->qr_r, c->qY0, c->qY1);
+  int rc = build_v2(c, m, &Jp);
   if (rc) return rc;
-  // rows of V_n[2] (and Q_0) in the order of the Multi-TTM result below
-  int64_t Lrows = 1;
-  for (int j = 0; j < m; ++j) Lrows *= c->qr_r[j];
-  HIPCHK(c, launch_table_to_v2(c->qT, Jp, Lrows, Ra, Rb, c->qV2, s));
   // shifted Cholesky-QR: three passes A <- A L^{-T}, R^T = L1 L2 L3
   double* A = c->qV2;
   double* bufs[2] = {c->qQa, c->qQb};
@@ -861,36 +904,52 @@ int update_mode_qr(tr_als_ctx* c, int m, int prec) {
     HIPCHK(c, launch_gemm64(n, n, n, 1.0, Lp, L3, 0.0, nullptr, 0, c->qLt, n, s));
   }
   const double* Q0 = A;
-  // Multi-TTM, most-compressing mode first
-  std::vector<int> order = chain;
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    return (double)c->qr_r[a] / c->dims[a] < (double)c->qr_r[b] / c->dims[b];
-  });
   int64_t cd[TR_MAXN];
-  for (int j = 0; j < N; ++j) cd[j] = c->dims[j];
-  rc = ensure_shadow(c, prec);
+  const double* Y = nullptr;
+  rc = multi_ttm_y(c, m, prec, &Y, cd);
   if (rc) return rc;
-  const void* cur = prec == TR_BF16 ? c->xbf16 : prec == TR_FP8 ? c->xfp8 : c->X;
-  int ctype = (prec == TR_BF16 || prec == TR_FP8) ? prec : c->xdt;
-  double scale = prec == TR_FP8 ? 1.0 / (double)c->fp8_scale : 1.0;
-  double* ybuf[2] = {c->qY0, c->qY1};
-  int yi = 0;
-  for (int j : order) {
-    const int64_t L = prod(cd, 0, j), T = prod(cd, j + 1, N);
-    HIPCHK(c, launch_ttm(cur, ctype, L, c->dims[j], T, c->qQ[j], (int)c->qr_r[j], scale, ybuf[yi], s));
-    cd[j] = c->qr_r[j];
-    cur = ybuf[yi];
-    yi ^= 1;
-    ctype = TR_F64;
-    scale = 1.0;
-  }
   // W_n = Y_[n] Q_0 (I_n x n)
-  HIPCHK(c, launch_tall_atb((const double*)cur, 0, Q0, Jp, Jp, (int)c->dims[m], n, 1, prod(cd, 0, m), c->dims[m],
+  HIPCHK(c, launch_tall_atb(Y, 0, Q0, Jp, Jp, (int)c->dims[m], n, 1, prod(cd, 0, m), c->dims[m],
                             prod(cd, m + 1, N), c->qpart, c->qpart_elems, c->qW, s));
   // G_n(2) = W_n R^{-T}: backward substitution with L = R^T
   HIPCHK(c, launch_trsm_rhs(c->qLt, nullptr, n, c->qW, c->dims[m], c->Gn, 0, c->status, s, 2));
   HIPCHK(c, launch_commit_core(c->Gn, c->dims[m], Ra, Rb, c->cores[m], c->status, s));
   return qr_core(c, m);
+}
+
+// One QRNE mode update (Alg. 4): S_n from the ring of the R-cores' Grams and
+// its inverse; V_n[2] from the R-cores; Y = X x_{j!=n} Q_j^T; M_n = Y_[n] V_n[2];
+// G_n(2) = M_n S_n^{-1} with iterative refinement; commit; re-factor core n
+// and refresh its R-core Gram.  The Grams of the R-cores equal those of the
+// cores (Q_j has orthonormal columns); Alg. 4 forms them from the R-cores.
+int update_mode_qrne(tr_als_ctx* c, int m, int prec, int refine) {
+  hipStream_t s = c->stream;
+  const int N = c->N;
+  const int Ra = c->R[m], Rb = c->R[m + 1], n = Ra * Rb;
+  int rc = compute_coef(c, m, c->S, s);
+  if (rc) return rc;
+  if (spd_inverse_fits(n)) {
+    HIPCHK(c, launch_spd_inverse(c->S, n, c->Sinv, c->status, s));
+  } else {
+    HIPCHK(c, launch_chol(c->S, n, c->Lf, c->LTf, c->cholw, c->status, s));
+    HIPCHK(c, launch_chol_solve(c->Lf, c->LTf, n, nullptr, n, c->Sinv, 0, c->status, s));
+  }
+  int64_t Jp = 1;
+  rc = build_v2(c, m, &Jp);
+  if (rc) return rc;
+  int64_t cd[TR_MAXN];
+  const double* Y = nullptr;
+  rc = multi_ttm_y(c, m, prec, &Y, cd);
+  if (rc) return rc;
+  // M_n = Y_[n] V_n[2] (I_n x n)
+  HIPCHK(c, launch_tall_atb(Y, 0, c->qV2, Jp, Jp, (int)c->dims[m], n, 1, prod(cd, 0, m), c->dims[m],
+                            prod(cd, m + 1, N), c->qpart, c->qpart_elems, c->M, s));
+  HIPCHK(c, launch_ne_apply(c->M, c->dims[m], n, c->S, c->Sinv, refine, c->Gn, c->status, s));
+  HIPCHK(c, launch_commit_core(c->Gn, c->dims[m], Ra, Rb, c->cores[m], c->status, s));
+  rc = qr_core(c, m);
+  if (rc) return rc;
+  HIPCHK(c, launch_gram(c->qR[m], Ra, c->qr_r[m], Rb, c->gram[m], s));
+  return TR_OK;
 }
 
 int read_status(tr_als_ctx* c) {
@@ -986,7 +1045,7 @@ int trx_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ranks,
   }
   if (N < 2 || N > TR_MAXN || !dims || !ranks || (!o.measure && (!X || !cores))) return TR_EINVAL;
   if (x_dtype != TR_F64 && x_dtype != TR_F32) return TR_EINVAL;
-  if (variant != TR_NE && variant != TR_QR) return TR_EINVAL;
+  if (variant != TR_NE && variant != TR_QR && variant != TR_QRNE) return TR_EINVAL;
   int64_t numel = 1;
   for (int k = 0; k < N; ++k) {
     if (dims[k] < 1 || ranks[k] < 1 || ranks[k] > TR_MAXR) return TR_EINVAL;
@@ -1107,7 +1166,7 @@ int trx_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ranks,
   c->partial_bytes = pbytes;
   A(&c->Bt, btb);
   c->bt_bytes = btb;
-  if (variant == TR_QR) {
+  if (variant == TR_QR || variant == TR_QRNE) {
     int64_t maxJ = 1, maxTT = 1, maxHn = 1;
     for (int k = 0; k < N; ++k) c->qr_r[k] = std::min<int64_t>(dims[k], (int64_t)c->R[k] * c->R[k + 1]);
     for (int m = 0; m < N; ++m) {
@@ -1120,7 +1179,7 @@ int trx_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ranks,
       maxJ = std::max(maxJ, Jp * c->R[m] * c->R[m + 1]);
       maxTT = std::max(maxTT, tb);
       maxHn = std::max(maxHn, (int64_t)dims[m] * c->R[m] * c->R[m + 1]);
-      if (c->R[m] * c->R[m + 1] > 128) rc = fail(c, TR_EINVAL, "QR variant needs R_n R_{n+1} <= 128");
+      if (c->R[m] * c->R[m + 1] > 128) rc = fail(c, TR_EINVAL, "QR and QRNE variants need R_n R_{n+1} <= 128");
     }
     maxTT = std::max(maxTT, maxJ);
     for (int k = 0; k < N; ++k) {
@@ -1197,10 +1256,16 @@ int trx_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ranks,
       return TR_EHIP;
     }
   }
-  if (variant == TR_QR) {
+  if (variant == TR_QR || variant == TR_QRNE) {
     for (int k = 0; k < N && rc == TR_OK; ++k) rc = qr_core(c, k);
     if (rc) { tr_als_destroy(c); return rc; }
   }
+  if (variant == TR_QRNE)   // Alg. 4 keeps the Grams of the R-cores
+    for (int k = 0; k < N; ++k)
+      if (hipfail(launch_gram(c->qR[k], c->R[k], c->qr_r[k], c->R[k + 1], c->gram[k], s), "gram")) {
+        tr_als_destroy(c);
+        return TR_EHIP;
+      }
   if (hipfail(launch_sumsq(X, x_dtype, numel, c->dpart, c->nred, c->dscal, s), "sumsq")) {
     tr_als_destroy(c);
     return TR_EHIP;
@@ -1336,6 +1401,92 @@ int tr_gen_planted(int N, const int64_t* dims, const int64_t* ranks, uint64_t se
   return rc;
 }
 
+// <A, B> of two tensors in TR format with the same dims (Sec. 3.4, read as
+// the trace of the product of the transfer matrices T_1 ... T_N): per core
+// the cross Gram A_k(2)^T B_k(2) on FP64 MFMA, reindexed into T_k, the ring
+// product, its trace.
+static int tr_inner_impl(int N, const int64_t* dims, const int64_t* ranksA, double* const* coresA,
+                         const int64_t* ranksB, double* const* coresB, double* out, hipStream_t s) {
+  if (N < 2 || N > TR_MAXN || !dims || !ranksA || !ranksB || !coresA || !coresB || !out) return TR_EINVAL;
+  int64_t maxU = 1, maxE = 1, maxP = 1;
+  int RA[TR_MAXN + 1], RB[TR_MAXN + 1];
+  for (int k = 0; k < N; ++k) {
+    if (dims[k] < 1 || ranksA[k] < 1 || ranksA[k] > TR_MAXR || ranksB[k] < 1 || ranksB[k] > TR_MAXR ||
+        !coresA[k] || !coresB[k])
+      return TR_EINVAL;
+    RA[k] = (int)ranksA[k];
+    RB[k] = (int)ranksB[k];
+  }
+  RA[N] = RA[0];
+  RB[N] = RB[0];
+  for (int k = 0; k < N; ++k) {
+    maxU = std::max<int64_t>(maxU, dims[k] * std::max(RA[k] * RA[k + 1], RB[k] * RB[k + 1]));
+    maxE = std::max<int64_t>(maxE, (int64_t)RA[k] * RA[k + 1] * RB[k] * RB[k + 1]);
+    maxP = std::max<int64_t>(maxP, (int64_t)RA[0] * RB[0] * RA[k + 1] * RB[k + 1]);
+  }
+  const size_t bytes = (size_t)(2 * maxU + 2 * maxE + 2 * maxP + 8) * sizeof(double);
+  char* ws = nullptr;
+  if (hipMalloc((void**)&ws, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return TR_ENOMEM;
+  }
+  double* UA = (double*)ws;
+  double* UB = UA + maxU;
+  double* E = UB + maxU;
+  double* T = E + maxE;
+  double* P[2] = {T + maxE, T + maxE + maxP};
+  double* res = P[1] + maxP;
+  int rc = TR_OK;
+  int cur = 0;
+  const int64_t rows = (int64_t)RA[0] * RB[0];
+  for (int k = 0; k < N && rc == TR_OK; ++k) {
+    const int64_t I = dims[k];
+    const int na = RA[k] * RA[k + 1], nb = RB[k] * RB[k + 1];
+    const int64_t cols = (int64_t)RA[k + 1] * RB[k + 1];
+    MatView At{UA, I, 2, 0, 0}, Bv{UB, I, 0, 0, 0};
+    double* Tk = k == 0 ? P[0] : T;
+    if (launch_core_unfold(coresA[k], RA[k], I, RA[k + 1], UA, s) != hipSuccess ||
+        launch_core_unfold(coresB[k], RB[k], I, RB[k + 1], UB, s) != hipSuccess ||
+        launch_gemm64(na, nb, I, 1.0, At, Bv, 0.0, nullptr, 0, E, na, s) != hipSuccess ||
+        launch_transfer_from_cross_gram(E, RA[k], RA[k + 1], RB[k], RB[k + 1], Tk, s) != hipSuccess) {
+      rc = TR_EHIP;
+      break;
+    }
+    if (k > 0) {
+      const int64_t inner = (int64_t)RA[k] * RB[k];
+      MatView Pv{P[cur], rows, 0, 0, 0}, Tv{T, inner, 0, 0, 0};
+      if (launch_gemm64(rows, cols, inner, 1.0, Pv, Tv, 0.0, nullptr, 0, P[cur ^ 1], rows, s) != hipSuccess) {
+        rc = TR_EHIP;
+        break;
+      }
+      cur ^= 1;
+    }
+  }
+  double v = 0.0;
+  if (rc == TR_OK && (launch_trace(P[cur], rows, res, s) != hipSuccess ||
+                      hipMemcpyAsync(&v, res, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess))
+    rc = TR_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess && rc == TR_OK) rc = TR_EHIP;
+  (void)hipGetLastError();
+  (void)hipFree(ws);
+  if (rc == TR_OK) *out = v;
+  return rc;
+}
+
+int tr_inner(int N, const int64_t* dims, const int64_t* ranksA, double* const* coresA, const int64_t* ranksB,
+             double* const* coresB, double* inner, void* hip_stream) {
+  return tr_inner_impl(N, dims, ranksA, coresA, ranksB, coresB, inner, (hipStream_t)hip_stream);
+}
+
+int tr_norm(int N, const int64_t* dims, const int64_t* ranks, double* const* cores, double* norm,
+            void* hip_stream) {
+  if (!norm) return TR_EINVAL;
+  double v = 0.0;
+  const int rc = tr_inner_impl(N, dims, ranks, cores, ranks, cores, &v, (hipStream_t)hip_stream);
+  if (rc == TR_OK) *norm = std::sqrt(std::max(0.0, v));
+  return rc;
+}
+
 // Allocation-free variant of the generator: its workspace lives in `scratch`,
 // a device array of TR_GEN_SCRATCH_MAX bytes that every GPU the library runs
 // on holds for the life of the process.  Host code never uses the array's
@@ -1391,6 +1542,7 @@ extern "C" {
 
 static int update_mode(tr_als_ctx* c, int m, int prec, int refine, bool in_sweep) {
   if (c->variant == TR_QR) return update_mode_qr(c, m, prec);
+  if (c->variant == TR_QRNE) return update_mode_qrne(c, m, prec, refine);
   return update_mode_ne(c, m, prec, refine, in_sweep);
 }
 
@@ -1474,6 +1626,49 @@ int tr_als_sweep(tr_als_ctx* c, int nsweeps, int prec, int refine) {
   rc = read_status(c);
   // cores written back in either case: on error they hold the last good update
   int rc2 = store_cores(c);
+  if (rc2) return rc2;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return rc;
+}
+
+// The Sec. 4 error identities from the last mode's intermediates, after a
+// sweep: dscal[4] = ||X||^2 - 2 <X, Xhat> + ||Xhat||^2 (dscal[5], dscal[6] the
+// two terms).
+static int enqueue_cheap_fit(tr_als_ctx* c) {
+  const int m = c->N - 1;
+  const int n = c->R[m] * c->R[m + 1];
+  if (2 * cheap_fit_blocks(c->dims[m]) > c->nred) return fail(c, TR_EINVAL, "internal: partial buffer too small");
+  const bool qr = c->variant == TR_QR;
+  HIPCHK(c, launch_cheap_fit(qr ? c->qW : c->M, c->Gn, qr ? c->qLt : c->S, qr ? 1 : 0, c->dims[m], n, c->dscal,
+                             c->dpart, c->dscal + 4, c->stream));
+  return TR_OK;
+}
+
+int tr_als_run(tr_als_ctx* c, int max_sweeps, int prec, int refine, double tol, int* sweeps_done,
+               double* rel_err) {
+  if (!valid_ctx(c)) return TR_EINVAL;
+  if (max_sweeps < 1 || prec < TR_F64 || prec > TR_FP8 || refine < 0 || refine > 4 || !(tol >= 0.0) ||
+      !sweeps_done || !rel_err)
+    return fail(c, TR_EINVAL, "bad arguments");
+  c->err.clear();
+  *sweeps_done = 0;
+  double prev = -1.0;
+  int rc = TR_OK;
+  for (int k = 1; k <= max_sweeps; ++k) {
+    rc = enqueue_sweeps(c, 1, prec, refine);
+    if (rc == TR_OK) rc = enqueue_cheap_fit(c);
+    if (rc) break;
+    double r2 = 0.0;
+    HIPCHK(c, hipMemcpyAsync(&r2, c->dscal + 4, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    rc = read_status(c);   // synchronises: r2 is valid after it
+    if (rc) break;
+    *sweeps_done = k;
+    const double f = c->xnorm2 > 0 ? std::sqrt(std::max(0.0, r2)) / std::sqrt(c->xnorm2) : 0.0;
+    *rel_err = f;
+    if (prev >= 0.0 && std::fabs(prev - f) <= tol) break;
+    prev = f;
+  }
+  const int rc2 = store_cores(c);
   if (rc2) return rc2;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return rc;

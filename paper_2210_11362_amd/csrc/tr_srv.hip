@@ -613,7 +613,7 @@ int validate(const tr_job_desc& d) {
   if (d.N < 2 || d.N > TR_MAXN) return TR_EINVAL;
   for (int k = 0; k < d.N; ++k)
     if (d.dims[k] < 1 || d.ranks[k] < 1 || d.ranks[k] > TR_MAXR) return TR_EINVAL;
-  if (d.variant != TR_NE && d.variant != TR_QR) return TR_EINVAL;
+  if (d.variant != TR_NE && d.variant != TR_QR && d.variant != TR_QRNE) return TR_EINVAL;
   if (d.prec_mixed < TR_F64 || d.prec_mixed > TR_FP8 || d.prec_fin < TR_F64 || d.prec_fin > TR_FP8) return TR_EINVAL;
   if (d.nsweeps_mixed < 0 || d.nsweeps_fin < 0 || d.refine < 0 || d.refine > 4) return TR_EINVAL;
   if (d.x_dtype != TR_F32 && d.x_dtype != TR_F64) return TR_EINVAL;

@@ -1,5 +1,7 @@
-"""The QR-stabilised update (Alg. 3) on the GPU against the oracle's regular ALS
-from the same initial cores (the variants are mathematically equivalent)."""
+"""The QR-based updates on the GPU -- TR-ALS-QR (Alg. 3) and TR-ALS-QRNE
+(Alg. 4) -- against the oracle's regular ALS from the same initial cores (the
+variants are mathematically equivalent), and against the oracle's literal
+Alg. 3 / Alg. 4 on conditioned cores."""
 import numpy as np
 import pytest
 
@@ -38,11 +40,12 @@ def _data(dims, ranks, seed, dtype=np.float64):
     return np.asfortranarray(X.astype(dtype)), init
 
 
+@pytest.mark.parametrize("variant", ["qr", "qrne"])
 @pytest.mark.parametrize("dims,ranks", QR_SHAPES, ids=[str(s[0]) for s in QR_SHAPES])
-def test_qr_variant_per_sweep_f64(dims, ranks):
-    say(f"[qr f64] dims={dims} ranks={ranks}")
+def test_qr_variant_per_sweep_f64(dims, ranks, variant):
+    say(f"[{variant} f64] dims={dims} ranks={ranks}")
     X, init = _data(dims, ranks, 11)
-    ctx, dev = _ctx(to_dev_flat(X), init, dims, ranks, "qr")
+    ctx, dev = _ctx(to_dev_flat(X), init, dims, ranks, variant)
     ref = [np.array(c) for c in init]
     for s in range(3):
         ref, _ = O.tr_als(X, ref, 1)
@@ -54,40 +57,45 @@ def test_qr_variant_per_sweep_f64(dims, ranks):
     ctx.close()
 
 
-def test_qr_matches_literal_alg3_on_conditioned_cores():
+@pytest.mark.parametrize("variant", ["qr", "qrne"])
+def test_qr_matches_literal_alg_on_conditioned_cores(variant):
     """Config 3's recipe (cores with condition number 1e4, ranks (6,8,10,8,6) scaled
-    to (2,3,4,3,2)) at 9^5: GPU QR sweeps track the oracle's literal Alg. 3."""
+    to (2,3,4,3,2)) at 9^5: GPU QR / QRNE sweeps track the oracle's literal
+    Alg. 3 / Alg. 4."""
     w = W.make_workload(3, dims=(9, 9, 9, 9, 9), ranks=(2, 3, 4, 3, 2))
     X = w.X.astype(np.float64)
-    ctx, dev = _ctx(to_dev_flat(w.X), w.init_cores, w.dims, w.ranks, "qr")
+    ctx, dev = _ctx(to_dev_flat(w.X), w.init_cores, w.dims, w.ranks, variant)
     ctx.sweep(2, "f64")
     got = cores_from_dev(dev, w.dims, w.ranks)
-    ref = O.tr_als_qr_literal(X, w.init_cores, 2)
+    lit = O.tr_als_qr_literal if variant == "qr" else O.tr_als_qrne_literal
+    ref = lit(X, w.init_cores, 2)
     errs = [rel(a, b) for a, b in zip(got, ref)]
     say(f"   core rel errs {[f'{e:.1e}' for e in errs]}")
     assert max(errs) <= 1e-8
     ctx.close()
 
 
+@pytest.mark.parametrize("variant", ["qr", "qrne"])
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
-def test_qr_variant_fit_mixed(prec):
+def test_qr_variant_fit_mixed(prec, variant):
     w = W.make_workload(2, dims=(18, 20, 16, 14), ranks=(4, 4, 4, 4))
-    ctx, dev = _ctx(to_dev_flat(w.X), w.init_cores, w.dims, w.ranks, "qr")
+    ctx, dev = _ctx(to_dev_flat(w.X), w.init_cores, w.dims, w.ranks, variant)
     ctx.sweep(6, prec)
     ctx.sweep(2, "f32")
     f_gpu = ctx.fit()
     ref, _ = O.tr_als(w.X.astype(np.float64), w.init_cores, 8)
     f_ref = O.rel_error(w.X.astype(np.float64), ref)
-    say(f"   [{prec}] fit gpu {f_gpu:.6e} oracle {f_ref:.6e}")
+    say(f"   [{variant} {prec}] fit gpu {f_gpu:.6e} oracle {f_ref:.6e}")
     assert abs(f_gpu - f_ref) <= 1e-3
     ctx.close()
 
 
-def test_qr_and_ne_agree():
+@pytest.mark.parametrize("variant", ["qr", "qrne"])
+def test_qr_and_ne_agree(variant):
     dims, ranks = (20, 18, 16, 14), (3, 4, 3, 4)
     X, init = _data(dims, ranks, 12)
     a, da = _ctx(to_dev_flat(X), init, dims, ranks, "ne")
-    b, db = _ctx(to_dev_flat(X), init, dims, ranks, "qr")
+    b, db = _ctx(to_dev_flat(X), init, dims, ranks, variant)
     a.sweep(4, "f64")
     b.sweep(4, "f64")
     for x, y in zip(cores_from_dev(da, dims, ranks), cores_from_dev(db, dims, ranks)):

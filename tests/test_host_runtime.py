@@ -41,12 +41,13 @@ def test_ne_contexts_stay_inside_their_buffers(host, dims, ranks):
         assert host.L.fakehip_launches(b"gemm64_kernel") + host.L.fakehip_launches(b"gemm64_pair_kernel") > 0
 
 
+@pytest.mark.parametrize("variant", ["qr", "qrne"])
 @pytest.mark.parametrize("dims,ranks", QR_SHAPES, ids=[f"{d}-{r}" for d, r in QR_SHAPES])
-def test_qr_contexts_stay_inside_their_buffers(host, dims, ranks):
+def test_qr_contexts_stay_inside_their_buffers(host, dims, ranks, variant):
     host.reset()
-    codes = R.run_context(host, dims, ranks, variant="qr", precs=("f64", "bf16"), xdt="f64")
+    codes = R.run_context(host, dims, ranks, variant=variant, precs=("f64", "bf16"), xdt="f64")
     assert all(rc == 0 for _, rc in codes), codes
-    _clean(host, f"QR {dims} {ranks}")
+    _clean(host, f"{variant} {dims} {ranks}")
 
 
 def test_ring_intermediates_exceed_one_gram_when_ranks_alternate(host):
@@ -170,3 +171,35 @@ def test_generator_without_allocation_host_side(host):
     rc = f(4, (ctypes.c_int64 * 4)(*dims), (ctypes.c_int64 * 4)(*ranks), 7, 0.01, ctypes.c_void_p(0x1000),
            C.TR_F32, None, None, None)
     assert rc == C.TR_ENOMEM and L.fakehip_launches(None) == 0
+
+
+@pytest.mark.parametrize("variant", ["ne", "qr", "qrne"])
+def test_in_loop_error_and_inner_product_host_side(host, variant):
+    """tr_als_run (sweeps + the in-loop error kernels) and tr_inner / tr_norm:
+    every launch in bounds, the workspace of tr_inner released."""
+    import ctypes
+    import numpy as np
+    L, C = host.L, host.C
+    dims, ranks, rb = (17, 20, 13, 11), (2, 3, 4, 3), (3, 2, 2, 4)
+    N = 4
+    X = host.alloc(int(np.prod(dims)) * 8)
+    ca = [host.alloc(R.core_elems(dims, ranks, k) * 8) for k in range(N)]
+    cb = [host.alloc(R.core_elems(dims, rb, k) * 8) for k in range(N)]
+    host.reset()
+    ctx = ctypes.c_void_p()
+    d, r, s = (ctypes.c_int64 * N)(*dims), (ctypes.c_int64 * N)(*ranks), (ctypes.c_int64 * N)(*rb)
+    assert L.tr_als_init(ctypes.byref(ctx), N, d, r, ctypes.c_void_p(X), C.TR_F64, (ctypes.c_void_p * N)(*ca),
+                         C.VARIANT[variant], None) == 0
+    k, f = ctypes.c_int(), ctypes.c_double()
+    # stand-in data are zeros: the estimate repeats, so tol 0 stops after the second sweep
+    assert L.tr_als_run(ctx, 3, C.TR_F64, 1, 0.0, ctypes.byref(k), ctypes.byref(f)) == 0 and k.value == 2
+    assert L.fakehip_launches(b"cheap_fit_kernel") == 2
+    L.tr_als_destroy(ctx)
+    v = ctypes.c_double()
+    live = L.fakehip_live_allocations()
+    assert L.tr_inner(N, d, r, (ctypes.c_void_p * N)(*ca), s, (ctypes.c_void_p * N)(*cb), ctypes.byref(v), None) == 0
+    assert L.tr_norm(N, d, s, (ctypes.c_void_p * N)(*cb), ctypes.byref(v), None) == 0
+    assert L.fakehip_live_allocations() == live
+    _clean(host, f"run / inner {variant}")
+    for p in ca + cb + [X]:
+        host.free(p)

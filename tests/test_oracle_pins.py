@@ -378,7 +378,8 @@ def test_variants_equivalent():
     init = rand_cores(dims, ranks, 30)
     ref, _ = O.tr_als(X, init, 10, solve="qr")
     for other in (O.tr_als(X, init, 10, solve="ne")[0], O.tr_als(X, init, 10, solve="lstsq")[0],
-                  O.tr_als_qr_literal(X, init, 10), O.tr_als_ne_literal(X, init, 10)):
+                  O.tr_als_qr_literal(X, init, 10), O.tr_als_ne_literal(X, init, 10),
+                  O.tr_als_qrne_literal(X, init, 10)):
         for a, b in zip(other, ref):
             assert np.linalg.norm(a - b) <= 1e-10 * np.linalg.norm(b)
 
@@ -391,9 +392,18 @@ def test_qr_literal_case_short_core():
     X = W.add_noise(O.tr_full(true), 1e-2, np.random.default_rng(32))
     init = rand_cores(dims, ranks, 33)
     ref, _ = O.tr_als(X, init, 3)
-    out = O.tr_als_qr_literal(X, init, 3)
-    for a, b in zip(out, ref):
-        assert np.linalg.norm(a - b) <= 1e-9 * np.linalg.norm(b)
+    for out in (O.tr_als_qr_literal(X, init, 3), O.tr_als_qrne_literal(X, init, 3)):
+        for a, b in zip(out, ref):
+            assert np.linalg.norm(a - b) <= 1e-9 * np.linalg.norm(b)
+
+
+def test_r_core_grams_equal_core_grams():
+    """Alg. 4 forms its Grams from the R-cores: G(2) = Q R(2) with orthonormal
+    Q, so the R-core Gram equals the core's Gram (also when I < R_n R_{n+1})."""
+    for dims, ranks, seed in (((9, 3), (2, 3), 40), ((12, 5, 7), (3, 2, 2), 41)):
+        for G in rand_cores(dims, ranks, seed):
+            _, Rc = O.mode2_qr(G)
+            assert np.allclose(O.gram_tensor(Rc), O.gram_tensor(G), rtol=0, atol=1e-12 * np.abs(G).max() ** 2)
 
 
 # ---------------------------------------------------------------------------
