@@ -40,6 +40,9 @@ typedef struct tr_als_ctx tr_als_ctx;
  * equation). */
 enum { TR_NE = 0, TR_QR = 1, TR_QRNE = 2 };
 
+/* Solve of the mode update (tr_als_set_solve). */
+enum { TR_SOLVE_FACTOR = 0, TR_SOLVE_PINV = 1 };
+
 /* Element types: storage type of X (TR_F64 or TR_F32) and the precision of the
  * X contraction (all four).  The Gram, ring, solve and QR steps are always FP64. */
 enum { TR_F64 = 0, TR_F32 = 1, TR_BF16 = 2, TR_FP8 = 3 };
@@ -93,6 +96,21 @@ int tr_als_init(tr_als_ctx** ctx, int N, const int64_t* dims, const int64_t* ran
  * update and the context stays usable.
  */
 int tr_als_sweep(tr_als_ctx* ctx, int nsweeps, int contraction_prec, int refine_steps);
+
+/*
+ * tr_als_set_solve -- how the mode update solves its least-squares problem.
+ *   TR_SOLVE_FACTOR (the default): TR_NE / TR_QRNE invert S_n<2> (SPD inverse,
+ *     or Cholesky for R_n R_{n+1} > 128), TR_QR substitutes with R_[2] (Alg. 3);
+ *     a singular or indefinite S_n / R_[2] stops the sweep with TR_ESINGULAR.
+ *   TR_SOLVE_PINV: the rank-deficient-safe solve (the remark after Alg. 3):
+ *     S_n<2>^+ by a one-sided Jacobi SVD in FP64, singular values of S_n at or
+ *     below rcond * max dropped (rcond = 0: R_n R_{n+1} * 2^-52), so each
+ *     update is the minimum-norm least-squares solution.  TR_QR then takes
+ *     Alg. 4's route through V_n[2]^T V_n[2] (a rank-deficient V_n[2] has no
+ *     Cholesky-QR).  rcond in [0, 1).
+ * Takes effect from the next mode update; synchronises the stream.
+ */
+int tr_als_set_solve(tr_als_ctx* ctx, int solve, double rcond);
 
 /*
  * tr_als_run -- sweeps until the relative error stops improving: after each

@@ -17,6 +17,8 @@ TR_OK, TR_EINVAL, TR_ENOMEM, TR_EHIP, TR_ESINGULAR, TR_ENONFINITE = 0, -1, -2, -
 
 PREC = {"f64": TR_F64, "f32": TR_F32, "bf16": TR_BF16, "fp8": TR_FP8}
 VARIANT = {"ne": TR_NE, "qr": TR_QR, "qrne": TR_QRNE}
+TR_SOLVE_FACTOR, TR_SOLVE_PINV = 0, 1
+SOLVE = {"factor": TR_SOLVE_FACTOR, "pinv": TR_SOLVE_PINV}
 
 _vp = ctypes.c_void_p
 _i64p = ctypes.POINTER(ctypes.c_int64)
@@ -41,6 +43,7 @@ _SIGS = {
     "tr_als_debug_overruns": (ctypes.c_int, []),
     "tr_als_debug_graphs": (ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.c_int]),
     "tr_als_profile_read": (ctypes.c_int, [_vp, _dp, _i64p, _dp]),
+    "tr_als_set_solve": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double]),
     "tr_als_run": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                   ctypes.POINTER(ctypes.c_int), _dp]),
     "tr_inner": (ctypes.c_int, [ctypes.c_int, _i64p, _i64p, ctypes.POINTER(_vp), _i64p, ctypes.POINTER(_vp), _dp,

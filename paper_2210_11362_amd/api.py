@@ -51,6 +51,10 @@ class TRContext:
     def sweep(self, nsweeps: int = 1, prec: str = "f32", refine: int = 1):
         return C.check(C.lib().tr_als_sweep(self._h, int(nsweeps), C.PREC[prec], int(refine)), self._h, "tr_als_sweep")
 
+    def set_solve(self, solve: str = "factor", rcond: float = 0.0):
+        """``factor`` (default) or ``pinv`` (rank-deficient-safe, ``tr_als_set_solve``)."""
+        C.check(C.lib().tr_als_set_solve(self._h, C.SOLVE[solve], float(rcond)), self._h, "tr_als_set_solve")
+
     def run(self, max_sweeps: int, prec: str = "f64", refine: int = 1, tol: float = 0.0):
         """Sweeps until the in-loop error estimate changes by at most ``tol``
         (``tr_als_run``): returns (sweeps run, last estimate)."""

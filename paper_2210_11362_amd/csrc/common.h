@@ -163,6 +163,11 @@ hipError_t launch_fit(const void* X, int xdt, int64_t I, int64_t K, const double
                       const double* F2, int64_t d1, int64_t m1, int64_t d2, int64_t m2, int Rb, int Rmid, int Ra,
                       double* partials, int nblk, double* out, hipStream_t s);
 hipError_t launch_table_absmax(const double* T, int64_t n, double* out, hipStream_t s);
+// pseudo-inverse of a square FP64 matrix by the one-sided Jacobi SVD (one
+// workgroup); singular values <= rcond * max count as zero; work: 2 n^2 doubles
+bool pinv_fits(int n);
+hipError_t launch_pinv(const double* A, int n, double rcond, double* Apinv, double* work, int* status,
+                       hipStream_t s);
 // cheap in-loop error (Sec. 4): rows of A (M_N or W_N) and G = G_N(2) (I x n);
 // mode 0: B = S_N (n x n), mode 1: B = R_[2]^T (lower); out[0] = ||X||^2 - 2a + b,
 // out[1] = a = <X, Xhat>, out[2] = b = ||Xhat||^2.  partials: 2 * cheap_fit_blocks(I)

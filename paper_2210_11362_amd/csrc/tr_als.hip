@@ -52,6 +52,12 @@ struct tr_als_ctx {
   hipStream_t cap_stream = nullptr;          // private stream the sweep graphs are captured on
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   double* Sinv = nullptr;
+  // solve of the mode update: TR_SOLVE_FACTOR (SPD inverse / Cholesky, or the
+  // triangular substitution of Alg. 3) or TR_SOLVE_PINV (pseudo-inverse by the
+  // Jacobi SVD, singular values <= rcond * max dropped)
+  int solve = TR_SOLVE_FACTOR;
+  double rcond = 0.0;
+  double* pinvw = nullptr;
   double* rdiag = nullptr;                   // reciprocal pivots of the Cholesky factor
   // QR variant state (Alg. 3): per-core Q_j (I_j x r_j) and R-cores
   // (R_j x r_j x R_{j+1}), r_j = min(I_j, R_j R_{j+1}); workspace
@@ -765,6 +771,11 @@ bool ring_prefix_single(const tr_als_ctx* c, int m, Gemm64Desc* d) {
   return true;
 }
 
+// Cut-off of the pseudo-inverse of S_n: the caller's rcond, else n * eps
+// (relative to the largest singular value of S_n, which squares those of
+// G^{!=n}_[2]).
+double pinv_rcond(const tr_als_ctx* c, int n) { return c->rcond > 0.0 ? c->rcond : n * 2.220446049250313e-16; }
+
 // One NE mode update.  The coefficient branch (Gram ring -> S_n -> Cholesky ->
 // S_n^{-1}) does not depend on X and runs on a second stream concurrently with
 // the MTTSP; the solve is then G = M S^{-1} with iterative refinement
@@ -788,7 +799,9 @@ int update_mode_ne(tr_als_ctx* c, int m, int prec, int refine, bool in_sweep) {
     const bool pair = prefix && m + 1 < c->N && ring_prefix_single(c, m + 1, &pd);
     const int r = compute_coef(c, m, c->S, s2, prefix && m > 0, pair ? &pd : nullptr);
     if (r) return r;
-    if (spd_inverse_fits(n)) {
+    if (c->solve == TR_SOLVE_PINV) {
+      HIPCHK(c, launch_pinv(c->S, n, pinv_rcond(c, n), c->Sinv, c->pinvw, c->status, s2));
+    } else if (spd_inverse_fits(n)) {
       HIPCHK(c, launch_spd_inverse(c->S, n, c->Sinv, c->status, s2));
     } else {
       HIPCHK(c, launch_chol(c->S, n, c->Lf, c->LTf, c->cholw, c->status, s2));
@@ -928,7 +941,9 @@ int update_mode_qrne(tr_als_ctx* c, int m, int prec, int refine) {
   const int Ra = c->R[m], Rb = c->R[m + 1], n = Ra * Rb;
   int rc = compute_coef(c, m, c->S, s);
   if (rc) return rc;
-  if (spd_inverse_fits(n)) {
+  if (c->solve == TR_SOLVE_PINV) {
+    HIPCHK(c, launch_pinv(c->S, n, pinv_rcond(c, n), c->Sinv, c->pinvw, c->status, s));
+  } else if (spd_inverse_fits(n)) {
     HIPCHK(c, launch_spd_inverse(c->S, n, c->Sinv, c->status, s));
   } else {
     HIPCHK(c, launch_chol(c->S, n, c->Lf, c->LTf, c->cholw, c->status, s));
@@ -1130,6 +1145,7 @@ int trx_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ranks,
   A((void**)&c->cholw, (size_t)maxRR * maxRR * 8);
   A((void**)&c->LinvT, (size_t)maxRR * maxRR * 8);
   A((void**)&c->Sinv, (size_t)maxRR * maxRR * 8);
+  A((void**)&c->pinvw, (size_t)2 * maxRR * maxRR * 8);
   A((void**)&c->rdiag, 256 * 8);
   A((void**)&c->Tsol, (size_t)maxI * maxRR * 8);
   A((void**)&c->W0, (size_t)maxW * 8);
@@ -1541,8 +1557,11 @@ int tr_gen_planted_noalloc(int N, const int64_t* dims, const int64_t* ranks, uin
 extern "C" {
 
 static int update_mode(tr_als_ctx* c, int m, int prec, int refine, bool in_sweep) {
-  if (c->variant == TR_QR) return update_mode_qr(c, m, prec);
-  if (c->variant == TR_QRNE) return update_mode_qrne(c, m, prec, refine);
+  // a rank-deficient V_n[2] breaks the Cholesky-QR before R_[2] exists: with
+  // the pseudo-inverse solve the QR variant takes Alg. 4's route (the same
+  // half-size problem, min ||Y_[n] - G V_n[2]^T||, through V_n[2]^T V_n[2])
+  if (c->variant == TR_QR && c->solve != TR_SOLVE_PINV) return update_mode_qr(c, m, prec);
+  if (c->variant == TR_QR || c->variant == TR_QRNE) return update_mode_qrne(c, m, prec, refine);
   return update_mode_ne(c, m, prec, refine, in_sweep);
 }
 
@@ -1638,7 +1657,7 @@ static int enqueue_cheap_fit(tr_als_ctx* c) {
   const int m = c->N - 1;
   const int n = c->R[m] * c->R[m + 1];
   if (2 * cheap_fit_blocks(c->dims[m]) > c->nred) return fail(c, TR_EINVAL, "internal: partial buffer too small");
-  const bool qr = c->variant == TR_QR;
+  const bool qr = c->variant == TR_QR && c->solve != TR_SOLVE_PINV;
   HIPCHK(c, launch_cheap_fit(qr ? c->qW : c->M, c->Gn, qr ? c->qLt : c->S, qr ? 1 : 0, c->dims[m], n, c->dscal,
                              c->dpart, c->dscal + 4, c->stream));
   return TR_OK;
@@ -1672,6 +1691,32 @@ int tr_als_run(tr_als_ctx* c, int max_sweeps, int prec, int refine, double tol, 
   if (rc2) return rc2;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return rc;
+}
+
+int tr_als_set_solve(tr_als_ctx* c, int solve, double rcond) {
+  if (!valid_ctx(c)) return TR_EINVAL;
+  if ((solve != TR_SOLVE_FACTOR && solve != TR_SOLVE_PINV) || !(rcond >= 0.0) || rcond >= 1.0)
+    return fail(c, TR_EINVAL, "bad solve arguments");
+  for (int m = 0; m < c->N; ++m)
+    if (solve == TR_SOLVE_PINV && !pinv_fits(c->R[m] * c->R[m + 1]))
+      return fail(c, TR_EINVAL, "R_n R_{n+1} too large for the pseudo-inverse");
+  if (solve == TR_SOLVE_PINV && c->variant == TR_QR && c->solve != TR_SOLVE_PINV) {
+    // the QR context's Grams were formed from the initial cores only: refresh
+    // them from the current R-cores for Alg. 4's route
+    for (int k = 0; k < c->N; ++k)
+      HIPCHK(c, launch_gram(c->qR[k], c->R[k], c->qr_r[k], c->R[k + 1], c->gram[k], c->stream));
+  }
+  c->solve = solve;
+  c->rcond = rcond;
+  // captured sweeps embed the solve: drop them
+  for (auto& row : c->graphs)
+    for (auto& g : row)
+      if (g) {
+        (void)hipGraphExecDestroy(g);
+        g = nullptr;
+      }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return TR_OK;
 }
 
 int tr_als_update_mode(tr_als_ctx* c, int n, int prec, int refine) {

@@ -496,3 +496,18 @@ def test_fp8_e4m3_encoder_fixed_values():
     for xv, qv in zip(x[:2000], q[:2000]):
         d = np.abs(fin - abs(float(xv)))
         assert abs(abs(qv) - abs(float(xv))) <= d.min() + 1e-12
+
+
+def test_lstsq_minimum_norm_on_a_duplicated_column():
+    """With A = [A1, A1[:, 0]] (one column repeated) the least-squares fit is the
+    full-rank fit of A1; the minimum-norm coefficients split the repeated
+    column's weight equally between its two copies.  Pins the oracle's
+    rank-deficient solve (lstsq) and the fallback of its default (qr) mode."""
+    g = np.random.default_rng(60)
+    A1 = g.standard_normal((40, 5))
+    B = g.standard_normal((40, 3))
+    A = np.hstack([A1, A1[:, :1]])
+    Z1 = O.solve_ls(A1, B, "qr")
+    want = np.vstack([Z1[:1] / 2, Z1[1:], Z1[:1] / 2])
+    for mode in ("lstsq", "qr"):
+        assert np.allclose(O.solve_ls(A, B, mode), want, rtol=0, atol=1e-12)
