@@ -58,6 +58,33 @@ struct XgArgs {
   void* partial;      // [nsplit][n_mt*n_nt][MT][NT] FP32 (FP64 for the FP64 path)
 };
 
+// Arguments of the slab contraction of an order-3 tensor (k_slab.hip): rows i
+// of the output mode, the contracted mode k (against a table of its core) and
+// the slab mode l (its core absorbed per slab).
+struct XslabArgs {
+  const void* X;
+  int64_t In, Ik, Il;     // extents of the output, contracted and slab modes
+  int64_t sn, sk, sl;     // their strides in X (elements); sn == 1 or sk == 1
+  int caseB;              // 0: table G_c1[b, k, m], absorb G_c2[m, l, a]; 1: table G_c2[m, k, a], absorb G_c1[b, l, m]
+  const double* Gl;       // the absorbed core (FP64)
+  int Rm, Ro, Rg, Rn;     // middle rank, other rank of the absorbed core, range of the group index, R_n
+  int NG, TWg, OWg;       // group size, table columns per group (multiple of 16), outputs per group
+  int n_mt, n_g;
+  int64_t ldb;            // k-stride of the table (Ik rounded up to the k tile)
+  const void* Bt;         // table, transposed, operand type: [g TWg + m + Rm u][k]
+  int64_t l_per_split;
+  int nsplit;
+  void* partial;          // [nsplit][n_mt n_g][128][OWg] FP32 (FP64 on the FP64 path)
+};
+int xslab_kt(int prec);
+size_t xslab_lds_bytes(const XslabArgs& a, int prec);
+int xslab_group(int Rm, int Ro);
+int xslab_rows();
+hipError_t launch_xslab_table(const XslabArgs& a, const double* Gk, int prec, void* Bt, hipStream_t s);
+hipError_t launch_xslab(const XslabArgs& a, int prec, int xdt, size_t lds, hipStream_t s);
+hipError_t launch_xslab_reduce(const XslabArgs& a, int prec, double out_scale, double* M, int* status,
+                               hipStream_t s);
+
 // Host-side launchers (defined in the .hip files).
 int xgemm_kt(int prec);
 hipError_t launch_xgemm(const XgArgs& g, int prec, int xdt, hipStream_t s);
@@ -117,6 +144,10 @@ bool solve_in_lds(int n);
 // S^{-1} of an SPD matrix with n <= 128 by the symmetric sweep operator (one
 // workgroup, registers); a non-positive pivot latches ST_SINGULAR.
 bool spd_inverse_fits(int n);
+// dst[r + ld_dst c] = src[r + ld_src c] for a rows x cols block (trans = 1:
+// src[c + ld_src r]; src == nullptr: zeros)
+hipError_t launch_copy_block(const double* src, int64_t ld_src, int rows, int cols, double* dst, int64_t ld_dst,
+                             hipStream_t s, int trans = 0);
 hipError_t launch_spd_inverse(const double* S, int n, double* Sinv, int* status, hipStream_t s);
 hipError_t launch_chol_lds(const double* S, int n, double* L, double* LT, double* rdiag, int* status, hipStream_t s);
 hipError_t launch_trsm_rhs(const double* L, const double* rdiag, int n, const double* Rhs, int64_t I, double* G,

@@ -99,8 +99,9 @@ __global__ __launch_bounds__(NTHR) void xstream_kernel(XsArgs a) {
   const int64_t i0 = (int64_t)mt * MT;
   const int b0 = nt * a.NTb;
   const int bcount = min(a.NTb, a.Rb - b0);
-  const int Rb4 = (a.Rb + 3) & ~3, Ra4 = (a.Ra + 3) & ~3;
-  const int row1 = a.Rmid * Rb4, row2 = a.Rmid * Ra4;
+  // F1 rows are staged only for this workgroup's b-range (NTb values)
+  const int Bw4 = (a.NTb + 3) & ~3, Ra4 = (a.Ra + 3) & ~3;
+  const int row1 = a.Rmid * Bw4, row2 = a.Rmid * Ra4;
   const int s1max = (a.d1 == 1) ? KT : min((int64_t)KT, (KT + a.d1 - 1) / a.d1 + 1);
   const int s2max = (a.d2 == 1) ? KT : min((int64_t)KT, (KT + a.d2 - 1) / a.d2 + 1);
 
@@ -139,52 +140,87 @@ __global__ __launch_bounds__(NTHR) void xstream_kernel(XsArgs a) {
     const int kvalid = (int)min((int64_t)KT, kend - k0);
     __syncthreads();
 
-    // ---- X tile -> Xs[i][kk] ----
+    // ---- X tile -> Xs[i][kk]: every load of the tile in flight before the
+    // LDS stores (one round trip to memory per tile, not one per element) ----
+    constexpr int XE = (128 * KT) / NTHR;   // MT <= 128
     if (a.layout == 0) {
       // A[i, k] at i + I*k: consecutive threads walk i (contiguous in memory)
-      for (int e = tid; e < MT * KT; e += NTHR) {
+      op_t xv[XE];
+#pragma unroll
+      for (int q = 0; q < XE; ++q) {
+        const int e = tid + q * NTHR;
         const int ii = e % MT, kk = e / MT;
         const int64_t i = i0 + ii;
-        op_t v = to_op<P>((gen_t)0);
-        if (i < a.I && kk < kvalid) v = x_to_op<P, Tin>(X[i + a.I * (k0 + kk)]);
-        Xs[ii * ST + kk] = v;
+        xv[q] = (e < MT * KT && i < a.I && kk < kvalid) ? x_to_op<P, Tin>(X[i + a.I * (k0 + kk)])
+                                                         : to_op<P>((gen_t)0);
+      }
+#pragma unroll
+      for (int q = 0; q < XE; ++q) {
+        const int e = tid + q * NTHR;
+        if (e < MT * KT) Xs[(e % MT) * ST + e / MT] = xv[q];
       }
     } else {
       // A[i, k] at (k % L) + L*i + L*I*(k / L): consecutive threads walk k
       const int64_t k = k0 + kk_t;
       const bool kok = kk_t < kvalid;
       const int64_t koff = kok ? (k % a.L) + a.L * a.I * (k / a.L) : 0;
-      for (int ii = tid / KT; ii < MT; ii += rstep) {
+      const int ii0 = tid / KT;
+      op_t xv[XE];
+#pragma unroll
+      for (int q = 0; q < XE; ++q) {
+        const int ii = ii0 + q * rstep;
         const int64_t i = i0 + ii;
-        op_t v = to_op<P>((gen_t)0);
-        if (kok && i < a.I) v = x_to_op<P, Tin>(X[koff + a.L * i]);
-        Xs[ii * ST + kk_t] = v;
+        xv[q] = (ii < MT && kok && i < a.I) ? x_to_op<P, Tin>(X[koff + a.L * i]) : to_op<P>((gen_t)0);
+      }
+#pragma unroll
+      for (int q = 0; q < XE; ++q) {
+        const int ii = ii0 + q * rstep;
+        if (ii < MT) Xs[ii * ST + kk_t] = xv[q];
       }
     }
 
-    // ---- stage the partial-subchain rows this tile needs ----
+    // ---- stage the partial-subchain rows this tile needs, eight loads per
+    // thread in flight at a time ----
     const int64_t s1f = k0 / a.d1, s2f = k0 / a.d2;
     const int ns1 = (int)((k0 + kvalid - 1) / a.d1 - s1f + 1);
     const int ns2 = (int)((k0 + kvalid - 1) / a.d2 - s2f + 1);
     {
-      const int tps = ns1 >= 64 ? 4 : (ns1 >= 16 ? 16 : 64);
-      for (int s = tid / tps; s < ns1; s += NTHR / tps) {
-        const double* src = a.F1 + ((s1f + s) % a.m1) * (int64_t)(a.Rb * a.Rmid);
-        gen_t* dst = F1s + s * row1;
-        for (int e = tid % tps; e < row1; e += tps) {
-          const int m = e / Rb4, b = e % Rb4;
-          dst[e] = (b < a.Rb) ? (gen_t)src[b + a.Rb * m] : (gen_t)0;
+      const int tot = ns1 * row1;
+      for (int base = tid; base < tot; base += 8 * NTHR) {
+        gen_t t[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int e = base + j * NTHR;
+          const int sidx = e / row1, el = e % row1;
+          const int m = el / Bw4, bl = el % Bw4;
+          t[j] = (e < tot && bl < bcount)
+                     ? (gen_t)a.F1[((s1f + sidx) % a.m1) * (int64_t)(a.Rb * a.Rmid) + (b0 + bl) + a.Rb * m]
+                     : (gen_t)0;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int e = base + j * NTHR;
+          if (e < tot) F1s[e] = t[j];
         }
       }
     }
     {
-      const int tps = ns2 >= 64 ? 4 : (ns2 >= 16 ? 16 : 64);
-      for (int s = tid / tps; s < ns2; s += NTHR / tps) {
-        const double* src = a.F2 + ((s2f + s) % a.m2) * (int64_t)(a.Rmid * a.Ra);
-        gen_t* dst = F2s + s * row2;
-        for (int e = tid % tps; e < row2; e += tps) {
-          const int m = e / Ra4, aa = e % Ra4;
-          dst[e] = (aa < a.Ra) ? (gen_t)src[m + a.Rmid * aa] : (gen_t)0;
+      const int tot = ns2 * row2;
+      for (int base = tid; base < tot; base += 8 * NTHR) {
+        gen_t t[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int e = base + j * NTHR;
+          const int sidx = e / row2, el = e % row2;
+          const int m = el / Ra4, aa = el % Ra4;
+          t[j] = (e < tot && aa < a.Ra)
+                     ? (gen_t)a.F2[((s2f + sidx) % a.m2) * (int64_t)(a.Rmid * a.Ra) + m + a.Rmid * aa]
+                     : (gen_t)0;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int e = base + j * NTHR;
+          if (e < tot) F2s[e] = t[j];
         }
       }
     }
@@ -211,7 +247,7 @@ __global__ __launch_bounds__(NTHR) void xstream_kernel(XsArgs a) {
 #pragma unroll
             for (int x = 0; x < 4; ++x) fa[x] = f2[m * Ra4 + 4 * ab + x];
 #pragma unroll
-            for (int y = 0; y < 4; ++y) fb[y] = f1[m * Rb4 + b0 + 4 * bb + y];
+            for (int y = 0; y < 4; ++y) fb[y] = f1[m * Bw4 + 4 * bb + y];
 #pragma unroll
             for (int x = 0; x < 4; ++x)
 #pragma unroll
@@ -332,9 +368,9 @@ size_t xstream_lds_bytes(const XsArgs& a, int prec, int kt) {
   }
   const size_t st = kt + pad;
   size_t bytes = (((size_t)(a.MT + a.NT) * st * ops) + 15) & ~(size_t)15;
-  const int Rb4 = (a.Rb + 3) & ~3, Ra4 = (a.Ra + 3) & ~3;
+  const int Bw4 = (a.NTb + 3) & ~3, Ra4 = (a.Ra + 3) & ~3;
   auto smax = [&](int64_t d) -> int64_t { return d == 1 ? kt : std::min<int64_t>(kt, (kt + d - 1) / d + 1); };
-  bytes += (size_t)(smax(a.d1) * a.Rmid * Rb4 + smax(a.d2) * a.Rmid * Ra4) * gens;
+  bytes += (size_t)(smax(a.d1) * a.Rmid * Bw4 + smax(a.d2) * a.Rmid * Ra4) * gens;
   return bytes;
 }
 

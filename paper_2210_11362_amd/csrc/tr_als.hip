@@ -31,6 +31,10 @@ struct Plan {
   int64_t gK = 1, gM = 1;     // group size and rows of the intermediate
   int gC = 1, gRu = 1, gRc = 1;
   bool reuse_prev = false;    // same group table as the previous mode of the sweep
+  // slab contraction (order 3, large ranks; k_slab.hip): mode contracted on
+  // MFMA against its core, slab mode absorbed per slab, and the case
+  bool slab = false;
+  int sk_mode = 0, sl_mode = 0, slab_caseB = 0;
   bool reuse_y = false;       // and the same reduced stage-1 result, still in Y0
   struct Step { int64_t lo, I, hi; int Ru, Rc, core, side; };
   std::vector<Step> steps;
@@ -58,6 +62,7 @@ struct tr_als_ctx {
   int solve = TR_SOLVE_FACTOR;
   double rcond = 0.0;
   double* pinvw = nullptr;
+  double* blkw = nullptr;   // workspace of the blocked SPD inverse (R_n R_{n+1} > 112)
   double* rdiag = nullptr;                   // reciprocal pivots of the Cholesky factor
   // QR variant state (Alg. 3): per-core Q_j (I_j x r_j) and R-cores
   // (R_j x r_j x R_{j+1}), r_j = min(I_j, R_j R_{j+1}); workspace
@@ -324,6 +329,25 @@ Plan make_plan(const tr_als_ctx* c, int m) {
     p.gC = p.gRu * p.gRc;
     p.gM = c->numel / p.gK;
   }
+  // Order 3 outside the two-stage regime with R_n R_{n+1} > 128: the fused
+  // kernel would form R^3 subchain values per k for many column tiles; the
+  // slab kernel contracts one mode against its core on MFMA and absorbs the
+  // other per slab instead (TR_ALS_NO_SLAB=1 keeps the fused kernel).
+  const bool no_slab = getenv("TR_ALS_NO_SLAB") && getenv("TR_ALS_NO_SLAB")[0] == '1';
+  if (N == 3 && p.regime == 2 && !no_slab && (int64_t)R[m] * R[m + 1] > 128) {
+    const int c1 = (m + 1) % 3, c2 = (m + 2) % 3;
+    // the contracted mode must leave a 2-D slab with unit stride along the rows or along k
+    const int kappa = m == 0 ? c1 : 0;
+    const int caseB = kappa == c2 ? 1 : 0;
+    const int Rm = R[c2];
+    const int Ro = caseB ? R[m + 1] : R[m];
+    if (xslab_group(Rm, Ro) > 0) {
+      p.slab = true;
+      p.sk_mode = kappa;
+      p.sl_mode = caseB ? c1 : c2;
+      p.slab_caseB = caseB;
+    }
+  }
   return p;
 }
 
@@ -427,6 +451,47 @@ XsCfg xs_config(const tr_als_ctx* c, int m, int prec) {
   a.k_per_split = tps * x.kt;
   a.nsplit = (int)((p.K + a.k_per_split - 1) / a.k_per_split);
   return x;
+}
+
+// Slab-kernel configuration of mode m (order 3): strides, ranks, groups and
+// the split over slabs (about two workgroups per CU in flight).
+XslabArgs xslab_config(const tr_als_ctx* c, int m, const void* X) {
+  const Plan& p = c->plan[m];
+  XslabArgs a;
+  const int64_t stride[3] = {1, c->dims[0], c->dims[0] * c->dims[1]};
+  a.X = X;
+  a.In = c->dims[m]; a.Ik = c->dims[p.sk_mode]; a.Il = c->dims[p.sl_mode];
+  a.sn = stride[m]; a.sk = stride[p.sk_mode]; a.sl = stride[p.sl_mode];
+  a.caseB = p.slab_caseB;
+  a.Gl = c->cores[p.sl_mode];
+  const int c2 = (m + 2) % 3;
+  a.Rm = c->R[c2];
+  a.Rn = c->R[m];
+  a.Rg = a.caseB ? c->R[m] : c->R[m + 1];
+  a.Ro = a.caseB ? c->R[m + 1] : c->R[m];
+  a.NG = xslab_group(a.Rm, a.Ro);
+  a.TWg = (a.NG * a.Rm + 15) / 16 * 16;
+  a.OWg = a.NG * a.Ro;
+  a.n_g = (a.Rg + a.NG - 1) / a.NG;
+  a.n_mt = (int)((a.In + xslab_rows() - 1) / xslab_rows());
+  a.ldb = 0;                 // set per precision by the caller (k tile)
+  const int64_t tiles = (int64_t)a.n_mt * a.n_g;
+  int64_t ns = std::max<int64_t>(1, std::min<int64_t>(a.Il, (512 + tiles - 1) / tiles));
+  a.l_per_split = (a.Il + ns - 1) / ns;
+  a.nsplit = (int)((a.Il + a.l_per_split - 1) / a.l_per_split);
+  a.Bt = c->Bt;
+  a.partial = c->partial;
+  return a;
+}
+
+size_t xslab_partial_bytes(const XslabArgs& a, int prec) {
+  return (size_t)a.nsplit * a.n_mt * a.n_g * xslab_rows() * a.OWg * (prec == TR_F64 ? 8 : 4);
+}
+
+size_t xslab_bt_bytes(const XslabArgs& a, int prec) {   // BF16: hi and lo parts
+  const int kt = xslab_kt(prec);
+  const int64_t ldb = (a.Ik + kt - 1) / kt * kt;
+  return (size_t)a.n_g * a.TWg * ldb * (prec == TR_F64 ? 8 : prec == TR_F32 ? 4 : 4);
 }
 
 XgArgs xg_config(const tr_als_ctx* c, int m, int prec, const void* X, int esize, bool transposed = false,
@@ -631,10 +696,46 @@ int compute_mttsp_two_stage(tr_als_ctx* c, int m, int prec, double* Mout, bool i
 
 // M_n = X_[n] G^{!=n}_[2] for the context's current cores (tables + X stream +
 // ordered split-K reduction).
+// M_n by the slab kernel (order 3, large ranks): table of the contracted
+// mode's core in the operand type, the slab pass over X, ordered reduction.
+int compute_mttsp_slab(tr_als_ctx* c, int m, int prec, double* Mout, const Hook& after_main) {
+  hipStream_t s = c->stream;
+  const Plan& p = c->plan[m];
+  int rc = ensure_shadow(c, prec);
+  if (rc) return rc;
+  const void* X = prec == TR_BF16 ? c->xbf16 : c->X;
+  XslabArgs a = xslab_config(c, m, X);
+  const int kt = xslab_kt(prec);
+  a.ldb = (a.Ik + kt - 1) / kt * kt;
+  if (xslab_partial_bytes(a, prec) > c->partial_bytes || xslab_bt_bytes(a, prec) > c->bt_bytes)
+    return fail(c, TR_EHIP, "internal: slab buffers too small");
+  HIPCHK(c, launch_xslab_table(a, c->cores[p.sk_mode], prec, c->Bt, s));
+  const bool prof = c->prof;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (prof) {
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    HIPCHK(c, hipEventRecord(e0, s));
+  }
+  HIPCHK(c, launch_xslab(a, prec, (prec == TR_F64 || prec == TR_F32) ? c->xdt : prec, xslab_lds_bytes(a, prec), s));
+  if (prof) {
+    HIPCHK(c, hipEventRecord(e1, s));
+    c->evs.push_back({e0, e1});
+    c->prof_bytes = (double)c->numel * (prec == TR_BF16 ? 2 : (c->xdt == TR_F64 ? 8 : 4));
+  }
+  if (after_main) {
+    const int hr = after_main();
+    if (hr) return hr;
+  }
+  HIPCHK(c, launch_xslab_reduce(a, prec, 1.0, Mout, c->status, s));
+  return TR_OK;
+}
+
 int compute_mttsp(tr_als_ctx* c, int m, int prec, double* Mout, bool in_sweep = false, const Hook& after_main = Hook()) {
   hipStream_t s = c->stream;
   const Plan& p = c->plan[m];
   if (p.regime == 1) return compute_mttsp_two_stage(c, m, prec, Mout, in_sweep, after_main);
+  if (p.slab && prec != TR_FP8) return compute_mttsp_slab(c, m, prec, Mout, after_main);
   int rc = build_table(c, p.f1c, p.Rmid, c->F1);
   if (rc) return rc;
   rc = build_table(c, p.f2c, p.Rmid, c->F2);
@@ -771,6 +872,74 @@ bool ring_prefix_single(const tr_als_ctx* c, int m, Gemm64Desc* d) {
   return true;
 }
 
+// S^{-1} of an SPD matrix larger than the one-workgroup inverse takes
+// (R_n R_{n+1} > 112), from a blocked Cholesky factor: with S = [A C; C^T D],
+// A = L_A L_A^T (LDS Cholesky of a block of at most 112), L_21 = C^T L_A^{-T}
+// (triangular solves on the rows of C^T), the Schur complement
+// D - L_21 L_21^T (FP64 MFMA) factored the same way, and the inverse factor
+// L^{-1} = [L_A^{-1} 0; -L_D^{-1} L_21 L_A^{-1}  L_D^{-1}]; then
+// S^{-1} = L^{-T} L^{-1}.  A non-positive pivot latches ST_SINGULAR.  S
+// (ld ldS) may be a sub-block; Linv (ld ldo) receives L^{-1}; ws holds
+// chol_inv_blocked_ws(n) doubles.
+int chol_inv_blocked(tr_als_ctx* c, const double* S, int64_t ldS, int n, double* Linv, int64_t ldo, double* ws,
+                     hipStream_t s) {
+  constexpr int b = 112;
+  const int nb = std::min(n, b);
+  double* Ac = ws;                       // nb x nb
+  double* L = Ac + nb * nb;              // nb x nb
+  double* LT = L + nb * nb;              // nb x nb
+  double* G = LT + nb * nb;              // nb x nb: L_A^{-T}
+  double* rd = G + nb * nb;              // 256 reciprocal pivots
+  double* rest = rd + 256;
+  HIPCHK(c, launch_copy_block(S, ldS, nb, nb, Ac, nb, s));
+  HIPCHK(c, launch_chol_lds(Ac, nb, L, LT, rd, c->status, s));
+  HIPCHK(c, launch_trsm_rhs(L, rd, nb, nullptr, nb, G, 0, c->status, s, 1));          // G = L_A^{-T}
+  HIPCHK(c, launch_copy_block(G, nb, nb, nb, Linv, ldo, s, 1));                       // L_A^{-1} = G^T
+  if (n <= b) return TR_OK;
+  const int m = n - b;
+  double* Ct = rest;                     // m x b: C^T = S[b:n, 0:b]
+  double* L21 = Ct + (int64_t)m * b;     // m x b
+  double* Sc = L21 + (int64_t)m * b;     // m x m
+  double* T1 = Sc + (int64_t)m * m;      // m x b
+  double* next = T1 + (int64_t)m * b;
+  HIPCHK(c, launch_copy_block(S + b, ldS, m, b, Ct, m, s));
+  HIPCHK(c, launch_trsm_rhs(L, rd, b, Ct, m, L21, 0, c->status, s, 1));             // L21 L_A^T = C^T
+  const MatView vL21{L21, m, 0, 0, 0}, vL21t{L21, m, 2, 0, 0};
+  HIPCHK(c, launch_gemm64(m, m, b, -1.0, vL21, vL21t, 1.0, S + b + ldS * b, ldS, Sc, m, s));   // D - L21 L21^T
+  double* Linv22 = Linv + b + ldo * b;
+  int rc = chol_inv_blocked(c, Sc, m, m, Linv22, ldo, next, s);
+  if (rc) return rc;
+  const MatView vGt{G, b, 2, 0, 0}, vT1{T1, m, 0, 0, 0}, vLi22{Linv22, ldo, 0, 0, 0};
+  HIPCHK(c, launch_gemm64(m, b, b, 1.0, vL21, vGt, 0.0, nullptr, 0, T1, m, s));                // L21 L_A^{-1}
+  HIPCHK(c, launch_gemm64(m, b, m, -1.0, vLi22, vT1, 0.0, nullptr, 0, Linv + b, ldo, s));      // -L_D^{-1} (.)
+  HIPCHK(c, launch_copy_block(nullptr, 0, b, m, Linv + ldo * b, ldo, s));                      // upper block 0
+  return TR_OK;
+}
+
+int64_t chol_inv_blocked_ws(int n) {
+  int64_t tot = 0;
+  while (true) {
+    const int64_t nb = std::min(n, 112);
+    tot += 4 * nb * nb + 256;
+    if (n <= 112) break;
+    const int64_t m = n - 112;
+    tot += 3 * m * 112 + m * m;
+    n = (int)m;
+  }
+  return tot;
+}
+
+int spd_inverse_blocked(tr_als_ctx* c, const double* S, int n, double* Sinv, double* ws, hipStream_t s) {
+  double* Linv = ws;
+  int rc = chol_inv_blocked(c, S, n, n, Linv, n, ws + (int64_t)n * n, s);
+  if (rc) return rc;
+  const MatView vLt{Linv, n, 2, 0, 0}, vL{Linv, n, 0, 0, 0};
+  HIPCHK(c, launch_gemm64(n, n, n, 1.0, vLt, vL, 0.0, nullptr, 0, Sinv, n, s));                // L^{-T} L^{-1}
+  return TR_OK;
+}
+
+int64_t spd_inverse_blocked_ws(int n) { return (int64_t)n * n + chol_inv_blocked_ws(n); }
+
 // Cut-off of the pseudo-inverse of S_n: the caller's rcond, else n * eps
 // (relative to the largest singular value of S_n, which squares those of
 // G^{!=n}_[2]).
@@ -804,8 +973,8 @@ int update_mode_ne(tr_als_ctx* c, int m, int prec, int refine, bool in_sweep) {
     } else if (spd_inverse_fits(n)) {
       HIPCHK(c, launch_spd_inverse(c->S, n, c->Sinv, c->status, s2));
     } else {
-      HIPCHK(c, launch_chol(c->S, n, c->Lf, c->LTf, c->cholw, c->status, s2));
-      HIPCHK(c, launch_chol_solve(c->Lf, c->LTf, n, nullptr, n, c->Sinv, 0, c->status, s2));
+      const int r2 = spd_inverse_blocked(c, c->S, n, c->Sinv, c->blkw, s2);
+      if (r2) return r2;
     }
     HIPCHK(c, hipEventRecord(c->ev_join, s2));
     // after the join: the next mode's prefix excludes this mode's core
@@ -946,8 +1115,8 @@ int update_mode_qrne(tr_als_ctx* c, int m, int prec, int refine) {
   } else if (spd_inverse_fits(n)) {
     HIPCHK(c, launch_spd_inverse(c->S, n, c->Sinv, c->status, s));
   } else {
-    HIPCHK(c, launch_chol(c->S, n, c->Lf, c->LTf, c->cholw, c->status, s));
-    HIPCHK(c, launch_chol_solve(c->Lf, c->LTf, n, nullptr, n, c->Sinv, 0, c->status, s));
+    rc = spd_inverse_blocked(c, c->S, n, c->Sinv, c->blkw, s);
+    if (rc) return rc;
   }
   int64_t Jp = 1;
   rc = build_v2(c, m, &Jp);
@@ -1146,6 +1315,7 @@ int trx_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ranks,
   A((void**)&c->LinvT, (size_t)maxRR * maxRR * 8);
   A((void**)&c->Sinv, (size_t)maxRR * maxRR * 8);
   A((void**)&c->pinvw, (size_t)2 * maxRR * maxRR * 8);
+  A((void**)&c->blkw, (size_t)spd_inverse_blocked_ws((int)maxRR) * 8);
   A((void**)&c->rdiag, 256 * 8);
   A((void**)&c->Tsol, (size_t)maxI * maxRR * 8);
   A((void**)&c->W0, (size_t)maxW * 8);
@@ -1176,6 +1346,11 @@ int trx_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ranks,
       } else {
         XsCfg x = xs_config(c, m, prec);
         pbytes = std::max(pbytes, partial_bytes_needed(x, prec));
+        if (c->plan[m].slab && prec != TR_FP8) {
+          const XslabArgs a = xslab_config(c, m, X);
+          pbytes = std::max(pbytes, xslab_partial_bytes(a, prec));
+          btb = std::max(btb, xslab_bt_bytes(a, prec));
+        }
       }
     }
   A(&c->partial, pbytes);
@@ -1760,7 +1935,7 @@ int tr_als_gram(tr_als_ctx* c, int k, double* Eout) {
 
 int tr_als_mode_regime(const tr_als_ctx* c, int n) {
   if (!c || c->N < 2 || n < 1 || n > c->N) return TR_EINVAL;
-  return c->plan[n - 1].regime;
+  return c->plan[n - 1].slab ? 3 : c->plan[n - 1].regime;
 }
 
 int tr_als_xnorm2(const tr_als_ctx* c, double* out) {

@@ -167,7 +167,12 @@ void check_range(const std::string& who, const Range& r) {
          r.what.c_str(), r.bytes, (size_t)(r.p - st), a->size, (size_t)(r.p + r.bytes - st - a->size));
 }
 
-std::string demangle(const char* m) {
+std::string demangle(const char* m0) {
+  // the host demangler does not know clang's mangling of __bf16 (DF16b):
+  // spell it as a vendor-extended type, which demangles to its name
+  std::string mm(m0);
+  for (size_t q; (q = mm.find("DF16b")) != std::string::npos;) mm.replace(q, 5, "u6__bf16");
+  const char* m = mm.c_str();
   int st = 0;
   char* d = abi::__cxa_demangle(m, nullptr, nullptr, &st);
   std::string s = (st == 0 && d) ? d : m;
@@ -178,9 +183,11 @@ std::string demangle(const char* m) {
 }
 
 // "ns::name<...>(T1, T2)" -> "name"
-std::string base_name(const std::string& full) {
+std::string base_name(const std::string& full) {   // template kernels demangle with a "void " prefix
   size_t end = full.find_first_of("<(");
   std::string s = full.substr(0, end);
+  const size_t sp = s.rfind(' ');
+  if (sp != std::string::npos) s = s.substr(sp + 1);
   const size_t c = s.rfind("::");
   return c == std::string::npos ? s : s.substr(c + 2);
 }
@@ -349,6 +356,42 @@ void check_extents(const std::string& full, const std::string& nm, void** a, std
     const size_t n = (size_t)(L(1) * L(2));
     r->push_back({D(0), n * es, "X"});
     r->push_back({D(4), n * (full.find("true>") != std::string::npos ? 1 : 2), "out"});
+  } else if (nm == "xslab_kernel" || nm == "xslab_reduce_kernel" || nm == "xslab_table_kernel") {
+    const XslabArgs x = arg<XslabArgs>(a, 0);
+    const bool f64 = full.find("<0") != std::string::npos || full.find("<double") != std::string::npos;
+    const size_t es = f64 ? 8 : (full.find("float") != std::string::npos ? 4 : 2);
+    const size_t pes = full.find("<0") != std::string::npos ? 8 : 4;   // partials of the FP64 path
+    const size_t parts = (size_t)x.nsplit * x.n_mt * x.n_g * 128 * x.OWg;
+    if (nm == "xslab_kernel") {
+      // X: the last element of the largest slab range the kernel walks
+      const size_t xes = full.find(", double") != std::string::npos ? 8 : full.find(", float") != std::string::npos ? 4 : 2;
+      const int64_t last = (x.In - 1) * x.sn + (x.Ik - 1) * x.sk + (x.Il - 1) * x.sl;
+      r->push_back({(uintptr_t)x.X, (size_t)(last + 1) * xes, "X"});
+      r->push_back({(uintptr_t)x.Bt, (size_t)x.n_g * x.TWg * x.ldb * (f64 ? 8 : es == 2 ? 4 : es), "table"});
+      r->push_back({(uintptr_t)x.partial, parts * (full.find("<0") != std::string::npos ? 8 : 4), "partial"});
+      r->push_back({(uintptr_t)x.Gl, (size_t)x.Rm * x.Il * x.Ro * 8, "absorbed core"});
+    } else if (nm == "xslab_reduce_kernel") {
+      r->push_back({(uintptr_t)x.partial, parts * pes, "partial"});
+      r->push_back({D(2), (size_t)(x.In * x.Rn * (x.caseB ? x.Ro : x.Rg) * 8), "M"});
+    } else {
+      r->push_back({D(2), (size_t)x.n_g * x.TWg * x.ldb * (es == 2 ? 4 : es), "table"});   // BF16: hi and lo
+      r->push_back({D(1), (size_t)x.Rm * x.Ik * x.Rg * 8, "core"});
+    }
+  } else if (nm == "copy_block_kernel") {   // (src, lds, rows, cols, dst, ldd, trans)
+    const int64_t rows = I(2), cols = I(3), lds_ = L(1), ldd = L(5);
+    if (D(0)) r->push_back({D(0), (size_t)((arg<int>(a, 6) ? lds_ * (rows - 1) + cols : lds_ * (cols - 1) + rows) * 8),
+                            "src"});
+    r->push_back({D(4), (size_t)((ldd * (cols - 1) + rows) * 8), "dst"});
+  } else if (nm == "chol_lds_kernel") {     // (S, n, L, LT, status, rdiag)
+    const size_t b = (size_t)(I(1) * I(1) * 8);
+    r->push_back({D(0), b, "S"});
+    r->push_back({D(2), b, "L"});
+    r->push_back({D(3), b, "LT"});
+  } else if (nm == "trsm_rhs_kernel") {     // (L, rdiag, n, Rhs, I, G, accumulate, status, mode)
+    const int64_t n = I(2), rows = L(4);
+    r->push_back({D(0), (size_t)(n * n * 8), "L"});
+    if (D(3)) r->push_back({D(3), (size_t)(rows * n * 8), "Rhs"});
+    r->push_back({D(5), (size_t)(rows * n * 8), "G"});
   } else if (nm == "philox_normal_kernel") {
     r->push_back({D(0), (size_t)L(1) * 8, "out"});
   } else if (nm == "tiny_als_kernel") {

@@ -62,12 +62,15 @@ def test_gram_and_coef(dims, ranks):
 @pytest.fixture
 def force_regime(request, monkeypatch):
     """Pin the MTTSP kernel: 1 = two-stage GEMM wherever a group exists,
-    2 = fused single pass, 0 = the cost rule."""
-    monkeypatch.setenv("TR_ALS_FORCE_REGIME", str(request.param))
+    2 = single pass (the slab kernel for order 3 with R_n R_{n+1} > 128, else
+    the fused kernel), 2f = the fused kernel, 0 = the cost rule."""
+    monkeypatch.setenv("TR_ALS_FORCE_REGIME", str(request.param)[0])
+    if request.param == "2f":   # the fused kernel also where the slab kernel would run (order 3, R_n R_{n+1} > 128)
+        monkeypatch.setenv("TR_ALS_NO_SLAB", "1")
     return request.param
 
 
-@pytest.mark.parametrize("force_regime", [0, 1, 2], indirect=True)
+@pytest.mark.parametrize("force_regime", [0, 1, 2, "2f"], indirect=True)
 @pytest.mark.parametrize("prec,xdt,tol", [("f64", np.float64, 1e-12), ("f32", np.float32, 1e-5),
                                           ("bf16", np.float32, 2e-2), ("fp8", np.float32, 1.5e-1)])
 @pytest.mark.parametrize("dims,ranks", SHAPES, ids=[str(s[0]) for s in SHAPES])
@@ -106,6 +109,28 @@ def test_update_f64_every_inverse_block_count(dims, ranks):
     got = cores_from_dev(dev, dims, ranks)
     for a, b in zip(got, ref):
         assert rel(a, b) <= 1e-10
+    ctx.close()
+
+
+# coefficient matrices larger than the one-workgroup inverse (R_n R_{n+1} > 128):
+# inverted by blocks through Schur complements (one and three levels)
+BLOCKED_SHAPES = [((30, 28, 26), (12, 11, 13)),   # n = 132, 143, 156
+                  ((24, 22, 20), (20, 20, 20))]   # n = 400, the rank-20 field workload's size
+
+
+@pytest.mark.parametrize("dims,ranks", BLOCKED_SHAPES, ids=[str(s[1]) for s in BLOCKED_SHAPES])
+def test_update_f64_blocked_inverse(dims, ranks):
+    say(f"[update f64, blocked inverse] dims={dims} ranks={ranks}")
+    X, init = _data(dims, ranks, 6)
+    ctx, dev = _ctx(to_dev_flat(X), init, dims, ranks)
+    ref = [np.array(c) for c in init]
+    for s in range(2):
+        ref, _ = O.tr_als(X, ref, 1)
+        ctx.sweep(1, "f64", refine=1)
+        got = cores_from_dev(dev, dims, ranks)
+        errs = [rel(a, b) for a, b in zip(got, ref)]
+        say(f"   sweep {s + 1}: max core rel err {max(errs):.2e}")
+        assert max(errs) <= 1e-9
     ctx.close()
 
 
