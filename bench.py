@@ -38,6 +38,11 @@ def main():
     ap.add_argument("--no-schedules", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-qr", action="store_true")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the legs on the other workloads (20^4 FP64, 40^5 conditioned, 512x512x256 field)")
+    ap.add_argument("--serving-full", action="store_true",
+                    help="serving leg on the full stream distribution: orders 3-5, modes 16-128, ranks 2-12, "
+                         "batch lanes on")
     ap.add_argument("--serving-jobs", type=int, default=400)
     ap.add_argument("--serving-only", action="store_true",
                     help="only run the serving stream and print its JSON (the bench runs it in a child process)")
@@ -50,7 +55,7 @@ def main():
         sys.exit(2)
 
     if args.serving_only:
-        print(json.dumps(serving_leg(args.serving_jobs)))
+        print(json.dumps(serving_leg(args.serving_jobs, args.serving_full)))
         return
     import torch
     if args.copy_probe:
@@ -108,7 +113,8 @@ def main():
 
     # ---- roofline of the X-stream kernel (HIP events on the library stream) --
     regimes = sorted({ctx.regime(n) for n in range(1, N + 1)})
-    kname = {1: "xgemm_kernel (two-stage X contraction, stage 1)", 2: "xstream_kernel (fused X contraction)"}
+    kname = {1: "xgemm_kernel (two-stage X contraction, stage 1)", 2: "xstream_kernel (fused X contraction)",
+             3: "xslab_kernel (slab X contraction, order 3)"}
     ctx.profile_enable(True)
     ctx.sweep(3, args.prec, refine=1)
     kms, nl, bpl = ctx.profile_read()
@@ -143,6 +149,14 @@ def main():
         ctx.sweep(5, "f32", refine=1)
         tb = time.perf_counter()
         extra["plain_f32_ms_per_sweep"] = round(1000 * (tb - ta) / 5, 4)
+        extra["plain_f32_roofline"] = kernel_roofline(ctx, "f32", w.numel, ranks[0] * ranks[1])
+        for p in ("f64", "fp8"):
+            ctx.sweep(1, p, refine=1)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            ctx.sweep(3, p, refine=1)
+            tb = time.perf_counter()
+            extra[f"{p}_path_ms_per_sweep"] = round(1000 * (tb - ta) / 3, 4)
         ctx.close()
         sched = {}
         for name, plan in (("mixed", [(args.prec, w.sweeps - 2), ("f32", 2)]), ("plain", [("f32", w.sweeps)])):
@@ -159,27 +173,32 @@ def main():
         sched["speedup_mixed_vs_plain"] = round(sched["plain"]["seconds"] / sched["mixed"]["seconds"], 3)
         extra["schedules_20_sweeps"] = sched
 
-    # ---- the QR-stabilised variant (Alg. 3) on the same workload ------------
+    # ---- the QR-based variants (Alg. 3 and Alg. 4) on the same workload -----
     if not args.no_qr:
-        try:
-            qr = {}
-            for p in ("f32", args.prec):
-                ctx, dev = fresh("qr")
-                ctx.sweep(1, p, refine=1)
-                torch.cuda.synchronize()
-                ta = time.perf_counter()
-                ctx.sweep(3, p, refine=1)
-                tb = time.perf_counter()
-                qr[f"{p}_ms_per_sweep"] = round(1000 * (tb - ta) / 3, 4)
-                qr[f"{p}_fit_after_4_sweeps"] = ctx.fit()
-                ctx.close()
-            extra["qr_variant"] = qr
-        except Exception as e:   # reported, never fatal to the bench line
-            extra["qr_variant"] = {"error": str(e)[:200]}
+        for variant in ("qr", "qrne"):
+            try:
+                qr = {}
+                for p in ("f32", args.prec):
+                    ctx, dev = fresh(variant)
+                    ctx.sweep(1, p, refine=1)
+                    torch.cuda.synchronize()
+                    ta = time.perf_counter()
+                    ctx.sweep(3, p, refine=1)
+                    tb = time.perf_counter()
+                    qr[f"{p}_ms_per_sweep"] = round(1000 * (tb - ta) / 3, 4)
+                    qr[f"{p}_fit_after_4_sweeps"] = ctx.fit()
+                    ctx.close()
+                extra[f"{variant}_variant"] = qr
+            except Exception as e:   # reported, never fatal to the bench line
+                extra[f"{variant}_variant"] = {"error": str(e)[:200]}
+
+    # ---- the other workloads ------------------------------------------------
+    if not args.no_configs:
+        extra["other_workloads"] = config_legs()
 
     # ---- serving: a Poisson stream of small jobs through the request loop ---
     if not args.no_serving and args.serving_jobs > 0:
-        extra["serving"] = serving_child(args.serving_jobs)
+        extra["serving"] = serving_child(args.serving_jobs, args.serving_full)
 
     # ---- CPU oracle on a bounded sample ------------------------------------
     cpu = None
@@ -196,7 +215,8 @@ def main():
         t_mode = tb - ta
         cpu = {"value": round(1.0 / (N * t_mode), 6), "unit": "sweeps/s", "cores": nthreads, "kind": "oracle",
                "sample": "one regular-ALS mode update (mode 1, explicit subchain + Householder QR) of the full "
-                         f"100^4 tensor in FP64 numpy/LAPACK, {t_mode:.2f} s, scaled x{N} to one sweep"}
+                         f"100^4 tensor in FP64 numpy/LAPACK, {t_mode:.2f} s, scaled x{N} to one sweep",
+               "cpu_model": cpu_model(), "blas": blas_name()}
 
     out = {
         "metric": "TR-ALS sweep time, % roofline, mixed vs plain at equal fit; p50/p99 latency",
@@ -223,6 +243,155 @@ def main():
     }
     out.update(extra)
     print(json.dumps(out))
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def blas_name():
+    try:
+        cfg = np.show_config(mode="dicts")["Build Dependencies"]["blas"]
+        return f"{cfg.get('name')} {cfg.get('version', '')}".strip()
+    except Exception:
+        return None
+
+
+def kernel_roofline(ctx, prec, numel, C, sweeps=2):
+    """Average duration (HIP events on the library stream) of the X-contraction
+    launches of `sweeps` sweeps in `prec`, with achieved GB/s and TFLOP/s against
+    the HBM and the precision's MFMA peak (algorithmic bytes = numel x bytes as
+    read; flops = 2 numel R_n R_{n+1})."""
+    ctx.profile_enable(True)
+    ctx.sweep(sweeps, prec, refine=1)
+    kms, nl, bpl = ctx.profile_read()
+    ctx.profile_enable(False)
+    t = (kms / max(nl, 1)) / 1000.0
+    gbs = numel * XBYTES[prec] / t / 1e9
+    tfl = 2.0 * numel * C / t / 1e12
+    hbm_time = numel * XBYTES[prec] / (HBM_PEAK_GBS * 1e9)
+    mfma_time = 2.0 * numel * C / (MFMA_PEAK_TFLOPS[prec] * 1e12)
+    bound = "hbm" if hbm_time >= mfma_time else "mfma"
+    return {"bound": bound, "avg_kernel_us": round(t * 1e6, 2), "launches": nl, "achieved_gbs": round(gbs, 1),
+            "achieved_tflops": round(tfl, 2),
+            "frac": round((hbm_time if bound == "hbm" else mfma_time) / t, 4),
+            "peak": HBM_PEAK_GBS if bound == "hbm" else MFMA_PEAK_TFLOPS[prec],
+            "unit": "GB/s" if bound == "hbm" else "TFLOP/s"}
+
+
+def config_legs():
+    """Sweep times (and rooflines of the X contraction) on the other workloads:
+    20^4 ranks 3 FP64 (all variants, FP64 path); the conditioned order-5 40^5
+    ranks (6,8,10,8,6) (NE / QR / QRNE, BF16 and FP8 mixed schedules of 18 + 2
+    FP32 finishing sweeps, final fits beside the all-FP32 schedule); the
+    512x512x256 sinusoid field at ranks 20 (FP32 vs 28 BF16 + 2 FP32).  Every
+    leg is reported, never fatal."""
+    import torch
+    import workloads as W
+    from paper_2210_11362_amd import TRContext
+
+    def dev_flat(a):
+        return torch.from_numpy(W.to_flat(np.asarray(a))).cuda()
+
+    def timed(ctx, k, p):
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        ctx.sweep(k, p, refine=1)
+        torch.cuda.synchronize()
+        return time.perf_counter() - ta
+
+    def leg(fn):
+        try:
+            return fn()
+        except Exception as e:
+            return {"error": str(e)[:240]}
+
+    out = {}
+    w1 = W.make_workload(1)
+    X1 = dev_flat(w1.X)
+
+    def cfg1():
+        r = {"workload": "20^4 FP64, Gaussian TR ranks 3 + 0.1% noise, fit ranks 3, FP64 path, 10 sweeps"}
+        for v in ("ne", "qr", "qrne"):
+            ctx = TRContext(X1, w1.dims, w1.ranks, [dev_flat(c) for c in w1.init_cores], variant=v)
+            ctx.sweep(1, "f64")
+            dt = timed(ctx, 10, "f64")
+            r[v] = {"ms_per_sweep": round(1000 * dt / 10, 4), "sweeps_per_s": round(10 / dt, 1), "fit": ctx.fit()}
+            ctx.close()
+        return r
+    out["cfg1_20x4_R3_f64"] = leg(cfg1)
+    del X1
+
+    w3 = W.make_workload(3)
+    X3 = dev_flat(w3.X)
+
+    def cfg3():
+        r = {"workload": "40^5 FP32, TR cores of condition 1e4, ranks (6,8,10,8,6), 1% noise; 20 sweeps"}
+        ctx = TRContext(X3, w3.dims, w3.ranks, [dev_flat(c) for c in w3.init_cores])
+        dt = timed(ctx, 20, "f32")
+        r["plain_f32"] = {"ms_per_sweep": round(1000 * dt / 20, 4), "fit": ctx.fit()}
+        ctx.close()
+        for v in ("ne", "qr", "qrne"):
+            for p in ("bf16", "fp8"):
+                def one():
+                    ctx = TRContext(X3, w3.dims, w3.ranks, [dev_flat(c) for c in w3.init_cores], variant=v)
+                    try:
+                        dt = timed(ctx, 18, p)
+                        dt2 = timed(ctx, 2, "f32")
+                        res = {"ms_per_mixed_sweep": round(1000 * dt / 18, 4), "seconds_20": round(dt + dt2, 4),
+                               "fit": ctx.fit()}
+                        res["fit_delta_vs_plain"] = abs(res["fit"] - r["plain_f32"]["fit"])
+                        if v == "ne":
+                            res["roofline"] = kernel_roofline(ctx, p, w3.numel, max(
+                                w3.ranks[k] * w3.ranks[(k + 1) % 5] for k in range(5)), sweeps=1)
+                        return res
+                    finally:
+                        ctx.close()
+                r[f"{v}_{p}"] = leg(one)
+        def pinv_fp8():
+            ctx = TRContext(X3, w3.dims, w3.ranks, [dev_flat(c) for c in w3.init_cores])
+            try:
+                ctx.set_solve("pinv")
+                dt = timed(ctx, 18, "fp8")
+                timed(ctx, 2, "f32")
+                f = ctx.fit()
+                return {"ms_per_mixed_sweep": round(1000 * dt / 18, 4), "fit": f,
+                        "fit_delta_vs_plain": abs(f - r["plain_f32"]["fit"])}
+            finally:
+                ctx.close()
+        r["ne_fp8_pinv_solve"] = leg(pinv_fp8)
+        return r
+    out["cfg3_40x5_cond1e4"] = leg(cfg3)
+    del X3
+
+    w4 = W.make_workload(4)
+    X4 = dev_flat(w4.X)
+
+    def cfg4():
+        r = {"workload": "512x512x256 FP32 sinusoid field (50 terms) + 2% noise, fit ranks 20, 30 sweeps, NE"}
+        for name, plan in (("mixed", [("bf16", 28), ("f32", 2)]), ("plain", [("f32", 30)])):
+            ctx = TRContext(X4, w4.dims, w4.ranks, [dev_flat(c) for c in w4.init_cores])
+            tot = 0.0
+            per = {}
+            for p, k in plan:
+                dt = timed(ctx, k, p)
+                tot += dt
+                per[p] = round(1000 * dt / k, 4)
+            r[name] = {"plan": [f"{k}x{p}" for p, k in plan], "seconds": round(tot, 4), "ms_per_sweep": per,
+                       "fit": ctx.fit()}
+            r[name]["roofline_" + plan[0][0]] = kernel_roofline(ctx, plan[0][0], w4.numel, 400, sweeps=1)
+            ctx.close()
+        r["fit_delta"] = abs(r["mixed"]["fit"] - r["plain"]["fit"])
+        r["speedup_mixed_vs_plain"] = round(r["plain"]["seconds"] / r["mixed"]["seconds"], 3)
+        return r
+    out["cfg4_512x512x256_R20"] = leg(cfg4)
+    return out
 
 
 def xgemm_source_sha():
@@ -253,42 +422,64 @@ def measured_traffic():
         return None
 
 
-def serving_child(njobs: int):
+def serving_child(njobs: int, full: bool = False):
     """The serving stream in a child process (its own device context): a failure
     there is reported in the bench line instead of ending the bench."""
     import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--serving-only", "--serving-jobs", str(njobs)]
+    if full:
+        cmd.append("--serving-full")
     try:
-        p = subprocess.run([sys.executable, os.path.abspath(__file__), "--serving-only", "--serving-jobs", str(njobs)],
-                           stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, timeout=300)
+        p = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, timeout=900)
     except subprocess.TimeoutExpired:
-        return {"error": "serving stream timed out after 300 s"}
+        return {"error": "serving stream timed out after 900 s"}
     lines = [l for l in p.stdout.splitlines() if l.startswith("{")]
     if p.returncode != 0 or not lines:
         return {"error": f"serving stream exited with status {p.returncode}", "stderr_tail": p.stderr[-400:]}
     return json.loads(lines[-1])
 
 
-def serving_leg(njobs: int):
+def serving_leg(njobs: int, full: bool = False):
     """Latency and throughput of the request loop on a Poisson stream (200 jobs/s)
-    of planted-TR jobs of order 3-4, mode sizes 16-48, ranks 2-8 (8 BF16 + 2 FP32
-    sweeps each), generated on the device; 8 slots, 16 GiB arena."""
+    of planted-TR jobs (8 BF16 + 2 FP32 sweeps each), generated on the device.
+    Default: orders 3-4, mode sizes 16-48, ranks 2-8, 8 slots, 16 GiB arena.
+    full: the whole distribution -- orders 3-5, mode sizes 16-128, ranks 2-12 --
+    with batch lanes on, 8 slots, 240 GiB arena."""
     import numpy as np
     import workloads as W
     from paper_2210_11362_amd import TRServer
-    jobs = W.serving_stream(njobs, orders=(3, 4), dim_range=(16, 48), rank_range=(2, 8))
-    srv = TRServer(16 << 30, 8)
-    ids = [srv.submit(j["dims"], j["ranks"], seed=j["seed"], eta=0.01, prec_mixed="bf16", nsweeps_mixed=8,
-                      prec_fin="f32", nsweeps_fin=2, t_arrival=0.05 + j["t_arrive"]) for j in jobs]
+    if full:
+        jobs = W.serving_stream(njobs)
+        srv = TRServer(240 << 30, 8, batch=True)
+        desc = f"{njobs} jobs, Poisson 200/s, order 3-5, dims 16-128, ranks 2-12, 8xbf16+2xf32 sweeps, lanes on"
+    else:
+        jobs = W.serving_stream(njobs, orders=(3, 4), dim_range=(16, 48), rank_range=(2, 8))
+        srv = TRServer(16 << 30, 8)
+        desc = f"{njobs} jobs, Poisson 200/s, order 3-4, dims 16-48, ranks 2-8, 8xbf16+2xf32 sweeps"
+    t_submit0 = time.perf_counter()
+    from paper_2210_11362_amd import TRError
+    ids, refused = [], 0
+    for j in jobs:
+        try:
+            ids.append(srv.submit(j["dims"], j["ranks"], seed=j["seed"], eta=0.01, prec_mixed="bf16",
+                                  nsweeps_mixed=8, prec_fin="f32", nsweeps_fin=2, t_arrival=0.05 + j["t_arrive"]))
+        except TRError:
+            refused += 1          # footprint larger than the whole arena
     srv.drain()
     infos = [srv.poll(i) for i in ids]
     st = srv.stats()
     srv.close()
-    lat = np.array([i["t_done"] - i["t_arrival"] for i in infos])
+    ok = [i for i in infos if i["state"] == 2]
+    lat = np.array([i["t_done"] - i["t_arrival"] for i in ok])
     span = max(i["t_done"] for i in infos) - min(i["t_arrival"] for i in infos)
-    return {"stream": f"{njobs} jobs, Poisson 200/s, order 3-4, dims 16-48, ranks 2-8, 8xbf16+2xf32 sweeps",
+    offered = njobs / max(1e-9, max(i["t_arrival"] for i in infos) - min(i["t_arrival"] for i in infos))
+    return {"stream": desc,
             "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
             "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
-            "jobs_per_s": round(njobs / span, 2), "failed": int(sum(i["state"] != 2 for i in infos)),
+            "jobs_per_s": round(len(ok) / span, 2), "offered_jobs_per_s": round(offered, 2),
+            "failed": int(len(infos) - len(ok)), "refused_at_submit": refused,
+            "batched": int(sum(bool(i["batched"]) for i in infos)),
+            "wall_s": round(time.perf_counter() - t_submit0, 2),
             "slots": st["slots"], "max_running": st["max_running"], "peak_hbm_bytes": st["peak_in_use"]}
 
 
