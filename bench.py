@@ -465,6 +465,16 @@ def serving_leg(njobs: int, full: bool = False):
                                   nsweeps_mixed=8, prec_fin="f32", nsweeps_fin=2, t_arrival=0.05 + j["t_arrive"]))
         except TRError:
             refused += 1          # footprint larger than the whole arena
+    # wait for the stream to finish, with a progress line every ~10 s
+    t_last = time.perf_counter()
+    while True:
+        st = srv.stats()
+        if st["done"] + st["failed"] >= len(ids):
+            break
+        time.sleep(0.05)
+        if time.perf_counter() - t_last > 10.0:
+            t_last = time.perf_counter()
+            print(f"serving: {st['done']} done, {st['failed']} failed of {len(ids)}", file=sys.stderr, flush=True)
     srv.drain()
     infos = [srv.poll(i) for i in ids]
     st = srv.stats()

@@ -291,22 +291,25 @@ constexpr int PST = 17;   // panel row stride in doubles (odd: spreads rows over
 // pivot met inside D is a Schur-complement diagonal, hence positive; one that
 // is not (S not positive definite in working precision) latches ST_SINGULAR.
 //
-// One workgroup of four waves.  The lower block triangle lives in registers
+// One workgroup of NW waves.  The lower block triangle lives in registers
 // as 16x16 FP64 MFMA accumulator tiles (lane l, element v holds row
-// (l >> 4) + 4v, column l & 15); wave W owns block rows W and NBT-1-W, fixed
-// at compile time so that each wave's update is straight-line MFMA code.  Per
+// (l >> 4) + 4v, column l & 15); with four waves wave W owns block rows W and
+// NBT-1-W, with eight waves block row W alone (used for eight block rows,
+// where the four-wave form spills heavily; at seven it spills a little and
+// still measures faster: 27 us against 33 us at n = 100), fixed at compile
+// time so that each wave's update is straight-line MFMA code.  Per
 // block step the owners publish block column k to LDS (one barrier); every
 // wave then sweeps D in its own registers (pivot column by DPP row broadcast,
 // pivot row by bpermute, no barrier) and applies the block update to its
 // tiles.  D^{-1} is symmetric, so the same registers serve as its A-operand
 // and B-operand fragments, and (-D^{-1}) A_kr computed in the accumulator
 // layout is already the A-operand of -A_rk D^{-1}.
-template <int NBT, int W>
+template <int NBT, int NW, int W>
 __device__ __forceinline__ void spd_block_inv_wave(const double* __restrict__ S, int n, double* __restrict__ Sinv,
                                                    int* status, double* panel, int lane) {
   constexpr int NP = 16 * NBT;
-  constexpr int ROW[2] = {W, NBT - 1 - W};
-  constexpr bool HAS[2] = {W < NBT, NBT - 1 - W > W};
+  constexpr int ROW[2] = {W, NW == 4 ? NBT - 1 - W : NBT};
+  constexpr bool HAS[2] = {W < NBT, NW == 4 && NBT - 1 - W > W};
   constexpr int MAXR = HAS[1] ? ROW[1] : HAS[0] ? ROW[0] : -1;   // highest block row owned
   const int g = lane >> 4, c16 = lane & 15;
   f64x4 t[2][NBT];
@@ -456,17 +459,21 @@ __device__ __forceinline__ void spd_block_inv_wave(const double* __restrict__ S,
   });
 }
 
-template <int NBT>
-__global__ __launch_bounds__(256) void spd_block_inv_kernel(const double* __restrict__ S, int n,
-                                                            double* __restrict__ Sinv, int* status) {
+template <int NBT, int NW>
+__global__ __launch_bounds__(NW * 64) void spd_block_inv_kernel(const double* __restrict__ S, int n,
+                                                                double* __restrict__ Sinv, int* status) {
   __shared__ double panel[2 * 16 * NBT * PST];
   if (*status != 0) return;
   const int lane = threadIdx.x & 63;
   switch (__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6))) {   // wave index, uniform per wave
-    case 0: spd_block_inv_wave<NBT, 0>(S, n, Sinv, status, panel, lane); break;
-    case 1: spd_block_inv_wave<NBT, 1>(S, n, Sinv, status, panel, lane); break;
-    case 2: spd_block_inv_wave<NBT, 2>(S, n, Sinv, status, panel, lane); break;
-    default: spd_block_inv_wave<NBT, 3>(S, n, Sinv, status, panel, lane); break;
+    case 0: spd_block_inv_wave<NBT, NW, 0>(S, n, Sinv, status, panel, lane); break;
+    case 1: spd_block_inv_wave<NBT, NW, 1>(S, n, Sinv, status, panel, lane); break;
+    case 2: spd_block_inv_wave<NBT, NW, 2>(S, n, Sinv, status, panel, lane); break;
+    case 3: spd_block_inv_wave<NBT, NW, 3>(S, n, Sinv, status, panel, lane); break;
+    case 4: if constexpr (NW == 8) spd_block_inv_wave<NBT, NW, 4>(S, n, Sinv, status, panel, lane); break;
+    case 5: if constexpr (NW == 8) spd_block_inv_wave<NBT, NW, 5>(S, n, Sinv, status, panel, lane); break;
+    case 6: if constexpr (NW == 8) spd_block_inv_wave<NBT, NW, 6>(S, n, Sinv, status, panel, lane); break;
+    default: if constexpr (NW == 8) spd_block_inv_wave<NBT, NW, 7>(S, n, Sinv, status, panel, lane); break;
   }
 }
 
@@ -515,18 +522,17 @@ hipError_t launch_copy_block(const double* src, int64_t ld_src, int rows, int co
   return hipGetLastError();
 }
 
-// n <= 112 (seven 16-wide pivot blocks): the eight-block instance spills its
-// registers (1.4 ms at n = 128 against 30 us at n = 100); larger matrices go
-// through the blocked inverse built on this one
-bool spd_inverse_fits(int n) { return n >= 1 && n <= 112; }
+// n <= 128 (eight 16-wide pivot blocks); larger matrices go through the
+// blocked inverse built on the LDS Cholesky
+bool spd_inverse_fits(int n) { return n >= 1 && n <= 128; }
 
 hipError_t launch_spd_inverse(const double* S, int n, double* Sinv, int* status, hipStream_t s) {
   const int nbt = (n + 15) / 16;
   switch (nbt) {
-#define SPD_INV_CASE(B) \
-  case B: hipLaunchKernelGGL(spd_block_inv_kernel<B>, dim3(1), dim3(256), 0, s, S, n, Sinv, status); break;
-    SPD_INV_CASE(1) SPD_INV_CASE(2) SPD_INV_CASE(3) SPD_INV_CASE(4)
-    SPD_INV_CASE(5) SPD_INV_CASE(6) SPD_INV_CASE(7) SPD_INV_CASE(8)
+#define SPD_INV_CASE(B, NW) \
+  case B: hipLaunchKernelGGL((spd_block_inv_kernel<B, NW>), dim3(1), dim3(NW * 64), 0, s, S, n, Sinv, status); break;
+    SPD_INV_CASE(1, 4) SPD_INV_CASE(2, 4) SPD_INV_CASE(3, 4) SPD_INV_CASE(4, 4)
+    SPD_INV_CASE(5, 4) SPD_INV_CASE(6, 4) SPD_INV_CASE(7, 4) SPD_INV_CASE(8, 8)
 #undef SPD_INV_CASE
     default: return hipErrorInvalidValue;
   }
