@@ -70,8 +70,10 @@ enum {
  *   cores    host array of N device pointers to FP64 cores in the layout above.
  *            Read here; overwritten in place at the end of each successful
  *            tr_als_sweep (stream order).  Caller-owned.
- *   variant  TR_NE, TR_QR or TR_QRNE.  TR_QR and TR_QRNE need
- *            R_n R_{n+1} <= 128 for every n (TR_EINVAL otherwise).
+ *   variant  TR_NE, TR_QR or TR_QRNE.  For TR_QR and TR_QRNE, modes with
+ *            R_n R_{n+1} > 128 factor V_n[2] by a blocked Cholesky-QR and
+ *            run its large FP64 products through rocBLAS (the context holds a
+ *            rocBLAS handle, created at the first such update).
  *   hip_stream  hipStream_t for all work of this context.
  * Allocates all workspace (freed by tr_als_destroy), computes ||X||_F^2 and the
  * per-core Grams (NE), core QRs (QR) or both, the Grams of the R-cores
@@ -100,7 +102,8 @@ int tr_als_sweep(tr_als_ctx* ctx, int nsweeps, int contraction_prec, int refine_
 /*
  * tr_als_set_solve -- how the mode update solves its least-squares problem.
  *   TR_SOLVE_FACTOR (the default): TR_NE / TR_QRNE invert S_n<2> (SPD inverse,
- *     or Cholesky for R_n R_{n+1} > 128), TR_QR substitutes with R_[2] (Alg. 3);
+ *     or a blocked Cholesky for R_n R_{n+1} > 128), TR_QR substitutes with
+ *     R_[2] (Alg. 3);
  *     a singular or indefinite S_n / R_[2] stops the sweep with TR_ESINGULAR.
  *   TR_SOLVE_PINV: the rank-deficient-safe solve (the remark after Alg. 3):
  *     S_n<2>^+ by a one-sided Jacobi SVD in FP64, singular values of S_n at or

@@ -25,6 +25,10 @@ FLAGS = [
 ]
 
 
+# rocBLAS: the plain FP64 products of the QR-based variants at R_n R_{n+1} > 128
+LINK = ["-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocblas"]
+
+
 def _run(cmd):
     p = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     out = "\n".join(l for l in p.stdout.splitlines() if "packed-fp32-ops" not in l)
@@ -49,7 +53,7 @@ def build(verbose: bool = False) -> str:
     if bad:
         raise RuntimeError("hipcc failed for: " + ", ".join(f for f, _ in bad))
     tmp = LIB + ".tmp"
-    rc, out = _run([HIPCC, "--offload-arch=gfx950", "-shared", "-o", tmp, *[j[2] for j in jobs]])
+    rc, out = _run([HIPCC, "--offload-arch=gfx950", "-shared", "-o", tmp, *[j[2] for j in jobs], *LINK])
     if rc != 0:
         print(out, file=sys.stderr)
         raise RuntimeError("link failed")

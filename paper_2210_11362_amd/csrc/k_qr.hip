@@ -940,6 +940,12 @@ hipError_t launch_ttm(const void* in, int in_type, int64_t L, int64_t I, int64_t
   return hipGetLastError();
 }
 
+hipError_t launch_sum_chunks(const double* part, int nchunk, int64_t n, double* C, hipStream_t s) {
+  if (nchunk < 1 || n < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(sum_chunks_kernel, dim3((unsigned)cdiv(n, 64)), dim3(256), 0, s, part, nchunk, n, C);
+  return hipGetLastError();
+}
+
 hipError_t launch_transpose(const double* A, int64_t rows, int64_t cols, double* At, hipStream_t s) {
   hipLaunchKernelGGL(transpose_kernel, dim3(cdiv(rows * cols, 256)), dim3(256), 0, s, A, rows, cols, At);
   return hipGetLastError();

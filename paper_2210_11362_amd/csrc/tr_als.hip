@@ -11,6 +11,8 @@
 #include <string>
 #include <vector>
 
+#include <rocblas/rocblas.h>
+
 #include "common.h"
 #include "runtime.h"
 
@@ -74,6 +76,13 @@ struct tr_als_ctx {
   double *qG = nullptr, *qL[3] = {nullptr, nullptr, nullptr}, *qLT = nullptr, *qRi = nullptr, *qLp = nullptr,
          *qLt = nullptr, *qshift = nullptr, *qpart = nullptr;
   int64_t qpart_elems = 0;
+  // R_n R_{n+1} > 128 (QR-based variants): the large plain FP64 products
+  // (Gram of V_n[2], the triangular passes of the Cholesky-QR, Y_[n] Q_0 and
+  // the substitution with R_[2]) go through rocBLAS; qWpart holds the per-slice
+  // products of Y_[n] Q_0 for a middle mode n
+  rocblas_handle blas = nullptr;
+  double* qWpart = nullptr;
+  int64_t qWpart_elems = 0;
   // captured sweeps, one per (precision, refinement steps)
   hipGraphExec_t graphs[4][5] = {{nullptr}};
   std::string graph_note;   // why the last sweep capture was abandoned (empty if none)
@@ -991,6 +1000,73 @@ int update_mode_ne(tr_als_ctx* c, int m, int prec, int refine, bool in_sweep) {
   return TR_OK;
 }
 
+// rocBLAS on the context's stream (handle created at the first use).
+int blas_on(tr_als_ctx* c, hipStream_t s) {
+  if (!c->blas && rocblas_create_handle(&c->blas) != rocblas_status_success) {
+    c->blas = nullptr;
+    return fail(c, TR_EHIP, "rocblas_create_handle failed");
+  }
+  if (rocblas_set_stream(c->blas, s) != rocblas_status_success) return fail(c, TR_EHIP, "rocblas_set_stream failed");
+  return TR_OK;
+}
+
+#define BLASCHK(c, x)                                                                              \
+  do {                                                                                             \
+    const rocblas_status st_ = (x);                                                                \
+    if (st_ != rocblas_status_success)                                                             \
+      return fail(c, TR_EHIP, std::string("rocBLAS: ") + rocblas_status_to_string(st_) + " in " #x); \
+  } while (0)
+
+// Lower Cholesky factor L (n x n, ld n, strict upper triangle zero) of the SPD
+// matrix whose lower triangle is in G (ld n), right-looking by 112-column
+// blocks: LDS factor of the diagonal block, triangular solve for the panel
+// below it, symmetric rank-k update of the trailing matrix.  A non-positive
+// pivot latches ST_SINGULAR.  ws holds 3 * 112^2 doubles.
+int chol_lower_blocked(tr_als_ctx* c, const double* G, int n, double* L, double* ws, hipStream_t s) {
+  constexpr int b = 112;
+  const double one = 1.0, mone = -1.0;
+  HIPCHK(c, launch_copy_block(G, n, n, n, L, n, s));
+  for (int j = 0; j < n; j += b) {
+    const int nb = std::min(b, n - j), m = n - j - nb;
+    double* Ajj = L + j + (int64_t)n * j;
+    HIPCHK(c, launch_copy_block(Ajj, n, nb, nb, ws, nb, s));
+    HIPCHK(c, launch_chol_lds(ws, nb, ws + b * b, ws + 2 * b * b, c->rdiag, c->status, s));
+    HIPCHK(c, launch_copy_block(ws + b * b, nb, nb, nb, Ajj, n, s));
+    if (j > 0) HIPCHK(c, launch_copy_block(nullptr, 0, j, nb, L + (int64_t)n * j, n, s));   // above the block
+    if (m > 0) {
+      BLASCHK(c, rocblas_dtrsm(c->blas, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
+                               rocblas_diagonal_non_unit, m, nb, &one, Ajj, n, Ajj + nb, n));
+      BLASCHK(c, rocblas_dsyrk(c->blas, rocblas_fill_lower, rocblas_operation_none, m, nb, &mone, Ajj + nb, n, &one,
+                               Ajj + nb + (int64_t)n * nb, n));
+    }
+  }
+  return TR_OK;
+}
+
+// W = Y_[n] B (I_n x Q) for the Multi-TTM result Y with extents cd (mode n of
+// size I_n between L = prod cd[0..n) and T = prod cd(n..N)) and B (L T x Q,
+// rows in Y's order, ld ldb): one GEMM when n is the first or last mode, else
+// one product per slice t of the slowest modes, summed in slice order.
+int blas_mode_product(tr_als_ctx* c, const double* Y, const int64_t* cd, int m, const double* B, int64_t ldb, int Q,
+                      double* W, hipStream_t s) {
+  const int64_t L = prod(cd, 0, m), I = c->dims[m], T = prod(cd, m + 1, c->N);
+  const double one = 1.0, zero = 0.0;
+  if (T == 1) {
+    BLASCHK(c, rocblas_dgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, (int)I, Q, (int)L, &one, Y,
+                             (int)L, B, (int)ldb, &zero, W, (int)I));
+  } else if (L == 1) {
+    BLASCHK(c, rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, (int)I, Q, (int)T, &one, Y,
+                             (int)I, B, (int)ldb, &zero, W, (int)I));
+  } else {
+    if (T * I * Q > c->qWpart_elems) return fail(c, TR_EHIP, "internal: slice-product buffer too small");
+    BLASCHK(c, rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none, (int)I, Q,
+                                             (int)L, &one, Y, (int)L, L * I, B, (int)ldb, L, &zero, c->qWpart, (int)I,
+                                             I * Q, (int)T));
+    HIPCHK(c, launch_sum_chunks(c->qWpart, (int)T, I * Q, W, s));
+  }
+  return TR_OK;
+}
+
 // Mode-2 QR of core k (Definition of the mode-n QR): Q_k and the R-core.
 int qr_core(tr_als_ctx* c, int k) {
   hipStream_t s = c->stream;
@@ -1056,6 +1132,48 @@ int build_v2(tr_als_ctx* c, int m, int64_t* Jp_out) {
 // V_n[2] = Q_0 R_[2] by shifted Cholesky-QR (three passes); Y = X x_{j!=n} Q_j^T
 // (most-compressing mode first); W_n = Y_[n] Q_0; G_n(2) R_[2]^T = W_n by
 // substitution; commit; re-factor core n.
+// The same update for n = R_n R_{n+1} > 128, its large products on rocBLAS:
+// the shifted Cholesky-QR passes A <- A L^{-T} as in-place triangular solves
+// with the blocked Cholesky factor, W_n = Y_[n] Q_0, and G_n(2) = W_n R^{-T}.
+int update_mode_qr_large(tr_als_ctx* c, int m, int prec, int64_t Jp) {
+  hipStream_t s = c->stream;
+  const int N = c->N;
+  const int Ra = c->R[m], Rb = c->R[m + 1], n = Ra * Rb;
+  const double one = 1.0, zero = 0.0;
+  int rc = blas_on(c, s);
+  if (rc) return rc;
+  double* A = c->qV2;   // V_n[2], orthogonalised in place into Q_0
+  for (int it = 0; it < 3; ++it) {
+    BLASCHK(c, rocblas_dsyrk(c->blas, rocblas_fill_lower, rocblas_operation_transpose, n, (int)Jp, &one, A, (int)Jp,
+                             &zero, c->qG, n));
+    if (it == 0) HIPCHK(c, launch_shift_and_add(c->qG, n, Jp, c->qshift, s));
+    rc = chol_lower_blocked(c, c->qG, n, c->qL[it], c->qLT, s);
+    if (rc) return rc;
+    BLASCHK(c, rocblas_dtrsm(c->blas, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
+                             rocblas_diagonal_non_unit, (int)Jp, n, &one, c->qL[it], n, A, (int)Jp));
+  }
+  {
+    MatView L1{c->qL[0], n, 0, 0, 0}, L2{c->qL[1], n, 0, 0, 0}, L3{c->qL[2], n, 0, 0, 0}, Lp{c->qLp, n, 0, 0, 0};
+    HIPCHK(c, launch_gemm64(n, n, n, 1.0, L1, L2, 0.0, nullptr, 0, c->qLp, n, s));
+    HIPCHK(c, launch_gemm64(n, n, n, 1.0, Lp, L3, 0.0, nullptr, 0, c->qLt, n, s));
+  }
+  int64_t cd[TR_MAXN];
+  const double* Y = nullptr;
+  rc = multi_ttm_y(c, m, prec, &Y, cd);
+  if (rc) return rc;
+  rc = blas_on(c, s);
+  if (rc) return rc;
+  rc = blas_mode_product(c, Y, cd, m, A, Jp, n, c->qW, s);
+  if (rc) return rc;
+  const int64_t I = c->dims[m];
+  // G_n(2) R_[2]^T = W_n with R_[2]^T = L_1 L_2 L_3 (lower): G L = W
+  HIPCHK(c, hipMemcpyAsync(c->Gn, c->qW, (size_t)I * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  BLASCHK(c, rocblas_dtrsm(c->blas, rocblas_side_right, rocblas_fill_lower, rocblas_operation_none,
+                           rocblas_diagonal_non_unit, (int)I, n, &one, c->qLt, n, c->Gn, (int)I));
+  HIPCHK(c, launch_commit_core(c->Gn, I, Ra, Rb, c->cores[m], c->status, s));
+  return qr_core(c, m);
+}
+
 int update_mode_qr(tr_als_ctx* c, int m, int prec) {
   hipStream_t s = c->stream;
   const int N = c->N;
@@ -1064,6 +1182,7 @@ int update_mode_qr(tr_als_ctx* c, int m, int prec) {
   int64_t Jp = 1;
   int rc = build_v2(c, m, &Jp);
   if (rc) return rc;
+  if (n > 128) return update_mode_qr_large(c, m, prec, Jp);
   // shifted Cholesky-QR: three passes A <- A L^{-T}, R^T = L1 L2 L3
   double* A = c->qV2;
   double* bufs[2] = {c->qQa, c->qQb};
@@ -1126,8 +1245,15 @@ int update_mode_qrne(tr_als_ctx* c, int m, int prec, int refine) {
   rc = multi_ttm_y(c, m, prec, &Y, cd);
   if (rc) return rc;
   // M_n = Y_[n] V_n[2] (I_n x n)
-  HIPCHK(c, launch_tall_atb(Y, 0, c->qV2, Jp, Jp, (int)c->dims[m], n, 1, prod(cd, 0, m), c->dims[m],
-                            prod(cd, m + 1, N), c->qpart, c->qpart_elems, c->M, s));
+  if (n > 128) {
+    rc = blas_on(c, s);
+    if (rc) return rc;
+    rc = blas_mode_product(c, Y, cd, m, c->qV2, Jp, n, c->M, s);
+    if (rc) return rc;
+  } else {
+    HIPCHK(c, launch_tall_atb(Y, 0, c->qV2, Jp, Jp, (int)c->dims[m], n, 1, prod(cd, 0, m), c->dims[m],
+                              prod(cd, m + 1, N), c->qpart, c->qpart_elems, c->M, s));
+  }
   HIPCHK(c, launch_ne_apply(c->M, c->dims[m], n, c->S, c->Sinv, refine, c->Gn, c->status, s));
   HIPCHK(c, launch_commit_core(c->Gn, c->dims[m], Ra, Rb, c->cores[m], c->status, s));
   rc = qr_core(c, m);
@@ -1207,6 +1333,7 @@ int tr_als_destroy(tr_als_ctx* ctx) {
   if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
   if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
   if (ctx->canary) check_guards(ctx);
+  if (ctx->blas) (void)rocblas_destroy_handle(ctx->blas);
   for (void* p : ctx->allocs) (void)hipFree(p);
   delete ctx;
   return TR_OK;
@@ -1358,7 +1485,7 @@ int trx_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ranks,
   A(&c->Bt, btb);
   c->bt_bytes = btb;
   if (variant == TR_QR || variant == TR_QRNE) {
-    int64_t maxJ = 1, maxTT = 1, maxHn = 1;
+    int64_t maxJ = 1, maxTT = 1, maxHn = 1, nq = 128, wpart = 0;
     for (int k = 0; k < N; ++k) c->qr_r[k] = std::min<int64_t>(dims[k], (int64_t)c->R[k] * c->R[k + 1]);
     for (int m = 0; m < N; ++m) {
       int64_t Jp = 1, tb = 1;
@@ -1367,10 +1494,16 @@ int trx_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ranks,
         Jp *= c->qr_r[j];
         tb = std::max(tb, Jp * c->R[(m + 1) % N] * c->R[j + 1]);
       }
-      maxJ = std::max(maxJ, Jp * c->R[m] * c->R[m + 1]);
+      const int64_t n = (int64_t)c->R[m] * c->R[m + 1];
+      maxJ = std::max(maxJ, Jp * n);
       maxTT = std::max(maxTT, tb);
-      maxHn = std::max(maxHn, (int64_t)dims[m] * c->R[m] * c->R[m + 1]);
-      if (c->R[m] * c->R[m + 1] > 128) rc = fail(c, TR_EINVAL, "QR and QRNE variants need R_n R_{n+1} <= 128");
+      maxHn = std::max(maxHn, (int64_t)dims[m] * n);
+      nq = std::max(nq, n);
+      if (n > 128 && m > 0 && m < N - 1) {   // slice products of Y_[n] Q_0 for a middle mode
+        int64_t T = 1;
+        for (int j = m + 1; j < N; ++j) T *= c->qr_r[j];
+        wpart = std::max(wpart, T * dims[m] * n);
+      }
     }
     maxTT = std::max(maxTT, maxJ);
     for (int k = 0; k < N; ++k) {
@@ -1387,14 +1520,18 @@ int trx_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ranks,
     A((void**)&c->qQb, (size_t)maxJ * 8);
     A((void**)&c->qY0, (size_t)std::max(numel, maxTT) * 8);
     A((void**)&c->qY1, (size_t)std::max(numel, maxTT) * 8);
-    A((void**)&c->qW, (size_t)maxI * 128 * 8);
-    for (int it = 0; it < 3; ++it) A((void**)&c->qL[it], 128 * 128 * 8);
-    A((void**)&c->qG, 128 * 128 * 8);
-    A((void**)&c->qLT, 128 * 128 * 8);
-    A((void**)&c->qRi, 128 * 128 * 8);
-    A((void**)&c->qLp, 128 * 128 * 8);
-    A((void**)&c->qLt, 128 * 128 * 8);
+    A((void**)&c->qW, (size_t)maxI * nq * 8);
+    for (int it = 0; it < 3; ++it) A((void**)&c->qL[it], (size_t)nq * nq * 8);
+    A((void**)&c->qG, (size_t)nq * nq * 8);
+    A((void**)&c->qLT, (size_t)std::max<int64_t>(nq * nq, 3 * 112 * 112) * 8);
+    A((void**)&c->qRi, (size_t)nq * nq * 8);
+    A((void**)&c->qLp, (size_t)nq * nq * 8);
+    A((void**)&c->qLt, (size_t)nq * nq * 8);
     A((void**)&c->qshift, 64);
+    if (wpart > 0) {
+      A((void**)&c->qWpart, (size_t)wpart * 8);
+      c->qWpart_elems = wpart;
+    }
     c->qpart_elems = (int64_t)512 * 128 * 128;
     A((void**)&c->qpart, (size_t)c->qpart_elems * 8);
     if (rc) { tr_als_destroy(c); return rc; }

@@ -796,3 +796,82 @@ void* fakehip_device_alloc(size_t bytes) {
 void fakehip_device_free(void* p) { (void)hipFree(p); }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// rocBLAS calls of the library (QR-based variants, R_n R_{n+1} > 128): the
+// operand extents are checked like a kernel's, the call is counted as a launch
+// under its own name, and none may be issued on a stream under capture
+// ---------------------------------------------------------------------------
+#include <rocblas/rocblas.h>
+
+namespace {
+struct FakeBlas { hipStream_t s = nullptr; };
+
+size_t mat_bytes(int64_t rows, int64_t cols, int64_t ld) {
+  if (rows <= 0 || cols <= 0) return 0;
+  if (ld < rows) viol("rocBLAS: leading dimension %lld below %lld rows", (long long)ld, (long long)rows);
+  return (size_t)(ld * (cols - 1) + rows) * sizeof(double);
+}
+
+void blas_call(rocblas_handle h, const char* nm, std::initializer_list<Range> rs) {
+  touch();
+  g_launches[nm]++;
+  FakeBlas* b = reinterpret_cast<FakeBlas*>(h);
+  if (capture_of(b->s)) viol("%s on a stream under capture", nm);
+  for (const Range& r : rs) check_range(nm, r);
+}
+}  // namespace
+
+extern "C" {
+rocblas_status rocblas_create_handle(rocblas_handle* h) {
+  *h = reinterpret_cast<rocblas_handle>(new FakeBlas());
+  return rocblas_status_success;
+}
+rocblas_status rocblas_destroy_handle(rocblas_handle h) {
+  delete reinterpret_cast<FakeBlas*>(h);
+  return rocblas_status_success;
+}
+rocblas_status rocblas_set_stream(rocblas_handle h, hipStream_t s) {
+  reinterpret_cast<FakeBlas*>(h)->s = s;
+  return rocblas_status_success;
+}
+const char* rocblas_status_to_string(rocblas_status) { return "stand-in"; }
+
+rocblas_status rocblas_dsyrk(rocblas_handle h, rocblas_fill, rocblas_operation t, rocblas_int n, rocblas_int k,
+                             const double*, const double* A, rocblas_int lda, const double*, double* C,
+                             rocblas_int ldc) {
+  const bool tr = t != rocblas_operation_none;
+  blas_call(h, "rocblas_dsyrk", {{(uintptr_t)A, tr ? mat_bytes(k, n, lda) : mat_bytes(n, k, lda), "A"},
+                                 {(uintptr_t)C, mat_bytes(n, n, ldc), "C"}});
+  return rocblas_status_success;
+}
+rocblas_status rocblas_dtrsm(rocblas_handle h, rocblas_side side, rocblas_fill, rocblas_operation, rocblas_diagonal,
+                             rocblas_int m, rocblas_int n, const double*, const double* A, rocblas_int lda, double* B,
+                             rocblas_int ldb) {
+  const int64_t k = side == rocblas_side_right ? n : m;
+  blas_call(h, "rocblas_dtrsm", {{(uintptr_t)A, mat_bytes(k, k, lda), "A"}, {(uintptr_t)B, mat_bytes(m, n, ldb), "B"}});
+  return rocblas_status_success;
+}
+rocblas_status rocblas_dgemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, rocblas_int m,
+                             rocblas_int n, rocblas_int k, const double*, const double* A, rocblas_int lda,
+                             const double* B, rocblas_int ldb, const double*, double* C, rocblas_int ldc) {
+  const bool a_t = ta != rocblas_operation_none, b_t = tb != rocblas_operation_none;
+  blas_call(h, "rocblas_dgemm", {{(uintptr_t)A, a_t ? mat_bytes(k, m, lda) : mat_bytes(m, k, lda), "A"},
+                                 {(uintptr_t)B, b_t ? mat_bytes(n, k, ldb) : mat_bytes(k, n, ldb), "B"},
+                                 {(uintptr_t)C, mat_bytes(m, n, ldc), "C"}});
+  return rocblas_status_success;
+}
+rocblas_status rocblas_dgemm_strided_batched(rocblas_handle h, rocblas_operation ta, rocblas_operation tb,
+                                             rocblas_int m, rocblas_int n, rocblas_int k, const double*,
+                                             const double* A, rocblas_int lda, rocblas_stride sa, const double* B,
+                                             rocblas_int ldb, rocblas_stride sb, const double*, double* C,
+                                             rocblas_int ldc, rocblas_stride sc, rocblas_int batch) {
+  const bool a_t = ta != rocblas_operation_none, b_t = tb != rocblas_operation_none;
+  const size_t last = batch > 0 ? (size_t)(batch - 1) : 0;
+  blas_call(h, "rocblas_dgemm_strided_batched",
+            {{(uintptr_t)A, last * sa * 8 + (a_t ? mat_bytes(k, m, lda) : mat_bytes(m, k, lda)), "A"},
+             {(uintptr_t)B, last * sb * 8 + (b_t ? mat_bytes(n, k, ldb) : mat_bytes(k, n, ldb)), "B"},
+             {(uintptr_t)C, last * sc * 8 + mat_bytes(m, n, ldc), "C"}});
+  return rocblas_status_success;
+}
+}  // extern "C"

@@ -150,3 +150,21 @@ def test_full_size_mode1_contraction_and_ring(cfg):
     say(f"   first update rel err {e1:.2e}")
     assert e1 <= 1e-2
     ctx.close()
+
+
+def test_full_size_field_mode1_qr_update():
+    """512 x 512 x 256, ranks 20 (R_n R_{n+1} = 400): the first Alg. 3 update of
+    mode 1 on the FP64 path (blocked Cholesky-QR of the 102400 x 400 V_1[2],
+    Multi-TTM of X, W_1 = Y_[1] Q_0) against the oracle's least-squares update."""
+    w = W.make_workload(4)
+    say(f"[full size, qr] {w.name}")
+    Xd = w.X.astype(np.float64)
+    ctx, dev = _ctx(w.X, w.init_cores, w.dims, w.ranks, variant="qr")
+    ctx.update_mode(1, "f64")
+    ctx.store_cores()
+    G1 = cores_from_dev(dev, w.dims, w.ranks)[0]
+    ctx.close()
+    G1o, _ = O.als_update(Xd, w.init_cores, 1, "qr")
+    e1 = rel(G1, G1o)
+    say(f"   mode-1 update rel err {e1:.2e}")
+    assert e1 <= 1e-8

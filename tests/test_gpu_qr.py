@@ -40,6 +40,33 @@ def _data(dims, ranks, seed, dtype=np.float64):
     return np.asfortranarray(X.astype(dtype)), init
 
 
+# R_n R_{n+1} > 128: the Cholesky-QR factor blocked, the large FP64 products
+# (Gram of V_n[2], the triangular passes, Y_[n] Q_0 or Y_[n] V_n[2], the
+# substitution with R_[2]) on rocBLAS
+LARGE_QR_SHAPES = [
+    ((24, 22, 20), (20, 20, 20)),          # n = 400, every core factor square (I_k < 400)
+    ((40, 36, 30), (12, 11, 13)),          # n = 132, 143, 156; the middle mode sums slice products
+    ((30, 28, 26, 12), (12, 12, 11, 2)),   # order 4: n = 144, 132 beside n = 22, 24
+]
+
+
+@pytest.mark.parametrize("variant", ["qr", "qrne"])
+@pytest.mark.parametrize("dims,ranks", LARGE_QR_SHAPES, ids=[str(s[1]) for s in LARGE_QR_SHAPES])
+def test_qr_variants_large_bond_products_f64(dims, ranks, variant):
+    say(f"[{variant} f64, large n] dims={dims} ranks={ranks}")
+    X, init = _data(dims, ranks, 17)
+    ctx, dev = _ctx(to_dev_flat(X), init, dims, ranks, variant)
+    ref = [np.array(c) for c in init]
+    for s in range(2):
+        ref, _ = O.tr_als(X, ref, 1)
+        ctx.sweep(1, "f64")
+        got = cores_from_dev(dev, dims, ranks)
+        errs = [rel(a, b) for a, b in zip(got, ref)]
+        say(f"   sweep {s + 1}: max core rel err {max(errs):.2e}")
+        assert max(errs) <= 1e-10
+    ctx.close()
+
+
 @pytest.mark.parametrize("variant", ["qr", "qrne"])
 @pytest.mark.parametrize("dims,ranks", QR_SHAPES, ids=[str(s[0]) for s in QR_SHAPES])
 def test_qr_variant_per_sweep_f64(dims, ranks, variant):

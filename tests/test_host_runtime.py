@@ -12,7 +12,7 @@ import pytest
 
 from tests.hostrt import replay as R
 from tests.test_gpu_parity import INV_SHAPES, SHAPES
-from tests.test_gpu_qr import QR_SHAPES
+from tests.test_gpu_qr import LARGE_QR_SHAPES, QR_SHAPES
 from tests.test_gpu_serving import LANE_JOBS, _mix_jobs
 
 GB = 1 << 30
@@ -48,6 +48,22 @@ def test_qr_contexts_stay_inside_their_buffers(host, dims, ranks, variant):
     codes = R.run_context(host, dims, ranks, variant=variant, precs=("f64", "bf16"), xdt="f64")
     assert all(rc == 0 for _, rc in codes), codes
     _clean(host, f"{variant} {dims} {ranks}")
+
+
+@pytest.mark.parametrize("variant", ["qr", "qrne"])
+@pytest.mark.parametrize("dims,ranks", LARGE_QR_SHAPES, ids=[f"{d}-{r}" for d, r in LARGE_QR_SHAPES])
+def test_qr_large_bond_products_host_side(host, dims, ranks, variant):
+    """R_n R_{n+1} > 128: every rocBLAS operand inside its buffer, none issued
+    on a stream under capture, the slice products of a middle mode in bounds."""
+    host.reset()
+    codes = R.run_context(host, dims, ranks, variant=variant, precs=("f64", "f32", "bf16"), xdt="f32")
+    assert all(rc == 0 for _, rc in codes), codes
+    _clean(host, f"{variant} {dims} {ranks}")
+    calls = {k: host.L.fakehip_launches(k.encode()) for k in ("rocblas_dsyrk", "rocblas_dtrsm", "rocblas_dgemm",
+                                                              "rocblas_dgemm_strided_batched")}
+    assert calls["rocblas_dgemm"] + calls["rocblas_dgemm_strided_batched"] > 0, calls
+    if variant == "qr":
+        assert calls["rocblas_dsyrk"] > 0 and calls["rocblas_dtrsm"] > 0, calls
 
 
 def test_ring_intermediates_exceed_one_gram_when_ranks_alternate(host):
