@@ -155,7 +155,13 @@ hipError_t launch_trsm_rhs(const double* L, const double* rdiag, int n, const do
 // QR variant
 hipError_t launch_householder_qr(double* A, int64_t m, int n, double* V, double* tau, double* Q, double* R,
                                  hipStream_t s);
+// out[e] = (double)x[e], e < n.
+hipError_t launch_widen_f32(const float* x, int64_t n, double* out, hipStream_t s);
 // C[e] = sum over the nchunk partials part[c * n + e] (fixed summation order).
+// C[e] = sum over the nchunk partials part[c * n + e] (fixed summation order).
+hipError_t launch_sum_chunks(const double* part, int nchunk, int64_t n, double* C, hipStream_t s);
+// out[i + I*(l + L*t)] = in[l + L*(i + I*t)] (each L x I slice transposed).
+hipError_t launch_slice_transpose(const double* in, int64_t L, int64_t I, int64_t T, double* out, hipStream_t s);
 hipError_t launch_sum_chunks(const double* part, int nchunk, int64_t n, double* C, hipStream_t s);
 hipError_t launch_tall_atb(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t K, int P, int Q,
                            int mode, int64_t L, int64_t Ip, int64_t T, double* part, int64_t part_elems, double* C,

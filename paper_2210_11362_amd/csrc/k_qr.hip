@@ -633,6 +633,32 @@ __global__ __launch_bounds__(256) void ttm_rb_kernel(const Tin* in, int64_t L, i
   }
 }
 
+// out[i + I*(l + L*t)] = in[l + L*(i + I*t)]: every slice t (an L x I matrix)
+// transposed, through a 32 x 32 LDS tile.
+__global__ __launch_bounds__(256) void slice_transpose_kernel(const double* in, int64_t L, int64_t I, int64_t T,
+                                                              double* out) {
+  __shared__ double tile[32][33];
+  const int64_t nl = (L + 31) / 32;
+  const int64_t l0 = (blockIdx.x % nl) * 32, i0 = (blockIdx.x / nl) * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+  for (int64_t t = blockIdx.y; t < T; t += gridDim.y) {
+    const double* src = in + L * I * t;
+    double* dst = out + L * I * t;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int64_t l = l0 + tx, i = i0 + ty + 8 * k;
+      if (l < L && i < I) tile[ty + 8 * k][tx] = src[l + L * i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int64_t i = i0 + tx, l = l0 + ty + 8 * k;
+      if (l < L && i < I) dst[i + I * l] = tile[tx][ty + 8 * k];
+    }
+    __syncthreads();
+  }
+}
+
 __global__ void transpose_kernel(const double* A, int64_t rows, int64_t cols, double* At) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= rows * cols) return;
@@ -943,6 +969,14 @@ hipError_t launch_ttm(const void* in, int in_type, int64_t L, int64_t I, int64_t
 hipError_t launch_sum_chunks(const double* part, int nchunk, int64_t n, double* C, hipStream_t s) {
   if (nchunk < 1 || n < 1) return hipErrorInvalidValue;
   hipLaunchKernelGGL(sum_chunks_kernel, dim3((unsigned)cdiv(n, 64)), dim3(256), 0, s, part, nchunk, n, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_slice_transpose(const double* in, int64_t L, int64_t I, int64_t T, double* out, hipStream_t s) {
+  const int64_t tiles = cdiv(L, 32) * cdiv(I, 32);
+  if (L < 1 || I < 1 || T < 1 || tiles > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(slice_transpose_kernel, dim3((unsigned)tiles, (unsigned)std::min<int64_t>(T, 65535)), dim3(256), 0,
+                     s, in, L, I, T, out);
   return hipGetLastError();
 }
 

@@ -724,6 +724,18 @@ hipError_t launch_chain_step(const double* T, int64_t J, int Rl, int Rm, const d
   return hipGetLastError();
 }
 
+namespace {
+__global__ void widen_f32_kernel(const float* x, int64_t n, double* out) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = (double)x[e];
+}
+}  // namespace
+
+hipError_t launch_widen_f32(const float* x, int64_t n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(widen_f32_kernel, dim3((unsigned)std::min<int64_t>(cdiv(n, 256), 65536)), dim3(256), 0, s, x, n, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_core_unfold(const double* core, int Ra, int64_t I, int Rb, double* out, hipStream_t s) {
   const int64_t n = (int64_t)Ra * I * Rb;
   hipLaunchKernelGGL(core_unfold_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, core, Ra, I, Rb, out);

@@ -78,11 +78,8 @@ struct tr_als_ctx {
   int64_t qpart_elems = 0;
   // R_n R_{n+1} > 128 (QR-based variants): the large plain FP64 products
   // (Gram of V_n[2], the triangular passes of the Cholesky-QR, Y_[n] Q_0 and
-  // the substitution with R_[2]) go through rocBLAS; qWpart holds the per-slice
-  // products of Y_[n] Q_0 for a middle mode n
+  // the substitution with R_[2]) go through rocBLAS
   rocblas_handle blas = nullptr;
-  double* qWpart = nullptr;
-  int64_t qWpart_elems = 0;
   // captured sweeps, one per (precision, refinement steps)
   hipGraphExec_t graphs[4][5] = {{nullptr}};
   std::string graph_note;   // why the last sweep capture was abandoned (empty if none)
@@ -1020,7 +1017,8 @@ int blas_on(tr_als_ctx* c, hipStream_t s) {
 // Lower Cholesky factor L (n x n, ld n, strict upper triangle zero) of the SPD
 // matrix whose lower triangle is in G (ld n), right-looking by 112-column
 // blocks: LDS factor of the diagonal block, triangular solve for the panel
-// below it, symmetric rank-k update of the trailing matrix.  A non-positive
+// below it, rank-k update of the trailing matrix (both triangles; only the
+// lower one is read later).  A non-positive
 // pivot latches ST_SINGULAR.  ws holds 3 * 112^2 doubles.
 int chol_lower_blocked(tr_als_ctx* c, const double* G, int n, double* L, double* ws, hipStream_t s) {
   constexpr int b = 112;
@@ -1036,44 +1034,83 @@ int chol_lower_blocked(tr_als_ctx* c, const double* G, int n, double* L, double*
     if (m > 0) {
       BLASCHK(c, rocblas_dtrsm(c->blas, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
                                rocblas_diagonal_non_unit, m, nb, &one, Ajj, n, Ajj + nb, n));
-      BLASCHK(c, rocblas_dsyrk(c->blas, rocblas_fill_lower, rocblas_operation_none, m, nb, &mone, Ajj + nb, n, &one,
-                               Ajj + nb + (int64_t)n * nb, n));
+      BLASCHK(c, rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_transpose, m, m, nb, &mone, Ajj + nb,
+                               n, Ajj + nb, n, &one, Ajj + nb + (int64_t)n * nb, n));
     }
   }
   return TR_OK;
 }
 
-// W = Y_[n] B (I_n x Q) for the Multi-TTM result Y with extents cd (mode n of
-// size I_n between L = prod cd[0..n) and T = prod cd(n..N)) and B (L T x Q,
-// rows in Y's order, ld ldb): one GEMM when n is the first or last mode, else
-// one product per slice t of the slowest modes, summed in slice order.
-int blas_mode_product(tr_als_ctx* c, const double* Y, const int64_t* cd, int m, const double* B, int64_t ldb, int Q,
-                      double* W, hipStream_t s) {
-  const int64_t L = prod(cd, 0, m), I = c->dims[m], T = prod(cd, m + 1, c->N);
+// C (P x Q) = op(A) B over a long inner dimension K, split into chunks whose
+// products (one strided-batched rocBLAS call, plus one for the remainder) are
+// summed in chunk order: rocBLAS runs such reduction-shaped products (small
+// C, K up to 10^6) as one long serial sweep otherwise.  trans_a: A is K x P
+// (ld lda), C = A^T B; else A is P x K (ld lda), C = A B.  B is K x Q (ld ldb).
+int blas_long_product(tr_als_ctx* c, bool trans_a, const double* A, int64_t lda, const double* B, int64_t ldb,
+                      int64_t K, int P, int Q, double* C, hipStream_t s) {
+  const int64_t pq = (int64_t)P * Q;
+  int64_t nch = std::min<int64_t>({64, c->qpart_elems / pq - 1, std::max<int64_t>(1, K / 256)});
+  if (nch < 1) return fail(c, TR_EHIP, "internal: chunk buffer too small");
+  const int64_t kc = K / nch, rem = K - nch * kc;
   const double one = 1.0, zero = 0.0;
-  if (T == 1) {
-    BLASCHK(c, rocblas_dgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, (int)I, Q, (int)L, &one, Y,
-                             (int)L, B, (int)ldb, &zero, W, (int)I));
-  } else if (L == 1) {
-    BLASCHK(c, rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, (int)I, Q, (int)T, &one, Y,
-                             (int)I, B, (int)ldb, &zero, W, (int)I));
-  } else {
-    if (T * I * Q > c->qWpart_elems) return fail(c, TR_EHIP, "internal: slice-product buffer too small");
-    BLASCHK(c, rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none, (int)I, Q,
-                                             (int)L, &one, Y, (int)L, L * I, B, (int)ldb, L, &zero, c->qWpart, (int)I,
-                                             I * Q, (int)T));
-    HIPCHK(c, launch_sum_chunks(c->qWpart, (int)T, I * Q, W, s));
-  }
+  const rocblas_operation ta = trans_a ? rocblas_operation_transpose : rocblas_operation_none;
+  const int64_t sa = trans_a ? kc : kc * lda;   // start of chunk q of A: row q kc (A^T) or column q kc
+  BLASCHK(c, rocblas_dgemm_strided_batched(c->blas, ta, rocblas_operation_none, P, Q, (int)kc, &one, A, (int)lda, sa, B,
+                                           (int)ldb, kc, &zero, c->qpart, P, pq, (int)nch));
+  if (rem > 0)
+    BLASCHK(c, rocblas_dgemm(c->blas, ta, rocblas_operation_none, P, Q, (int)rem, &one, A + nch * sa, (int)lda,
+                             B + nch * kc, (int)ldb, &zero, c->qpart + nch * pq, P));
+  HIPCHK(c, launch_sum_chunks(c->qpart, (int)(nch + (rem > 0 ? 1 : 0)), pq, C, s));
   return TR_OK;
 }
 
+// W = Y_[n] B (I_n x Q) for the Multi-TTM result Y with extents cd (mode n of
+// size I_n between L = prod cd[0..n) and T = prod cd(n..N)) and B (L T x Q,
+// rows in Y's order, ld ldb).  For a middle mode the slices of Y are
+// transposed first into tmp (L I T doubles), so that Y_[n] is I_n x (L T).
+int blas_mode_product(tr_als_ctx* c, const double* Y, const int64_t* cd, int m, const double* B, int64_t ldb, int Q,
+                      double* W, double* tmp, hipStream_t s) {
+  const int64_t L = prod(cd, 0, m), I = c->dims[m], T = prod(cd, m + 1, c->N);
+  if (T == 1) return blas_long_product(c, true, Y, L, B, ldb, L, (int)I, Q, W, s);
+  if (L > 1) {
+    HIPCHK(c, launch_slice_transpose(Y, L, I, T, tmp, s));
+    Y = tmp;
+  }
+  return blas_long_product(c, false, Y, I, B, ldb, L * T, (int)I, Q, W, s);
+}
+
 // Mode-2 QR of core k (Definition of the mode-n QR): Q_k and the R-core.
+// A tall unfolding with more than 128 columns (I_k >= R_k R_{k+1} > 128) is
+// factored by the shifted Cholesky-QR (three passes, as for V_n[2]) on
+// rocBLAS: Q_k = A L_1^{-T} L_2^{-T} L_3^{-T}, R = (L_1 L_2 L_3)^T.  The
+// factors can differ from Householder's by the signs of matching columns of Q
+// and rows of R, which leaves every product Q_k R the same.
 int qr_core(tr_als_ctx* c, int k) {
   hipStream_t s = c->stream;
   const int Ra = c->R[k], Rb = c->R[k + 1], n = Ra * Rb;
   const int64_t I = c->dims[k], r = c->qr_r[k];
   HIPCHK(c, launch_core_unfold(c->cores[k], Ra, I, Rb, c->qA, s));
-  HIPCHK(c, launch_householder_qr(c->qA, I, n, c->qV, c->qtau, c->qQ[k], c->qRt, s));
+  if (n > 128 && I >= n) {
+    int rc = blas_on(c, s);
+    if (rc) return rc;
+    const double one = 1.0;
+    for (int it = 0; it < 3; ++it) {
+      rc = blas_long_product(c, true, c->qA, I, c->qA, I, I, n, n, c->qG, s);
+      if (rc) return rc;
+      if (it == 0) HIPCHK(c, launch_shift_and_add(c->qG, n, I, c->qshift, s));
+      rc = chol_lower_blocked(c, c->qG, n, c->qL[it], c->qLT, s);
+      if (rc) return rc;
+      BLASCHK(c, rocblas_dtrsm(c->blas, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
+                               rocblas_diagonal_non_unit, (int)I, n, &one, c->qL[it], n, c->qA, (int)I));
+    }
+    MatView L1{c->qL[0], n, 0, 0, 0}, L2{c->qL[1], n, 0, 0, 0}, L3{c->qL[2], n, 0, 0, 0}, Lp{c->qLp, n, 0, 0, 0};
+    HIPCHK(c, launch_gemm64(n, n, n, 1.0, L1, L2, 0.0, nullptr, 0, c->qLp, n, s));
+    HIPCHK(c, launch_gemm64(n, n, n, 1.0, Lp, L3, 0.0, nullptr, 0, c->qLt, n, s));
+    HIPCHK(c, hipMemcpyAsync(c->qQ[k], c->qA, (size_t)I * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, launch_transpose(c->qLt, n, n, c->qRt, s));
+  } else {
+    HIPCHK(c, launch_householder_qr(c->qA, I, n, c->qV, c->qtau, c->qQ[k], c->qRt, s));
+  }
   HIPCHK(c, launch_core_fold(c->qRt, r, Ra, Rb, c->qR[k], s));
   return TR_OK;
 }
@@ -1095,12 +1132,39 @@ int multi_ttm_y(tr_als_ctx* c, int m, int prec, const double** Y, int64_t* cd) {
   if (rc) return rc;
   const void* cur = prec == TR_BF16 ? c->xbf16 : prec == TR_FP8 ? c->xfp8 : c->X;
   int ctype = (prec == TR_BF16 || prec == TR_FP8) ? prec : c->xdt;
+  if (prec == TR_F64 && ctype == TR_F32 && !order.empty()) {
+    // a large first mode product on the FP64 path: X widened to FP64 once (into
+    // the second ping-pong buffer, free until the second product) for rocBLAS
+    const int j = order[0];
+    if (c->dims[j] > 112 || c->qr_r[j] > 112) {
+      HIPCHK(c, launch_widen_f32((const float*)c->X, c->numel, c->qY1, s));
+      cur = c->qY1;
+      ctype = TR_F64;
+    }
+  }
   double scale = prec == TR_FP8 ? 1.0 / (double)c->fp8_scale : 1.0;
   double* ybuf[2] = {c->qY0, c->qY1};
   int yi = 0;
   for (int j : order) {
     const int64_t L = prod(cd, 0, j), T = prod(cd, j + 1, N);
-    HIPCHK(c, launch_ttm(cur, ctype, L, c->dims[j], T, c->qQ[j], (int)c->qr_r[j], scale, ybuf[yi], s));
+    const int64_t I = c->dims[j], R = c->qr_r[j];
+    if (ctype == TR_F64 && scale == 1.0 && (I > 112 || R > 112)) {
+      // out(l, r, t) = sum_i in(l + L (i + I t)) Q(i, r): Q^T in_[j] per slice t
+      int rc = blas_on(c, s);
+      if (rc) return rc;
+      const double one = 1.0, zero = 0.0;
+      const double* in = (const double*)cur;
+      if (L == 1) {
+        BLASCHK(c, rocblas_dgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, (int)R, (int)T, (int)I,
+                                 &one, c->qQ[j], (int)I, in, (int)I, &zero, ybuf[yi], (int)R));
+      } else {
+        BLASCHK(c, rocblas_dgemm_strided_batched(c->blas, rocblas_operation_none, rocblas_operation_none, (int)L,
+                                                 (int)R, (int)I, &one, in, (int)L, L * I, c->qQ[j], (int)I, 0, &zero,
+                                                 ybuf[yi], (int)L, L * R, (int)T));
+      }
+    } else {
+      HIPCHK(c, launch_ttm(cur, ctype, L, I, T, c->qQ[j], (int)R, scale, ybuf[yi], s));
+    }
     cd[j] = c->qr_r[j];
     cur = ybuf[yi];
     yi ^= 1;
@@ -1133,8 +1197,10 @@ int build_v2(tr_als_ctx* c, int m, int64_t* Jp_out) {
 // (most-compressing mode first); W_n = Y_[n] Q_0; G_n(2) R_[2]^T = W_n by
 // substitution; commit; re-factor core n.
 // The same update for n = R_n R_{n+1} > 128, its large products on rocBLAS:
-// the shifted Cholesky-QR passes A <- A L^{-T} as in-place triangular solves
-// with the blocked Cholesky factor, W_n = Y_[n] Q_0, and G_n(2) = W_n R^{-T}.
+// the Grams split over chunks of rows, the shifted Cholesky-QR passes
+// A <- A L^{-T} as in-place triangular solves with the blocked Cholesky factor
+// (the third applied to W_n instead of V_n[2]), W_n = Y_[n] Q_0, and
+// G_n(2) = W_n R^{-T}.
 int update_mode_qr_large(tr_als_ctx* c, int m, int prec, int64_t Jp) {
   hipStream_t s = c->stream;
   const int N = c->N;
@@ -1142,15 +1208,16 @@ int update_mode_qr_large(tr_als_ctx* c, int m, int prec, int64_t Jp) {
   const double one = 1.0, zero = 0.0;
   int rc = blas_on(c, s);
   if (rc) return rc;
-  double* A = c->qV2;   // V_n[2], orthogonalised in place into Q_0
+  double* A = c->qV2;   // V_n[2], orthogonalised in place (two passes; Q_0 = A L_3^{-T})
   for (int it = 0; it < 3; ++it) {
-    BLASCHK(c, rocblas_dsyrk(c->blas, rocblas_fill_lower, rocblas_operation_transpose, n, (int)Jp, &one, A, (int)Jp,
-                             &zero, c->qG, n));
+    rc = blas_long_product(c, true, A, Jp, A, Jp, Jp, n, n, c->qG, s);
+    if (rc) return rc;
     if (it == 0) HIPCHK(c, launch_shift_and_add(c->qG, n, Jp, c->qshift, s));
     rc = chol_lower_blocked(c, c->qG, n, c->qL[it], c->qLT, s);
     if (rc) return rc;
-    BLASCHK(c, rocblas_dtrsm(c->blas, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
-                             rocblas_diagonal_non_unit, (int)Jp, n, &one, c->qL[it], n, A, (int)Jp));
+    if (it < 2)
+      BLASCHK(c, rocblas_dtrsm(c->blas, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
+                               rocblas_diagonal_non_unit, (int)Jp, n, &one, c->qL[it], n, A, (int)Jp));
   }
   {
     MatView L1{c->qL[0], n, 0, 0, 0}, L2{c->qL[1], n, 0, 0, 0}, L3{c->qL[2], n, 0, 0, 0}, Lp{c->qLp, n, 0, 0, 0};
@@ -1163,9 +1230,12 @@ int update_mode_qr_large(tr_als_ctx* c, int m, int prec, int64_t Jp) {
   if (rc) return rc;
   rc = blas_on(c, s);
   if (rc) return rc;
-  rc = blas_mode_product(c, Y, cd, m, A, Jp, n, c->qW, s);
+  // W_n = Y_[n] Q_0 = (Y_[n] A) L_3^{-T}
+  rc = blas_mode_product(c, Y, cd, m, A, Jp, n, c->qW, Y == c->qY0 ? c->qY1 : c->qY0, s);
   if (rc) return rc;
   const int64_t I = c->dims[m];
+  BLASCHK(c, rocblas_dtrsm(c->blas, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
+                           rocblas_diagonal_non_unit, (int)I, n, &one, c->qL[2], n, c->qW, (int)I));
   // G_n(2) R_[2]^T = W_n with R_[2]^T = L_1 L_2 L_3 (lower): G L = W
   HIPCHK(c, hipMemcpyAsync(c->Gn, c->qW, (size_t)I * n * sizeof(double), hipMemcpyDeviceToDevice, s));
   BLASCHK(c, rocblas_dtrsm(c->blas, rocblas_side_right, rocblas_fill_lower, rocblas_operation_none,
@@ -1183,13 +1253,15 @@ int update_mode_qr(tr_als_ctx* c, int m, int prec) {
   int rc = build_v2(c, m, &Jp);
   if (rc) return rc;
   if (n > 128) return update_mode_qr_large(c, m, prec, Jp);
-  // shifted Cholesky-QR: three passes A <- A L^{-T}, R^T = L1 L2 L3
+  // shifted Cholesky-QR: passes A <- A L^{-T}, R^T = L1 L2 L3; the first two
+  // are applied to V_n[2], the third to W_n
   double* A = c->qV2;
   double* bufs[2] = {c->qQa, c->qQb};
   for (int it = 0; it < 3; ++it) {
     HIPCHK(c, launch_tall_atb(A, Jp, A, Jp, Jp, n, n, 0, 1, 1, 1, c->qpart, c->qpart_elems, c->qG, s));
     if (it == 0) HIPCHK(c, launch_shift_and_add(c->qG, n, Jp, c->qshift, s));
     HIPCHK(c, launch_chol_lds(c->qG, n, c->qL[it], c->qLT, c->rdiag, c->status, s));
+    if (it == 2) break;   // Q_0 = A L_3^{-T} is applied to W_n instead
     HIPCHK(c, launch_trsm_rhs(c->qL[it], c->rdiag, n, nullptr, n, c->qRi, 0, c->status, s, 1));
     if (n <= 112) {
       HIPCHK(c, launch_tall_gemm(A, Jp, Jp, n, c->qRi, n, n, bufs[it & 1], Jp, s));
@@ -1204,14 +1276,14 @@ int update_mode_qr(tr_als_ctx* c, int m, int prec) {
     HIPCHK(c, launch_gemm64(n, n, n, 1.0, L1, L2, 0.0, nullptr, 0, c->qLp, n, s));
     HIPCHK(c, launch_gemm64(n, n, n, 1.0, Lp, L3, 0.0, nullptr, 0, c->qLt, n, s));
   }
-  const double* Q0 = A;
   int64_t cd[TR_MAXN];
   const double* Y = nullptr;
   rc = multi_ttm_y(c, m, prec, &Y, cd);
   if (rc) return rc;
-  // W_n = Y_[n] Q_0 (I_n x n)
-  HIPCHK(c, launch_tall_atb(Y, 0, Q0, Jp, Jp, (int)c->dims[m], n, 1, prod(cd, 0, m), c->dims[m],
-                            prod(cd, m + 1, N), c->qpart, c->qpart_elems, c->qW, s));
+  // W_n = Y_[n] Q_0 = (Y_[n] A) L_3^{-T} (I_n x n), Y_[n] A staged in M
+  HIPCHK(c, launch_tall_atb(Y, 0, A, Jp, Jp, (int)c->dims[m], n, 1, prod(cd, 0, m), c->dims[m],
+                            prod(cd, m + 1, N), c->qpart, c->qpart_elems, c->M, s));
+  HIPCHK(c, launch_trsm_rhs(c->qL[2], c->rdiag, n, c->M, c->dims[m], c->qW, 0, c->status, s, 1));
   // G_n(2) = W_n R^{-T}: backward substitution with L = R^T
   HIPCHK(c, launch_trsm_rhs(c->qLt, nullptr, n, c->qW, c->dims[m], c->Gn, 0, c->status, s, 2));
   HIPCHK(c, launch_commit_core(c->Gn, c->dims[m], Ra, Rb, c->cores[m], c->status, s));
@@ -1248,7 +1320,7 @@ int update_mode_qrne(tr_als_ctx* c, int m, int prec, int refine) {
   if (n > 128) {
     rc = blas_on(c, s);
     if (rc) return rc;
-    rc = blas_mode_product(c, Y, cd, m, c->qV2, Jp, n, c->M, s);
+    rc = blas_mode_product(c, Y, cd, m, c->qV2, Jp, n, c->M, Y == c->qY0 ? c->qY1 : c->qY0, s);
     if (rc) return rc;
   } else {
     HIPCHK(c, launch_tall_atb(Y, 0, c->qV2, Jp, Jp, (int)c->dims[m], n, 1, prod(cd, 0, m), c->dims[m],
@@ -1485,7 +1557,7 @@ int trx_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ranks,
   A(&c->Bt, btb);
   c->bt_bytes = btb;
   if (variant == TR_QR || variant == TR_QRNE) {
-    int64_t maxJ = 1, maxTT = 1, maxHn = 1, nq = 128, wpart = 0;
+    int64_t maxJ = 1, maxTT = 1, maxHn = 1, nq = 128;
     for (int k = 0; k < N; ++k) c->qr_r[k] = std::min<int64_t>(dims[k], (int64_t)c->R[k] * c->R[k + 1]);
     for (int m = 0; m < N; ++m) {
       int64_t Jp = 1, tb = 1;
@@ -1499,11 +1571,6 @@ int trx_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ranks,
       maxTT = std::max(maxTT, tb);
       maxHn = std::max(maxHn, (int64_t)dims[m] * n);
       nq = std::max(nq, n);
-      if (n > 128 && m > 0 && m < N - 1) {   // slice products of Y_[n] Q_0 for a middle mode
-        int64_t T = 1;
-        for (int j = m + 1; j < N; ++j) T *= c->qr_r[j];
-        wpart = std::max(wpart, T * dims[m] * n);
-      }
     }
     maxTT = std::max(maxTT, maxJ);
     for (int k = 0; k < N; ++k) {
@@ -1528,10 +1595,6 @@ int trx_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ranks,
     A((void**)&c->qLp, (size_t)nq * nq * 8);
     A((void**)&c->qLt, (size_t)nq * nq * 8);
     A((void**)&c->qshift, 64);
-    if (wpart > 0) {
-      A((void**)&c->qWpart, (size_t)wpart * 8);
-      c->qWpart_elems = wpart;
-    }
     c->qpart_elems = (int64_t)512 * 128 * 128;
     A((void**)&c->qpart, (size_t)c->qpart_elems * 8);
     if (rc) { tr_als_destroy(c); return rc; }

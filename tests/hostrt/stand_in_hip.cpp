@@ -314,6 +314,16 @@ void check_extents(const std::string& full, const std::string& nm, void** a, std
     r->push_back({D(4), (size_t)(n * n * 8), "Sinv"});
     r->push_back({D(6), (size_t)(L(1) * n * 8), "G"});
     r->push_back({D(7), 4, "status"});
+  } else if (nm == "widen_f32_kernel") {   // (x, n, out)
+    r->push_back({D(0), (size_t)(L(1) * 4), "x"});
+    r->push_back({D(2), (size_t)(L(1) * 8), "out"});
+  } else if (nm == "transpose_kernel") {   // (A, rows, cols, At)
+    r->push_back({D(0), (size_t)(L(1) * L(2) * 8), "A"});
+    r->push_back({D(3), (size_t)(L(1) * L(2) * 8), "At"});
+  } else if (nm == "slice_transpose_kernel") {   // (in, L, I, T, out)
+    const size_t b = (size_t)(L(1) * L(2) * L(3) * 8);
+    r->push_back({D(0), b, "in"});
+    r->push_back({D(4), b, "out"});
   } else if (nm == "spd_block_inv_kernel") {   // (S, n, Sinv, status)
     const int64_t n = I(1);
     r->push_back({D(0), (size_t)(n * n * 8), "S"});

@@ -47,6 +47,7 @@ LARGE_QR_SHAPES = [
     ((24, 22, 20), (20, 20, 20)),          # n = 400, every core factor square (I_k < 400)
     ((40, 36, 30), (12, 11, 13)),          # n = 132, 143, 156; the middle mode sums slice products
     ((30, 28, 26, 12), (12, 12, 11, 2)),   # order 4: n = 144, 132 beside n = 22, 24
+    ((150, 150, 20), (12, 12, 2)),         # core 1 unfolding 150 x 144: Cholesky-QR of a tall core
 ]
 
 

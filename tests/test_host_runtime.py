@@ -63,7 +63,8 @@ def test_qr_large_bond_products_host_side(host, dims, ranks, variant):
                                                               "rocblas_dgemm_strided_batched")}
     assert calls["rocblas_dgemm"] + calls["rocblas_dgemm_strided_batched"] > 0, calls
     if variant == "qr":
-        assert calls["rocblas_dsyrk"] > 0 and calls["rocblas_dtrsm"] > 0, calls
+        assert calls["rocblas_dgemm_strided_batched"] > 0 and calls["rocblas_dtrsm"] > 0, calls
+    assert calls["rocblas_dsyrk"] == 0, calls   # rocBLAS's SYRK is slow at these shapes
 
 
 def test_ring_intermediates_exceed_one_gram_when_ranks_alternate(host):
