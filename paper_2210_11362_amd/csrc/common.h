@@ -36,7 +36,7 @@ struct XsArgs {
   int64_t k_per_split;
   int nsplit;
   int wgm, wgn;       // 2-D arrangement of the 4 waves over the tile
-  float bscale;       // FP8: generated subchain rows are multiplied by this
+  const double* tmax; // FP8: device max|F1|, max|F2| (the table scale is derived from them in the kernel)
   void* partial;      // [nsplit][n_mt*n_nt][MT][NT] FP32 (FP64 for the FP64 path)
 };
 
@@ -55,8 +55,21 @@ struct XgArgs {
   int64_t k_per_split;
   int nsplit;
   int xcd_map;        // 1: 1-D grid, workgroups on one XCD share k-splits (nsplit % 8 == 0)
+  const double* tmax; // FP8: device max|T| of the operand table (its scale is derived from it)
   void* partial;      // [nsplit][n_mt*n_nt][MT][NT] FP32 (FP64 for the FP64 path)
 };
+
+// FP8 operand tables are stored as two E4M3 parts at one power-of-two scale s
+// (hi = fp8(T s), lo = fp8(T s - hi)), both contracted into the same FP32
+// accumulator: 3 fraction bits per part, about 7 together.  s = 2^floor(log2(448 / bound))
+// for a bound on |T| (1 when the bound is 0); the same expression on both
+// sides of the contraction.
+__device__ __forceinline__ double fp8_table_scale(double bound) {
+  if (!(bound > 0.0)) return 1.0;
+  int e = 0;
+  (void)frexp(448.0 / bound, &e);   // 448 / bound = m 2^e, m in [0.5, 1)
+  return ldexp(1.0, e - 1);
+}
 
 // Arguments of the slab contraction of an order-3 tensor (k_slab.hip): rows i
 // of the output mode, the contracted mode k (against a table of its core) and
@@ -94,7 +107,8 @@ hipError_t launch_xg_reduce(const XgArgs& g, int prec, double out_scale, double*
 hipError_t launch_group_bt(const double* G0, int Rl, int64_t I0, int Rm, const double* G1, int64_t I1, int two,
                            int64_t K, int C, int Crows, int64_t ldb, int prec, void* Bt, hipStream_t s);
 hipError_t launch_table_to_bt(const double* T, int64_t K, int C, int Crows, int64_t ldb, int prec, double scale,
-                              void* Bt, hipStream_t s);
+                              void* Bt, hipStream_t s,
+                              const double* tmax = nullptr);
 hipError_t launch_absorb(const double* Y, int64_t lo, int64_t I, int64_t hi, int Ru, int Rc, const double* core,
                          int Rl, int Rr, int side, int final_out, double* out, double* part, size_t part_bytes,
                          hipStream_t s);

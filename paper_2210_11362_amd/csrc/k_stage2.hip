@@ -19,6 +19,7 @@ namespace {
 template <int P>
 __global__ __launch_bounds__(256) void xg_reduce_kernel(XgArgs g, int MT, double out_scale, double* Y, int* status) {
   using part_t = typename std::conditional<P == TR_F64, double, float>::type;
+  if (g.tmax) out_scale /= fp8_table_scale(*g.tmax);   // FP8: undo the table's scale
   __shared__ double tl[16][65];
   const int NT = g.NT;
   const int64_t tsz = (int64_t)MT * NT;
@@ -67,6 +68,22 @@ __global__ __launch_bounds__(256) void xg_reduce_kernel(XgArgs g, int MT, double
     }
   }
   if (bad) atomicOr(status, ST_NONFINITE);
+}
+
+// FP8: Bt holds the hi part in rows [0, Crows) and the lo part in rows
+// [Crows, 2 Crows), at the scale derived from the device max |T|.
+__global__ void table_to_bt_fp8_kernel(const double* T, int64_t K, int C, int Crows, int64_t ldb, const double* tmax,
+                                       uint8_t* Bt) {
+  const int64_t c = blockIdx.y;
+  const double sc = fp8_table_scale(*tmax);
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ldb; k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = c * ldb + k;
+    const double v = (c < C && k < K) ? T[k * C + c] * sc : 0.0;
+    const uint8_t hi = (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32((float)v, 0.0f, 0, false) & 0xff);
+    const double r = v - (double)__builtin_amdgcn_cvt_f32_fp8((int)hi, 0);
+    Bt[e] = hi;
+    Bt[e + (int64_t)Crows * ldb] = (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32((float)r, 0.0f, 0, false) & 0xff);
+  }
 }
 
 // Bt[c * ldb + k] = op(T[k * C + c] * scale), zero for k >= K or c >= C (padding).
@@ -433,8 +450,13 @@ hipError_t launch_xg_reduce(const XgArgs& g, int prec, double out_scale, double*
 }
 
 hipError_t launch_table_to_bt(const double* T, int64_t K, int C, int Crows, int64_t ldb, int prec, double scale,
-                              void* Bt, hipStream_t s) {
+                              void* Bt, hipStream_t s, const double* tmax) {
   const dim3 grid((unsigned)std::min<int64_t>(cdiv(ldb, 256), 64), (unsigned)Crows);
+  if (prec == TR_FP8) {
+    if (!tmax) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(table_to_bt_fp8_kernel, grid, dim3(256), 0, s, T, K, C, Crows, ldb, tmax, (uint8_t*)Bt);
+    return hipGetLastError();
+  }
   switch (prec) {
     case TR_F64: hipLaunchKernelGGL(table_to_bt_kernel<double>, dim3(grid), dim3(256), 0, s, T, K, C, Crows, ldb, scale, (double*)Bt); break;
     case TR_F32: hipLaunchKernelGGL(table_to_bt_kernel<float>, dim3(grid), dim3(256), 0, s, T, K, C, Crows, ldb, scale, (float*)Bt); break;

@@ -84,6 +84,7 @@ __global__ __launch_bounds__(NTHR) void xgemm_kernel(XgArgs g) {
   constexpr int AV = MT * KT / V / NTHR;
   constexpr int KV = KT / V;                  // packed vectors along a tile row
   constexpr int MBW = MT / 64;                // row blocks per wave (waves stacked along rows)
+  constexpr int NPART = P == TR_FP8 ? 2 : 1;  // FP8 tables: hi and lo parts, NT rows each
   extern __shared__ __align__(16) unsigned char smem[];
   op_t* As = reinterpret_cast<op_t*>(smem);
   op_t* Bs = As + MT * ST;
@@ -108,6 +109,7 @@ __global__ __launch_bounds__(NTHR) void xgemm_kernel(XgArgs g) {
   const int NT = g.NT, NB = NT / 16;
   const Tin* X = reinterpret_cast<const Tin*>(g.X);
   const op_t* Bt = reinterpret_cast<const op_t*>(g.Bt) + (size_t)nt * NT * g.ldb;
+  const size_t bpart = (size_t)g.n_nt * NT * g.ldb;   // elements from one table part to the next
 
   const int64_t kbeg = (int64_t)split * g.k_per_split;
   const int64_t kend = min(g.K, kbeg + g.k_per_split);
@@ -175,17 +177,19 @@ __global__ __launch_bounds__(NTHR) void xgemm_kernel(XgArgs g) {
   // B tile: NT rows of KT contiguous elements, zero-padded in the table
   // itself.  For 8/16-bit operands it is fetched into registers one tile
   // ahead of its LDS store; wider operands copy it when it is needed.
-  constexpr int BQ = (NBMAX * 16 * KV + NTHR - 1) / NTHR;
+  // LDS row q of the B tile: row q % NT of table part q / NT
+  constexpr int BQ = (NPART * NBMAX * 16 * KV + NTHR - 1) / NTHR;
   constexpr bool BPF = BQ <= 4;
   u32x4 breg[BPF ? BQ : 1];
+  auto b_src = [&](int q, int64_t k) { return Bt + (size_t)(q / NT) * bpart + (size_t)(q % NT) * g.ldb + k; };
   auto load_b = [&](int64_t k0) {
     if constexpr (BPF) {
 #pragma unroll
       for (int q = 0; q < BQ; ++q) {
         const int e = tid + q * NTHR;
-        if (e < NT * KV) {
+        if (e < NPART * NT * KV) {
           const int row = e / KV, kv = e % KV;
-          breg[q] = *reinterpret_cast<const u32x4*>(Bt + (size_t)row * g.ldb + k0 + kv * V);
+          breg[q] = *reinterpret_cast<const u32x4*>(b_src(row, k0 + kv * V));
         }
       }
     }
@@ -195,16 +199,15 @@ __global__ __launch_bounds__(NTHR) void xgemm_kernel(XgArgs g) {
 #pragma unroll
       for (int q = 0; q < BQ; ++q) {
         const int e = tid + q * NTHR;
-        if (e < NT * KV) {
+        if (e < NPART * NT * KV) {
           const int row = e / KV, kv = e % KV;
           *reinterpret_cast<u32x4*>(Bs + row * ST + kv * V) = breg[q];
         }
       }
     } else {
-      for (int e = tid; e < NT * KV; e += NTHR) {
+      for (int e = tid; e < NPART * NT * KV; e += NTHR) {
         const int row = e / KV, kv = e % KV;
-        *reinterpret_cast<u32x4*>(Bs + row * ST + kv * V) =
-            *reinterpret_cast<const u32x4*>(Bt + (size_t)row * g.ldb + k0 + kv * V);
+        *reinterpret_cast<u32x4*>(Bs + row * ST + kv * V) = *reinterpret_cast<const u32x4*>(b_src(row, k0 + kv * V));
       }
     }
   };
@@ -230,9 +233,12 @@ __global__ __launch_bounds__(NTHR) void xgemm_kernel(XgArgs g) {
 #pragma unroll
       for (int c = 0; c < NBMAX; ++c) {
         if (c < NB) {
-          const frag_t bf = Frag<P>::ld(Bs, c * 16 + (lane & 15), ST, kb, lane);
 #pragma unroll
-          for (int r = 0; r < MBW; ++r) mma(acc[r][c], af[r], bf);
+          for (int part = 0; part < NPART; ++part) {
+            const frag_t bf = Frag<P>::ld(Bs + part * NT * ST, c * 16 + (lane & 15), ST, kb, lane);
+#pragma unroll
+            for (int r = 0; r < MBW; ++r) mma(acc[r][c], af[r], bf);
+          }
         }
       }
     }
@@ -259,7 +265,7 @@ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 template <int P, typename Tin, bool NN, bool VEC, int MT, int KT>
 hipError_t launch_g(const XgArgs& g, hipStream_t s) {
   using op_t = typename PT<P>::op_t;
-  const size_t lds = (size_t)(MT + g.NT) * (KT + Pad<P>::v) * sizeof(op_t);
+  const size_t lds = (size_t)(MT + (P == TR_FP8 ? 2 : 1) * g.NT) * (KT + Pad<P>::v) * sizeof(op_t);
   const dim3 grid = g.xcd_map ? dim3((unsigned)(g.n_mt * g.n_nt * g.nsplit)) : dim3(g.n_mt * g.n_nt, g.nsplit);
   auto k = xgemm_kernel<P, Tin, NN, VEC, MT, KT, 8>;
   if (lds > 64 * 1024) hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -105,16 +105,20 @@ __global__ __launch_bounds__(NTHR) void xstream_kernel(XsArgs a) {
   const int s1max = (a.d1 == 1) ? KT : min((int64_t)KT, (KT + a.d1 - 1) / a.d1 + 1);
   const int s2max = (a.d2 == 1) ? KT : min((int64_t)KT, (KT + a.d2 - 1) / a.d2 + 1);
 
+  // FP8: the generated subchain rows are stored as hi and lo E4M3 parts
+  // (NT rows each), both contracted into the same accumulators
+  constexpr int NPART = P == TR_FP8 ? 2 : 1;
   op_t* Xs = reinterpret_cast<op_t*>(smem);
   op_t* Bs = Xs + MT * ST;
-  gen_t* F1s = reinterpret_cast<gen_t*>(smem + (((size_t)(MT + NT) * ST * sizeof(op_t) + 15) & ~(size_t)15));
+  gen_t* F1s = reinterpret_cast<gen_t*>(smem + (((size_t)(MT + NPART * NT) * ST * sizeof(op_t) + 15) & ~(size_t)15));
   gen_t* F2s = F1s + (size_t)s1max * row1;
 
   const Tin* X = reinterpret_cast<const Tin*>(a.X);
-  const gen_t bscale = (gen_t)a.bscale;
+  // FP8 scale of the generated rows from the device bound max|F1| max|F2| Rmid
+  const gen_t bscale = P == TR_FP8 ? (gen_t)fp8_table_scale(a.tmax[0] * a.tmax[1] * a.Rmid) : (gen_t)1;
 
   // columns of the B tile that are never written by the generator stay zero
-  for (int e = tid; e < NT * ST; e += NTHR) Bs[e] = to_op<P>((gen_t)0);
+  for (int e = tid; e < NPART * NT * ST; e += NTHR) Bs[e] = to_op<P>((gen_t)0);
 
   // wave -> block sub-grid
   const int MB = MT / 16, NB = NT / 16;
@@ -259,7 +263,13 @@ __global__ __launch_bounds__(NTHR) void xstream_kernel(XsArgs a) {
 #pragma unroll
           for (int y = 0; y < 4; ++y) {
             const int aa = 4 * ab + x, bl = 4 * bb + y;
-            if (aa < a.Ra && bl < bcount) Bs[(aa + a.Ra * bl) * ST + kk_t] = to_op<P>(g[x][y] * bscale);
+            if (aa < a.Ra && bl < bcount) {
+              const gen_t v = g[x][y] * bscale;
+              const op_t hi = to_op<P>(v);
+              Bs[(aa + a.Ra * bl) * ST + kk_t] = hi;
+              if constexpr (P == TR_FP8)
+                Bs[(NT + aa + a.Ra * bl) * ST + kk_t] = to_op<P>(v - __builtin_amdgcn_cvt_f32_fp8((int)hi, 0));
+            }
           }
       }
     }
@@ -269,17 +279,20 @@ __global__ __launch_bounds__(NTHR) void xstream_kernel(XsArgs a) {
     using frag_t = typename Frag<P>::t;
 #pragma unroll 2
     for (int kb = 0; kb < KT; kb += KS) {
-      frag_t bf[WN];
 #pragma unroll
-      for (int c = 0; c < WN; ++c)
-        if (c < nbc) bf[c] = Frag<P>::ld(Bs, (bc0 + c) * 16 + (lane & 15), ST, kb, lane);
+      for (int part = 0; part < NPART; ++part) {
+        frag_t bf[WN];
 #pragma unroll
-      for (int r = 0; r < WM; ++r) {
-        if (r < nbr) {
-          const frag_t af = Frag<P>::ld(Xs, (br0 + r) * 16 + (lane & 15), ST, kb, lane);
+        for (int c = 0; c < WN; ++c)
+          if (c < nbc) bf[c] = Frag<P>::ld(Bs + part * NT * ST, (bc0 + c) * 16 + (lane & 15), ST, kb, lane);
 #pragma unroll
-          for (int c = 0; c < WN; ++c)
-            if (c < nbc) mma(acc[r][c], af, bf[c]);
+        for (int r = 0; r < WM; ++r) {
+          if (r < nbr) {
+            const frag_t af = Frag<P>::ld(Xs, (br0 + r) * 16 + (lane & 15), ST, kb, lane);
+#pragma unroll
+            for (int c = 0; c < WN; ++c)
+              if (c < nbc) mma(acc[r][c], af, bf[c]);
+          }
         }
       }
     }
@@ -324,6 +337,7 @@ __global__ void xs_reduce_kernel(XsArgs a, double out_scale, double* M, int* sta
   const size_t sstride = (size_t)(ntiles * tsz);
   double s = 0.0;
   for (int sp = 0; sp < a.nsplit; ++sp) s += (double)p[sp * sstride];
+  if (a.tmax) out_scale /= fp8_table_scale(a.tmax[0] * a.tmax[1] * a.Rmid);   // FP8
   s *= out_scale;
   if (!isfinite(s)) atomicOr(status, ST_NONFINITE);
   M[i + a.I * (int64_t)(aa + a.Ra * b)] = s;
@@ -367,7 +381,7 @@ size_t xstream_lds_bytes(const XsArgs& a, int prec, int kt) {
     default: ops = op_size<TR_FP8>(); gens = gen_size<TR_FP8>(); pad = Pad<TR_FP8>::v; break;
   }
   const size_t st = kt + pad;
-  size_t bytes = (((size_t)(a.MT + a.NT) * st * ops) + 15) & ~(size_t)15;
+  size_t bytes = (((size_t)(a.MT + (prec == TR_FP8 ? 2 : 1) * a.NT) * st * ops) + 15) & ~(size_t)15;
   const int Bw4 = (a.NTb + 3) & ~3, Ra4 = (a.Ra + 3) & ~3;
   auto smax = [&](int64_t d) -> int64_t { return d == 1 ? kt : std::min<int64_t>(kt, (kt + d - 1) / d + 1); };
   bytes += (size_t)(smax(a.d1) * a.Rmid * Bw4 + smax(a.d2) * a.Rmid * Ra4) * gens;

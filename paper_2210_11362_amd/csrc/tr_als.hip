@@ -417,7 +417,7 @@ XsCfg xs_config(const tr_als_ctx* c, int m, int prec) {
   a.F1 = c->F1; a.F2 = c->F2;
   a.d1 = p.d1; a.m1 = p.m1; a.d2 = p.d2; a.m2 = p.m2;
   a.Rb = p.Rb; a.Rmid = p.Rmid; a.Ra = p.Ra;
-  a.bscale = 1.0f;
+  a.tmax = nullptr;
   a.partial = c->partial;
   if (p.I <= 128) { a.MT = (int)((p.I + 15) / 16 * 16); a.n_mt = 1; }
   else { a.MT = 128; a.n_mt = (int)((p.I + 127) / 128); }
@@ -549,6 +549,7 @@ XgArgs xg_config(const tr_als_ctx* c, int m, int prec, const void* X, int esize,
   g.nsplit = (int)((p.gK + g.k_per_split - 1) / g.k_per_split);
   if (g.xcd_map && g.nsplit != ns) g.xcd_map = 0;
   g.Bt = c->Bt;
+  g.tmax = nullptr;
   g.partial = c->partial;
   return g;
 }
@@ -557,8 +558,8 @@ size_t xg_partial_bytes(const XgArgs& g, int prec) {
   return (size_t)g.nsplit * g.n_mt * g.n_nt * g.MT * g.NT * (prec == TR_F64 ? 8 : 4);
 }
 
-size_t xg_bt_bytes(const XgArgs& g, int prec) {
-  const size_t es = prec == TR_F64 ? 8 : prec == TR_F32 ? 4 : prec == TR_BF16 ? 2 : 1;
+size_t xg_bt_bytes(const XgArgs& g, int prec) {   // FP8: hi and lo parts
+  const size_t es = prec == TR_F64 ? 8 : prec == TR_F32 ? 4 : prec == TR_BF16 ? 2 : 2;
   return (size_t)g.n_nt * g.NT * g.ldb * es;
 }
 
@@ -633,7 +634,7 @@ int absorb_steps(tr_als_ctx* c, const Plan& p, double* cur, double* Mout, hipStr
 int compute_mttsp_two_stage(tr_als_ctx* c, int m, int prec, double* Mout, bool in_sweep, const Hook& after_main) {
   hipStream_t s = c->stream;
   const Plan& p = c->plan[m];
-  const bool reuse = in_sweep && p.reuse_prev && prec != TR_FP8;
+  const bool reuse = in_sweep && p.reuse_prev;
   if (reuse && p.reuse_y) {
     // the previous mode contracted X with this same group table and left the
     // reduced result in Y0 (identical bits): only the absorptions differ
@@ -657,14 +658,15 @@ int compute_mttsp_two_stage(tr_als_ctx* c, int m, int prec, double* Mout, bool i
   XgArgs g = xg_config(c, m, prec, X, esize, use_t);
   if (xg_partial_bytes(g, prec) > c->partial_bytes || xg_bt_bytes(g, prec) > c->bt_bytes)
     return fail(c, TR_EHIP, "internal: stage-1 buffers too small");
-  double bscale = 1.0, out_scale = 1.0;
-  if (prec == TR_FP8) {
+  double out_scale = 1.0;
+  if (prec == TR_FP8 && !reuse) {
+    // the table's scale is derived on the device from its max (no host round
+    // trip: the sweep stays capturable); the reduction undoes it
     HIPCHK(c, launch_table_absmax(c->F1, p.gK * p.gC, c->dscal + 2, s));
-    double tm = 0;
-    HIPCHK(c, hipMemcpyAsync(&tm, c->dscal + 2, sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
-    bscale = tm > 0 ? std::ldexp(1.0, (int)std::floor(std::log2(448.0 / tm))) : 1.0;
-    out_scale = 1.0 / ((double)c->fp8_scale * bscale);
+  }
+  if (prec == TR_FP8) {
+    g.tmax = c->dscal + 2;
+    out_scale = 1.0 / (double)c->fp8_scale;
   }
   if (!reuse && direct) {
     const int g0 = p.gcores[0], two = p.gcores.size() == 2;
@@ -672,7 +674,7 @@ int compute_mttsp_two_stage(tr_als_ctx* c, int m, int prec, double* Mout, bool i
     HIPCHK(c, launch_group_bt(c->cores[g0], c->R[g0], c->dims[g0], c->R[g0 + 1], c->cores[g1], c->dims[g1], two, p.gK,
                               p.gC, g.n_nt * g.NT, g.ldb, prec, c->Bt, s));
   } else if (!reuse) {
-    HIPCHK(c, launch_table_to_bt(c->F1, p.gK, p.gC, g.n_nt * g.NT, g.ldb, prec, bscale, c->Bt, s));
+    HIPCHK(c, launch_table_to_bt(c->F1, p.gK, p.gC, g.n_nt * g.NT, g.ldb, prec, 1.0, c->Bt, s, c->dscal + 2));
   }
   const bool prof = c->prof;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -755,19 +757,14 @@ int compute_mttsp(tr_als_ctx* c, int m, int prec, double* Mout, bool in_sweep = 
   if (prec == TR_BF16) x.a.X = c->xbf16;
   else if (prec == TR_FP8) {
     x.a.X = c->xfp8;
-    // scale the generated subchain rows into the E4M3 range using a bound of
-    // max|F1 F2| <= Rmid * max|F1| * max|F2|
+    // the generated subchain rows are scaled into the E4M3 range by a power of
+    // two derived on the device from max|F1 F2| <= Rmid max|F1| max|F2| (no
+    // host round trip); the reduction undoes it
     const int64_t n1 = table_elems(c, p.f1c, p.Rmid), n2 = table_elems(c, p.f2c, p.Rmid);
     HIPCHK(c, launch_table_absmax(c->F1, n1, c->dscal + 2, s));
     HIPCHK(c, launch_table_absmax(c->F2, n2, c->dscal + 3, s));
-    double tm[2];
-    HIPCHK(c, hipMemcpyAsync(tm, c->dscal + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
-    double bound = tm[0] * tm[1] * p.Rmid;
-    double bs = bound > 0 ? 448.0 / bound : 1.0;
-    bs = std::ldexp(1.0, (int)std::floor(std::log2(bs)));  // power of two: exact rescale
-    x.a.bscale = (float)bs;
-    out_scale = 1.0 / ((double)c->fp8_scale * bs);
+    x.a.tmax = c->dscal + 2;
+    out_scale = 1.0 / (double)c->fp8_scale;
   } else x.a.X = c->X;
   const bool prof = c->prof;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1942,9 +1939,9 @@ static int update_mode(tr_als_ctx* c, int m, int prec, int refine, bool in_sweep
 
 // One sweep of mode updates captured into a HIP graph and replayed: the sweep
 // issues ~20 small kernels per mode whose launch cost would otherwise show.
-// FP8 (host-side scale readback) and profiled runs launch eagerly.
+// Profiled runs launch eagerly.
 static hipGraphExec_t sweep_graph(tr_als_ctx* c, int prec, int refine) {
-  if (!c->graphs_ok || c->prof || prec == TR_FP8 || c->variant != TR_NE) return nullptr;
+  if (!c->graphs_ok || c->prof || c->variant != TR_NE) return nullptr;
   if (c->graphs[prec][refine]) return c->graphs[prec][refine];
   if (ensure_shadow(c, prec) != TR_OK) return nullptr;
   // The caller's stream may be the legacy default stream, which cannot be

@@ -332,8 +332,13 @@ void check_extents(const std::string& full, const std::string& nm, void** a, std
     const size_t b = (size_t)(L(1) * I(2) * I(3) * 8);
     r->push_back({D(0), b, "Y"});
     r->push_back({D(4), b, "M"});
+  } else if (nm == "table_to_bt_fp8_kernel") {   // (T, K, C, Crows, ldb, tmax, Bt)
+    r->push_back({D(0), (size_t)(L(1) * I(2) * 8), "T"});
+    r->push_back({D(5), 8, "tmax"});
+    r->push_back({D(6), (size_t)(2 * I(3) * L(4)), "Bt"});
   } else if (nm == "xg_reduce_kernel") {   // <prec>(XgArgs, int, double, Y, status)
     const XgArgs g = arg<XgArgs>(a, 0);
+    if (g.tmax) r->push_back({(uintptr_t)g.tmax, 8, "tmax"});
     const size_t es = template_int(full, 0) == 0 ? 8 : 4;
     r->push_back({(uintptr_t)g.partial, (size_t)g.nsplit * g.n_mt * g.n_nt * g.MT * g.NT * es, "partial"});
     r->push_back({D(3), (size_t)(g.M * g.C * 8), "Y"});
@@ -343,17 +348,20 @@ void check_extents(const std::string& full, const std::string& nm, void** a, std
     const size_t xes = p == 0 ? (full.find("float") != std::string::npos ? 4 : 8) : p == 1 ? 4 : es_of_prec(p);
     const size_t bes = p == 0 ? 8 : p == 1 ? 4 : es_of_prec(p);
     r->push_back({(uintptr_t)g.X, (size_t)(g.M * g.K) * xes, "X"});
-    r->push_back({(uintptr_t)g.Bt, (size_t)g.n_nt * g.NT * g.ldb * bes, "Bt"});
+    r->push_back({(uintptr_t)g.Bt, (size_t)g.n_nt * g.NT * g.ldb * bes * (p == 3 ? 2 : 1), "Bt"});   // FP8: hi, lo
+    if (p == 3) r->push_back({(uintptr_t)g.tmax, 8, "tmax"});
     r->push_back({(uintptr_t)g.partial, (size_t)g.nsplit * g.n_mt * g.n_nt * g.MT * g.NT * (p == 0 ? 8 : 4),
                   "partial"});
   } else if (nm == "xs_reduce_kernel") {   // <prec>(XsArgs, double, M, status)
     const XsArgs x = arg<XsArgs>(a, 0);
+    if (x.tmax) r->push_back({(uintptr_t)x.tmax, 16, "tmax"});
     const size_t es = template_int(full, 0) == 0 ? 8 : 4;
     r->push_back({(uintptr_t)x.partial, (size_t)x.nsplit * x.n_mt * x.n_nt * x.MT * x.NT * es, "partial"});
     r->push_back({D(2), (size_t)(x.I * x.Ra * x.Rb * 8), "M"});
   } else if (nm == "xstream_kernel") {
     const XsArgs x = arg<XsArgs>(a, 0);
     const int p = template_int(full, 0);
+    if (p == 3) r->push_back({(uintptr_t)x.tmax, 16, "tmax"});
     r->push_back({(uintptr_t)x.partial, (size_t)x.nsplit * x.n_mt * x.n_nt * x.MT * x.NT * (p == 0 ? 8 : 4),
                   "partial"});
   } else if (nm == "to_bf16_kernel" || nm == "to_fp8_kernel" || nm == "sumsq_kernel" || nm == "absmax_kernel") {

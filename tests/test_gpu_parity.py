@@ -72,7 +72,7 @@ def force_regime(request, monkeypatch):
 
 @pytest.mark.parametrize("force_regime", [0, 1, 2, "2f"], indirect=True)
 @pytest.mark.parametrize("prec,xdt,tol", [("f64", np.float64, 1e-12), ("f32", np.float32, 1e-5),
-                                          ("bf16", np.float32, 2e-2), ("fp8", np.float32, 1.5e-1)])
+                                          ("bf16", np.float32, 2e-2), ("fp8", np.float32, 8e-2)])
 @pytest.mark.parametrize("dims,ranks", SHAPES, ids=[str(s[0]) for s in SHAPES])
 def test_mttsp(dims, ranks, prec, xdt, tol, force_regime):
     say(f"[mttsp] dims={dims} ranks={ranks} prec={prec} regime={force_regime}")
@@ -237,7 +237,7 @@ def test_graph_replays_match_eager(monkeypatch):
     eager, de = _ctx(to_dev_flat(w.X), w.init_cores, w.dims, w.ranks)
     monkeypatch.delenv("TR_ALS_NO_GRAPH")
     graph, dg = _ctx(to_dev_flat(w.X), w.init_cores, w.dims, w.ranks)
-    for prec in ("f32", "bf16", "f32"):
+    for prec in ("f32", "bf16", "fp8", "f32"):
         for rep in range(3):
             eager.sweep(1, prec, refine=1)
             graph.sweep(1, prec, refine=1)
@@ -247,7 +247,7 @@ def test_graph_replays_match_eager(monkeypatch):
                 assert np.array_equal(x, y), (prec, rep)
     assert eager.graphs()[0] == 0
     n, note = graph.graphs()
-    assert n == 2 and note == "", (n, note)   # f32 and bf16 sweeps were captured, not run eagerly
+    assert n == 3 and note == "", (n, note)   # f32, bf16 and fp8 sweeps were captured, not run eagerly
     eager.close()
     graph.close()
 
