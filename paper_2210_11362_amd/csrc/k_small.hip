@@ -578,17 +578,25 @@ __global__ void max_partials_kernel(const float* partials, int n, float* out) {
   }
 }
 
-__global__ void table_absmax_kernel(const double* T, int64_t n, double* out) {
+// max |T| over the whole grid: each block reduces its share, then one atomic
+// max on the bit pattern (non-negative doubles order like their bits), so the
+// result does not depend on the order of the blocks; *out is zeroed by a
+// one-thread kernel launched before (no memset: the sweep may be captured).
+__global__ void zero_double_kernel(double* out) { *out = 0.0; }
+
+__global__ __launch_bounds__(256) void table_absmax_kernel(const double* T, int64_t n, double* out) {
   __shared__ double red[256];
   double s = 0.0;
-  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) s = fmax(s, fabs(T[e]));
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    s = fmax(s, fabs(T[e]));
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) *out = red[0];
+  if (threadIdx.x == 0)
+    atomicMax(reinterpret_cast<unsigned long long*>(out), (unsigned long long)__double_as_longlong(red[0]));
 }
 
 template <typename T>
@@ -847,7 +855,9 @@ hipError_t launch_absmax(const void* X, int xdt, int64_t n, float* partials, int
 }
 
 hipError_t launch_table_absmax(const double* T, int64_t n, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(table_absmax_kernel, dim3(1), dim3(256), 0, s, T, n, out);
+  hipLaunchKernelGGL(zero_double_kernel, dim3(1), dim3(1), 0, s, out);
+  hipLaunchKernelGGL(table_absmax_kernel, dim3((unsigned)std::min<int64_t>(std::max<int64_t>(cdiv(n, 2048), 1), 1024)),
+                     dim3(256), 0, s, T, n, out);
   return hipGetLastError();
 }
 

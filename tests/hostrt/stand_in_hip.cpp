@@ -320,6 +320,11 @@ void check_extents(const std::string& full, const std::string& nm, void** a, std
   } else if (nm == "transpose_kernel") {   // (A, rows, cols, At)
     r->push_back({D(0), (size_t)(L(1) * L(2) * 8), "A"});
     r->push_back({D(3), (size_t)(L(1) * L(2) * 8), "At"});
+  } else if (nm == "table_absmax_kernel") {   // (T, n, out)
+    r->push_back({D(0), (size_t)(L(1) * 8), "T"});
+    r->push_back({D(2), 8, "out"});
+  } else if (nm == "zero_double_kernel") {   // (out)
+    r->push_back({D(0), 8, "out"});
   } else if (nm == "slice_transpose_kernel") {   // (in, L, I, T, out)
     const size_t b = (size_t)(L(1) * L(2) * L(3) * 8);
     r->push_back({D(0), b, "in"});
