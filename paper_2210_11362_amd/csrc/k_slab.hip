@@ -25,6 +25,8 @@
 
 namespace {
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
 template <int P> struct ST_;
 template <> struct ST_<TR_F64>  { using op_t = double; using acc_t = f64x4; using t_t = double; static constexpr int KS = 4;  static constexpr int PAD = 2; };
 template <> struct ST_<TR_F32>  { using op_t = float;  using acc_t = f32x4; using t_t = float;  static constexpr int KS = 4;  static constexpr int PAD = 4; };
@@ -63,7 +65,7 @@ template <> __device__ __forceinline__ __bf16 cvt<TR_BF16, __bf16>(__bf16 v) { r
 constexpr int NTHR = 256;
 constexpr int MTX = 128;     // rows per tile
 constexpr int TWX = 128;     // T columns per group (NG * Rm <= TWX)
-constexpr int UPT = 2;       // group values per thread in the absorption (2 threads per row: NG <= 4)
+constexpr int UPT = 2;       // group values per thread in the absorption (two threads per row: NG <= 4)
 constexpr int XPT = 32;      // largest other rank of the absorbed core
 constexpr int RMX = 32;      // largest middle rank
 
@@ -74,7 +76,7 @@ __global__ __launch_bounds__(NTHR) void xslab_kernel(XslabArgs a) {
   using t_t = typename ST_<P>::t_t;
   constexpr int KS = ST_<P>::KS;
   constexpr int ST = KT + ST_<P>::PAD;
-  constexpr int WM = 2, WN = 8;    // 4 waves stacked over the rows, each 2 x 8 blocks of 16 x 16
+  constexpr int WM = MTX / 16 / (NTHR / 64), WN = 8;   // 4 waves stacked over the rows, each 2 x 8 blocks of 16 x 16
   extern __shared__ __align__(16) unsigned char smem[];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -89,19 +91,23 @@ __global__ __launch_bounds__(NTHR) void xslab_kernel(XslabArgs a) {
   // BF16: the table is held as hi + lo BF16 parts (two products), so that
   // only X is rounded to BF16; FP32 / FP64 tables are one part
   constexpr int NPART = P == TR_BF16 ? 2 : 1;
+  // LDS: the X and table tiles of the k loop, and (after it, in the same
+  // bytes) the spilled T of the slab; then the slab of the absorbed core
   op_t* Xs = reinterpret_cast<op_t*>(smem);                // MTX x ST
   op_t* Bs = Xs + MTX * ST;                                // NPART x TWX x ST
-  t_t* Ts = reinterpret_cast<t_t*>(smem + (((size_t)(MTX + NPART * TWX) * ST * sizeof(op_t) + 15) & ~(size_t)15));
+  t_t* Ts = reinterpret_cast<t_t*>(smem);                  // MTX x TSW, aliases Xs / Bs
   const int TSW = a.TWg + 1;                               // padded row of Ts (odd: conflict-free rows)
-  t_t* Gls = Ts + (size_t)MTX * TSW;                       // Rm x Ro slab of the absorbed core
+  const size_t xb_bytes = ((size_t)(MTX + NPART * TWX) * ST * sizeof(op_t) + 15) & ~(size_t)15;
+  const size_t ts_bytes = ((size_t)MTX * TSW * sizeof(t_t) + 15) & ~(size_t)15;
+  t_t* Gls = reinterpret_cast<t_t*>(smem + (xb_bytes > ts_bytes ? xb_bytes : ts_bytes));   // Rm x Ro
 
   const Tin* X = reinterpret_cast<const Tin*>(a.X);
   const op_t* Bt = reinterpret_cast<const op_t*>(a.Bt);   // [col][k], ldb = a.ldb
 
   // absorbed outputs of this thread: row i = tid % 128, group values
-  // u = u_lo .. u_lo + UPT - 1 (the two threads of a row split the group)
+  // u = u_lo .. u_lo + UPT - 1 (the threads of a row split the group)
   const int my_i = tid & (MTX - 1);
-  const int u_lo = (tid >> 7) * UPT;
+  const int u_lo = (tid / MTX) * UPT;
   t_t macc[UPT][XPT];      // FP64 on the FP64 path, else FP32
 #pragma unroll
   for (int uu = 0; uu < UPT; ++uu)
@@ -110,6 +116,136 @@ __global__ __launch_bounds__(NTHR) void xslab_kernel(XslabArgs a) {
 
   const int64_t l_beg = (int64_t)split * a.l_per_split;
   const int64_t l_end = min(a.Il, l_beg + a.l_per_split);
+  // operand chunks in registers; BF16 fetches them one k step ahead (and the
+  // next slab's first chunk during the last step of a slab) so that their
+  // global loads overlap the MFMAs of the current chunk
+  // BF16: 16-byte loads of 8 consecutive elements (rows i when they are
+  // contiguous, else k) and of the table; other types element by element
+  constexpr int VW = P == TR_BF16 ? 8 : 1;
+  constexpr int XE = MTX * KT / NTHR / VW;
+  constexpr int BE = TWX * KT / NTHR / VW;
+  using vec_t = typename std::conditional<P == TR_BF16, u32x4, op_t>::type;
+  vec_t xv[XE];
+  vec_t bv[NPART][BE];
+  const bool rows_c = a.sn == 1;   // rows contiguous in X (else k contiguous)
+  auto load_chunk = [&](int64_t l, int64_t k0) {
+    const Tin* Xl = X + a.sl * l;
+    const int kvalid = (int)min((int64_t)KT, a.Ik - k0);
+    if constexpr (P == TR_BF16) {
+      // whole vectors are in or out: In and Ik are multiples of 8 and the
+      // strides keep 16-byte alignment (checked by the host)
+      if (rows_c) {
+#pragma unroll
+        for (int q = 0; q < XE; ++q) {
+          const int e = tid + q * NTHR;
+          const int iv = e % (MTX / VW), kk = e / (MTX / VW);
+          const int64_t i = i0 + VW * iv;
+          xv[q] = (i < a.In && kk < kvalid) ? *reinterpret_cast<const u32x4*>(Xl + i + a.sk * (k0 + kk))
+                                           : u32x4{0, 0, 0, 0};
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < XE; ++q) {
+          const int e = tid + q * NTHR;
+          const int kv = e % (KT / VW), ii = e / (KT / VW);
+          const int64_t i = i0 + ii;
+          xv[q] = (i < a.In && VW * kv < kvalid) ? *reinterpret_cast<const u32x4*>(Xl + a.sn * i + k0 + VW * kv)
+                                                : u32x4{0, 0, 0, 0};
+        }
+      }
+#pragma unroll
+      for (int part = 0; part < NPART; ++part) {
+        const op_t* Bp = Bt + (size_t)part * a.n_g * a.TWg * a.ldb;
+#pragma unroll
+        for (int q = 0; q < BE; ++q) {
+          const int e = tid + q * NTHR;
+          const int kv = e % (KT / VW), cl = e / (KT / VW);
+          bv[part][q] = (cl < TWp) ? *reinterpret_cast<const u32x4*>(Bp + (int64_t)(g * a.TWg + cl) * a.ldb + k0 + VW * kv)
+                                   : u32x4{0, 0, 0, 0};
+        }
+      }
+    } else {
+      if (rows_c) {              // threads walk i
+#pragma unroll
+        for (int q = 0; q < XE; ++q) {
+          const int e = tid + q * NTHR;
+          const int ii = e % MTX, kk = e / MTX;
+          const int64_t i = i0 + ii;
+          xv[q] = (i < a.In && kk < kvalid) ? cvt<P, Tin>(Xl[i + a.sk * (k0 + kk)]) : (op_t)0;
+        }
+      } else {                   // threads walk k
+#pragma unroll
+        for (int q = 0; q < XE; ++q) {
+          const int e = tid + q * NTHR;
+          const int kk = e % KT, ii = e / KT;
+          const int64_t i = i0 + ii;
+          xv[q] = (i < a.In && kk < kvalid) ? cvt<P, Tin>(Xl[a.sn * i + (k0 + kk)]) : (op_t)0;
+        }
+      }
+#pragma unroll
+      for (int part = 0; part < NPART; ++part) {   // table chunk (zero-padded beyond ldb)
+        const op_t* Bp = Bt + (size_t)part * a.n_g * a.TWg * a.ldb;
+#pragma unroll
+        for (int q = 0; q < BE; ++q) {
+          const int e = tid + q * NTHR;
+          const int kk = e % KT, cl = e / KT;
+          bv[part][q] = (cl < TWp) ? Bp[(int64_t)(g * a.TWg + cl) * a.ldb + k0 + kk] : (op_t)0;
+        }
+      }
+    }
+  };
+  auto store_chunk = [&]() {
+    if constexpr (P == TR_BF16) {
+      if (rows_c) {
+#pragma unroll
+        for (int q = 0; q < XE; ++q) {
+          const int e = tid + q * NTHR;
+          const int iv = e % (MTX / VW), kk = e / (MTX / VW);
+          const __bf16* v = reinterpret_cast<const __bf16*>(&xv[q]);
+#pragma unroll
+          for (int j = 0; j < VW; ++j) Xs[(VW * iv + j) * ST + kk] = v[j];
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < XE; ++q) {
+          const int e = tid + q * NTHR;
+          *reinterpret_cast<u32x4*>(Xs + (e / (KT / VW)) * ST + VW * (e % (KT / VW))) = xv[q];
+        }
+      }
+#pragma unroll
+      for (int part = 0; part < NPART; ++part)
+#pragma unroll
+        for (int q = 0; q < BE; ++q) {
+          const int e = tid + q * NTHR;
+          *reinterpret_cast<u32x4*>(Bs + part * TWX * ST + (e / (KT / VW)) * ST + VW * (e % (KT / VW))) = bv[part][q];
+        }
+    } else {
+      if (rows_c) {
+#pragma unroll
+        for (int q = 0; q < XE; ++q) {
+          const int e = tid + q * NTHR;
+          Xs[(e % MTX) * ST + e / MTX] = xv[q];
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < XE; ++q) {
+          const int e = tid + q * NTHR;
+          Xs[(e / KT) * ST + e % KT] = xv[q];
+        }
+      }
+#pragma unroll
+      for (int part = 0; part < NPART; ++part)
+#pragma unroll
+        for (int q = 0; q < BE; ++q) {
+          const int e = tid + q * NTHR;
+          Bs[part * TWX * ST + (e / KT) * ST + e % KT] = bv[part][q];
+        }
+    }
+  };
+  // BF16 fetches one chunk ahead; the wider types (no register room for a
+  // second chunk) fetch each chunk right before storing it
+  constexpr bool PREF = P == TR_BF16;
+  if (PREF && l_beg < l_end) load_chunk(l_beg, 0);
   for (int64_t l = l_beg; l < l_end; ++l) {
     acc_t acc[WM][WN];
 #pragma unroll
@@ -118,59 +254,15 @@ __global__ __launch_bounds__(NTHR) void xslab_kernel(XslabArgs a) {
       for (int c = 0; c < WN; ++c)
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[r][c][v] = 0;
-    const Tin* Xl = X + a.sl * l;
     for (int64_t k0 = 0; k0 < a.Ik; k0 += KT) {
-      const int kvalid = (int)min((int64_t)KT, a.Ik - k0);
+      __syncthreads();             // the tiles (or, at k0 = 0, the previous slab's T) are free
+      if constexpr (!PREF) load_chunk(l, k0);
+      store_chunk();
       __syncthreads();
-      // X chunk: every load in flight before the stores
-      constexpr int XE = MTX * KT / NTHR;
-      op_t xv[XE];
-      if (a.sn == 1) {             // rows contiguous: threads walk i
-#pragma unroll
-        for (int q = 0; q < XE; ++q) {
-          const int e = tid + q * NTHR;
-          const int ii = e % MTX, kk = e / MTX;
-          const int64_t i = i0 + ii;
-          xv[q] = (i < a.In && kk < kvalid) ? cvt<P, Tin>(Xl[i + a.sk * (k0 + kk)]) : (op_t)0;
-        }
-#pragma unroll
-        for (int q = 0; q < XE; ++q) {
-          const int e = tid + q * NTHR;
-          Xs[(e % MTX) * ST + e / MTX] = xv[q];
-        }
-      } else {                     // k contiguous: threads walk k
-#pragma unroll
-        for (int q = 0; q < XE; ++q) {
-          const int e = tid + q * NTHR;
-          const int kk = e % KT, ii = e / KT;
-          const int64_t i = i0 + ii;
-          xv[q] = (i < a.In && kk < kvalid) ? cvt<P, Tin>(Xl[a.sn * i + (k0 + kk)]) : (op_t)0;
-        }
-#pragma unroll
-        for (int q = 0; q < XE; ++q) {
-          const int e = tid + q * NTHR;
-          Xs[(e / KT) * ST + e % KT] = xv[q];
-        }
+      if constexpr (PREF) {
+        if (k0 + KT < a.Ik) load_chunk(l, k0 + KT);
+        else if (l + 1 < l_end) load_chunk(l + 1, 0);
       }
-      // table chunk (zero-padded beyond ldb), each part
-#pragma unroll
-      for (int part = 0; part < NPART; ++part) {
-        constexpr int BE = TWX * KT / NTHR;
-        const op_t* Bp = Bt + (size_t)part * a.n_g * a.TWg * a.ldb;
-        op_t bv[BE];
-#pragma unroll
-        for (int q = 0; q < BE; ++q) {
-          const int e = tid + q * NTHR;
-          const int kk = e % KT, cl = e / KT;
-          bv[q] = (cl < TWp) ? Bp[(int64_t)(g * a.TWg + cl) * a.ldb + k0 + kk] : (op_t)0;
-        }
-#pragma unroll
-        for (int q = 0; q < BE; ++q) {
-          const int e = tid + q * NTHR;
-          Bs[part * TWX * ST + (e / KT) * ST + e % KT] = bv[q];
-        }
-      }
-      __syncthreads();
       using frag_t = typename Fr<P>::t;
 #pragma unroll
       for (int part = 0; part < NPART; ++part)
@@ -210,25 +302,21 @@ __global__ __launch_bounds__(NTHR) void xslab_kernel(XslabArgs a) {
       Gls[e] = (t_t)a.Gl[src];
     }
     __syncthreads();
-    // absorb: outputs (u, x) of this thread's row, x in [0, Ro)
+    // absorb: outputs (u, x) of this thread's row, x in [0, Ro), one middle
+    // index m at a time (in increasing m), straight into the accumulators
     if (i0 + my_i < a.In) {
       const t_t* trow = Ts + my_i * TSW;
 #pragma unroll
       for (int uu = 0; uu < UPT; ++uu) {
         const int u = u_lo + uu;
         if (u < ng) {
-          t_t tv[RMX];
+          for (int m = 0; m < a.Rm; ++m) {
+            const t_t tv = trow[m + a.Rm * u];
+            const t_t* gm = Gls + m * a.Ro;
 #pragma unroll
-          for (int m = 0; m < RMX; ++m) tv[m] = m < a.Rm ? trow[m + a.Rm * u] : (t_t)0;
-#pragma unroll
-          for (int x = 0; x < XPT; ++x)
-            if (x < a.Ro) {
-              t_t s = 0;
-#pragma unroll
-              for (int m = 0; m < RMX; ++m)
-                if (m < a.Rm) s += tv[m] * Gls[m * a.Ro + x];
-              macc[uu][x] += s;
-            }
+            for (int x = 0; x < XPT; ++x)
+              if (x < a.Ro) macc[uu][x] += tv * gm[x];
+          }
         }
       }
     }
@@ -319,15 +407,15 @@ size_t xslab_lds_bytes(const XslabArgs& a, int prec) {
   const int pad = prec == TR_F64 ? 2 : prec == TR_F32 ? 4 : 8;
   const int nparts = prec == TR_BF16 ? 2 : 1;
   size_t b = ((size_t)(MTX + nparts * TWX) * (kt + pad) * ops + 15) & ~(size_t)15;
-  b += ((size_t)MTX * (a.TWg + 1) + (size_t)a.Rm * a.Ro) * ts;
-  return b;
+  const size_t tsb = ((size_t)MTX * (a.TWg + 1) * ts + 15) & ~(size_t)15;   // T aliases the tiles
+  return std::max(b, tsb) + (size_t)a.Rm * a.Ro * ts;
 }
 
 // Group size of the slab kernel for a middle rank Rm and the absorbed core's
 // other rank Ro, or 0 when it does not apply.
 int xslab_group(int Rm, int Ro) {
   if (Rm < 1 || Rm > RMX || Ro < 1 || Ro > XPT) return 0;
-  return std::min(2 * UPT, TWX / Rm);
+  return std::min(NTHR / MTX * UPT, TWX / Rm);
 }
 int xslab_rows() { return MTX; }
 

@@ -743,7 +743,12 @@ int compute_mttsp(tr_als_ctx* c, int m, int prec, double* Mout, bool in_sweep = 
   hipStream_t s = c->stream;
   const Plan& p = c->plan[m];
   if (p.regime == 1) return compute_mttsp_two_stage(c, m, prec, Mout, in_sweep, after_main);
-  if (p.slab && prec != TR_FP8) return compute_mttsp_slab(c, m, prec, Mout, after_main);
+  // the slab kernel's BF16 form loads 8 consecutive elements at a time: every
+  // mode size a multiple of 8 (else BF16 takes the fused kernel); FP8 always
+  // takes the fused kernel
+  const bool slab_bf16_ok = c->N == 3 && c->dims[0] % 8 == 0 && c->dims[1] % 8 == 0 && c->dims[2] % 8 == 0;
+  if (p.slab && prec != TR_FP8 && (prec != TR_BF16 || slab_bf16_ok))
+    return compute_mttsp_slab(c, m, prec, Mout, after_main);
   int rc = build_table(c, p.f1c, p.Rmid, c->F1);
   if (rc) return rc;
   rc = build_table(c, p.f2c, p.Rmid, c->F2);

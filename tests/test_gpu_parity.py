@@ -88,6 +88,25 @@ def test_mttsp(dims, ranks, prec, xdt, tol, force_regime):
     ctx.close()
 
 
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32", 1e-5), ("bf16", 2e-2)])
+def test_slab_kernel_vector_path(prec, tol, monkeypatch):
+    """Order 3 with R_n R_{n+1} > 128 and every mode size a multiple of 8: the
+    slab kernel, whose BF16 form loads 8 elements at a time (rows i contiguous
+    for mode 1, k contiguous for modes 2 and 3) and fetches a chunk ahead."""
+    monkeypatch.setenv("TR_ALS_FORCE_REGIME", "2")
+    dims, ranks = (48, 40, 32), (12, 11, 13)
+    X, init = _data(dims, ranks, 8, np.float32)
+    ctx, _ = _ctx(to_dev_flat(X), init, dims, ranks)
+    assert all(ctx.regime(n) == 3 for n in range(1, 4))
+    Xd = X.astype(np.float64)
+    for n in range(1, 4):
+        M = ctx.mttsp(n, prec).cpu().numpy()
+        e = rel(M, O.mttsp(Xd, init, n))
+        say(f"   [slab {prec}] mode {n}: rel err {e:.3e}")
+        assert e <= tol, (n, e)
+    ctx.close()
+
+
 # ranks whose products R_nR_{n+1} give coefficient matrices of 1 to 8 blocks of
 # 16 (n = 12..128, ragged and full last blocks) for the in-register inverse
 INV_SHAPES = [
