@@ -40,6 +40,8 @@ def main():
     ap.add_argument("--no-qr", action="store_true")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the legs on the other workloads (20^4 FP64, 40^5 conditioned, 512x512x256 field)")
+    ap.add_argument("--configs", default="1,3,4",
+                    help="which of the other workloads to run (comma list of 1, 3, 4)")
     ap.add_argument("--serving-full", action="store_true",
                     help="serving leg on the full stream distribution: orders 3-5, modes 16-128, ranks 2-12, "
                          "batch lanes on")
@@ -194,7 +196,7 @@ def main():
 
     # ---- the other workloads ------------------------------------------------
     if not args.no_configs:
-        extra["other_workloads"] = config_legs()
+        extra["other_workloads"] = config_legs({int(v) for v in args.configs.split(",") if v.strip()})
 
     # ---- serving: a Poisson stream of small jobs through the request loop ---
     if not args.no_serving and args.serving_jobs > 0:
@@ -285,13 +287,13 @@ def kernel_roofline(ctx, prec, numel, C, sweeps=2):
             "unit": "GB/s" if bound == "hbm" else "TFLOP/s"}
 
 
-def config_legs():
+def config_legs(which=(1, 3, 4)):
     """Sweep times (and rooflines of the X contraction) on the other workloads:
     20^4 ranks 3 FP64 (all variants, FP64 path); the conditioned order-5 40^5
     ranks (6,8,10,8,6) (NE / QR / QRNE, BF16 and FP8 mixed schedules of 18 + 2
     FP32 finishing sweeps, final fits beside the all-FP32 schedule); the
-    512x512x256 sinusoid field at ranks 20 (FP32 vs 28 BF16 + 2 FP32).  Every
-    leg is reported, never fatal."""
+    512x512x256 sinusoid field at ranks 20 (FP32 vs 28 BF16 or 28 FP8 + 2
+    FP32).  Every leg is reported, never fatal."""
     import torch
     import workloads as W
     from paper_2210_11362_amd import TRContext
@@ -313,6 +315,16 @@ def config_legs():
             return {"error": str(e)[:240]}
 
     out = {}
+    if 1 in which:
+        out["cfg1_20x4_R3_f64"] = leg(lambda: cfg1_leg(W, TRContext, dev_flat, timed))
+    if 3 in which:
+        out["cfg3_40x5_cond1e4"] = leg(lambda: cfg3_leg(W, TRContext, dev_flat, timed, leg))
+    if 4 in which:
+        out["cfg4_512x512x256_R20"] = leg(lambda: cfg4_leg(W, TRContext, dev_flat, timed))
+    return out
+
+
+def cfg1_leg(W, TRContext, dev_flat, timed):
     w1 = W.make_workload(1)
     X1 = dev_flat(w1.X)
 
@@ -325,9 +337,10 @@ def config_legs():
             r[v] = {"ms_per_sweep": round(1000 * dt / 10, 4), "sweeps_per_s": round(10 / dt, 1), "fit": ctx.fit()}
             ctx.close()
         return r
-    out["cfg1_20x4_R3_f64"] = leg(cfg1)
-    del X1
+    return cfg1()
 
+
+def cfg3_leg(W, TRContext, dev_flat, timed, leg):
     w3 = W.make_workload(3)
     X3 = dev_flat(w3.X)
 
@@ -367,15 +380,17 @@ def config_legs():
                 ctx.close()
         r["ne_fp8_pinv_solve"] = leg(pinv_fp8)
         return r
-    out["cfg3_40x5_cond1e4"] = leg(cfg3)
-    del X3
+    return cfg3()
 
+
+def cfg4_leg(W, TRContext, dev_flat, timed):
     w4 = W.make_workload(4)
     X4 = dev_flat(w4.X)
 
     def cfg4():
         r = {"workload": "512x512x256 FP32 sinusoid field (50 terms) + 2% noise, fit ranks 20, 30 sweeps, NE"}
-        for name, plan in (("mixed", [("bf16", 28), ("f32", 2)]), ("plain", [("f32", 30)])):
+        for name, plan in (("mixed", [("bf16", 28), ("f32", 2)]), ("mixed_fp8", [("fp8", 28), ("f32", 2)]),
+                           ("plain", [("f32", 30)])):
             ctx = TRContext(X4, w4.dims, w4.ranks, [dev_flat(c) for c in w4.init_cores])
             tot = 0.0
             per = {}
@@ -389,9 +404,9 @@ def config_legs():
             ctx.close()
         r["fit_delta"] = abs(r["mixed"]["fit"] - r["plain"]["fit"])
         r["speedup_mixed_vs_plain"] = round(r["plain"]["seconds"] / r["mixed"]["seconds"], 3)
+        r["fit_delta_fp8"] = abs(r["mixed_fp8"]["fit"] - r["plain"]["fit"])
         return r
-    out["cfg4_512x512x256_R20"] = leg(cfg4)
-    return out
+    return cfg4()
 
 
 def xgemm_source_sha():
