@@ -450,8 +450,6 @@ __global__ __launch_bounds__(256) void tall_atb_lds_kernel(TallArgs g) {
       }
 }
 
-// C = sum over chunks; a block takes 64 outputs, its four waves each sum a
-// contiguous quarter of the chunks, and the quarters are added in order.
 // Gram C = A^T A of a tall column-major A (K x P, P <= 112) with no LDS
 // staging.  The MFMA fragment of a 16-column block (lane: column lane&15, rows
 // 4*(lane>>4) .. +3 of a 16-row group) is the same for both operands, so each
@@ -549,6 +547,155 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   }
 }
 
+// C (P x Q) = A^T B for two different tall operands (K rows, P, Q <= 16*NB)
+// with the MFMA fragments loaded straight into registers, as in the Gram
+// kernel above.  Element (k, p) of A sits at A[k*ks + p*ps] (column-major,
+// or the row-major layout of a first-mode unfolding), or, when L > 1, at
+// A[l + LIp*t + L*p] with k = l + L*t (mode n of a Multi-TTM result, L >= 4);
+// B is column-major (ld ldb).  The NB x NB output tiles, in column-major tile
+// order, are dealt to the four waves in runs of ceil(NB^2/4), so a wave's
+// accumulators fit its registers; every wave runs over the whole chunk (the
+// repeated fragment loads hit the caches) and stores its own tiles.  In the
+// group of 16 rows starting at row g, lane (c, kq) holds rows g + 4kq + j,
+// j = 0..3, of both operands.
+struct AtbArgs {
+  const double* A; int64_t ks, ps, L, LIp;
+  const double* B; int64_t ldb;
+  int64_t K, kc; int P, Q;
+  double* part;
+};
+
+template <int NB, int W, int G, bool LAY, bool BV>
+__device__ __forceinline__ void atb_frag_wave(const AtbArgs& g) {
+  constexpr int NT = NB * NB, TW = (NT + 3) / 4, T0 = W * TW < NT ? W * TW : NT;
+  constexpr int T1 = T0 + TW < NT ? T0 + TW : NT;
+  constexpr int NTW = T1 > T0 ? T1 - T0 : 1, BQ0 = T0 / NB, NQ = T1 > T0 ? (T1 - 1) / NB - BQ0 + 1 : 1;
+  constexpr int RS = 16 * G;   // rows per loop step
+  if (T1 <= T0) return;
+  const int lane = threadIdx.x & 63, cl = lane & 15, kq = lane >> 4;
+  const int64_t k0 = (int64_t)blockIdx.x * g.kc;
+  const int64_t k1 = min(g.K, k0 + g.kc);
+  // Columns past P or Q read column P-1 or Q-1: those rows and columns of the
+  // tiles are never stored, and the MFMA keeps them apart from the rest.
+  // Rows past the chunk read a row inside it with B's value zeroed, so every
+  // load is unconditional (no branch around it).
+  const double* acol[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) acol[b] = g.A + (int64_t)min(16 * b + cl, g.P - 1) * (LAY ? g.L : g.ps);
+  const double* bcol[NQ];
+#pragma unroll
+  for (int u = 0; u < NQ; ++u) bcol[u] = g.B + g.ldb * min(16 * (BQ0 + u) + cl, g.Q - 1);
+  f64x4 acc[NTW];
+#pragma unroll
+  for (int t = 0; t < NTW; ++t) acc[t] = f64x4{0, 0, 0, 0};
+  // G 16-row groups in registers (rows j = 4s + jj: group s, row jj of the
+  // lane), reloaded a quarter (two rows) at a time as each quarter's MFMAs
+  // are issued, so a load has 2G - 1 quarters of MFMAs to arrive.  One group
+  // measured fastest (100 x 100 result, 10^6 rows: 630-870 us against
+  // 950-1350 us for two and 720-1130 us for three).
+  double fa[NB][4 * G], fb[NQ][4 * G];
+  // per group s: the lane's first row's position in the layout (l, and the
+  // element offset ro = l + LIp*t, or row*ks), advanced with the rows; L is
+  // below 2^31 here, so l and the wrap count are 32-bit
+  uint32_t lg[G];
+  int64_t rg[G];
+#pragma unroll
+  for (int sg = 0; sg < G; ++sg) {
+    const int64_t r0 = k0 + 16 * sg + 4 * kq;
+    if (LAY) { lg[sg] = (uint32_t)(r0 % g.L); rg[sg] = lg[sg] + g.LIp * (r0 / g.L); }
+    else { lg[sg] = 0; rg[sg] = r0 * g.ks; }
+  }
+  auto load = [&](int64_t gg, int q) {
+    const int sg = q >> 1, h = q & 1;
+    const int64_t rb = gg + 16 * sg + 4 * kq;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int jj = 2 * h + e;
+      const int64_t r = rb + jj;
+      int64_t ro;
+      if (LAY) ro = rg[sg] + jj + ((int64_t)lg[sg] + jj >= g.L ? g.LIp - g.L : 0);
+      else ro = rg[sg] + jj * g.ks;
+      ro = r < k1 ? ro : 0;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) fa[b][4 * sg + jj] = acol[b][ro];
+    }
+    if (BV) {   // ldb and the chunk ends even: rows rb + 2h, +1 are in or out together
+      const int64_t r = rb + 2 * h;
+      const double m = r < k1 ? 1.0 : 0.0;
+      const int64_t rc = r < k1 ? r : k0;
+#pragma unroll
+      for (int u = 0; u < NQ; ++u) {
+        const double2 v = *reinterpret_cast<const double2*>(bcol[u] + rc);
+        fb[u][4 * sg + 2 * h] = m * v.x;
+        fb[u][4 * sg + 2 * h + 1] = m * v.y;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int64_t r = rb + 2 * h + e;
+        const double m = r < k1 ? 1.0 : 0.0;
+        const int64_t rc = r < k1 ? r : k0;
+#pragma unroll
+        for (int u = 0; u < NQ; ++u) fb[u][4 * sg + 2 * h + e] = m * bcol[u][rc];
+      }
+    }
+  };
+  auto mfma = [&](int q) {
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+#pragma unroll
+      for (int t = T0; t < T1; ++t) mma64(acc[t - T0], fa[t % NB][2 * q + e], fb[t / NB - BQ0][2 * q + e]);
+  };
+  int64_t gg = k0;
+#pragma unroll
+  for (int q = 0; q < 2 * G; ++q) load(gg, q);
+  // past the chunk end the loads are redirected as above, so the loop has no
+  // branches around them
+  for (; gg < k1; gg += RS) {
+#pragma unroll
+    for (int sg = 0; sg < G; ++sg) {
+      if (LAY) {   // advance RS rows: w wraps of l past L, each a step of LIp - L
+        const uint32_t L32 = (uint32_t)g.L, w = (lg[sg] + (uint32_t)RS) / L32;
+        lg[sg] = lg[sg] + (uint32_t)RS - w * L32;
+        rg[sg] += RS + (int64_t)w * (g.LIp - g.L);
+      } else {
+        rg[sg] += RS * g.ks;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 2 * G; ++q) {
+      mfma(q);
+      load(gg + RS, q);
+    }
+  }
+  double* out = g.part + (size_t)blockIdx.x * g.P * g.Q;
+#pragma unroll
+  for (int t = T0; t < T1; ++t) {
+    const int bp = t % NB, bq = t / NB;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = bp * 16 + (lane >> 4) + 4 * v, col = bq * 16 + cl;
+      if (row < g.P && col < g.Q) out[row + (int64_t)g.P * col] = acc[t - T0][v];
+    }
+  }
+}
+
+// Row groups held per wave and workgroups (row chunks) per launch of
+// atb_frag_kernel.
+constexpr int ATB_G = 1, ATB_CHUNKS = 512;
+
+template <int NB, bool LAY, bool BV>
+__global__ __launch_bounds__(256) void atb_frag_kernel(AtbArgs g) {
+  switch (threadIdx.x >> 6) {
+    case 0: atb_frag_wave<NB, 0, ATB_G, LAY, BV>(g); break;
+    case 1: atb_frag_wave<NB, 1, ATB_G, LAY, BV>(g); break;
+    case 2: atb_frag_wave<NB, 2, ATB_G, LAY, BV>(g); break;
+    default: atb_frag_wave<NB, 3, ATB_G, LAY, BV>(g); break;
+  }
+}
+
+// C = sum over chunks; a block takes 64 outputs, its four waves each sum a
+// contiguous quarter of the chunks, and the quarters are added in order.
 __global__ __launch_bounds__(256) void sum_chunks_kernel(const double* part, int nchunk, int64_t n, double* C) {
   __shared__ double red[4][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -708,114 +855,146 @@ __global__ __launch_bounds__(256) void table_to_v2_tiled_kernel(const double* T,
 // Batched C_b = scale * A_b B for tall A_b (M x K) and a small B (K x N, ld
 // ldb), K, N <= 16*NB.  Element (m, k) of A_b sits at A[b*sa + m*rs + k*ks]
 // and (m, n) of C_b at C[b*sc + m*crs + n*cns]: a column-major matrix, one
-// t-slice of a mode product, or the row-major first-mode product.  Each wave
-// keeps its 16-column tiles of B as MFMA fragments in registers for the whole
-// launch; blocks stride over 64-row slabs, staged through LDS with lanes
-// along the rows (KFAST: along k, for row-major slabs).  The MFMA forms
-// C^T = B^T A^T so a store covers 16 consecutive rows.  Step (j, e) takes
-// from lane group kq the inner index k = 8j + 2kq + e.
+// t-slice of a mode product, or the row-major first-mode product.  B is
+// staged once per workgroup in LDS as [n][k]; each wave then takes 16-row
+// tiles of the batches' rows laid end to end (a tile may span two batches)
+// with no further barrier: the tile's A fragments come straight from memory
+// into registers, the next tile's while the current one's MFMAs run, and the
+// wave forms all the column tiles of C for its rows.  With column-major C
+// the MFMA forms C^T = B^T A^T, so a store covers 16 consecutive rows; with
+// row-major C (ROWOUT) it forms C = A B, so a store covers 16 consecutive
+// columns.  Step (j, e) takes from lane group kq the inner index
+// k = 8j + 2kq + e; k past K reads A at k = K-1 against zero rows of B.
 struct TGArgs {
   const void* A; int64_t rs, ks, sa, M; int K;
   const double* B; int ldb, N;
   double* C; int64_t crs, cns, sc, nbatch;
   double scale;
 };
-constexpr int TG_ROWS = 64;
-template <int NB, bool KFAST, typename Tin>
-__global__ __launch_bounds__(256) void tall_gemm_kernel(TGArgs g) {
-  constexpr int KJ = 2 * NB, CT = (NB + 3) / 4, AP = 16 * NB + 2, NL = 16 * NB / 4;
-  extern __shared__ __align__(16) double tsm[];
+constexpr int TG_WAVES = 4;
+template <int NB, bool ROWOUT, typename Tin>
+__global__ __launch_bounds__(64 * TG_WAVES) void tall_gemm_kernel(TGArgs g) {
+  constexpr int NP = 16 * NB, BST = NP + 2, KJ = 2 * NB;
+  extern __shared__ __align__(16) double tsm[];   // B as [n][k], NP x BST
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int cl = lane & 15, kq = lane >> 4;
   const int K = g.K, N = g.N;
-  const int nbn = (N + 15) / 16;
-  double2 bf[CT][KJ];
-#pragma unroll
-  for (int ct = 0; ct < CT; ++ct)
+  for (int e = tid; e < NP * NP; e += 64 * TG_WAVES) {
+    const int n = e / NP, k = e % NP;
+    tsm[n * BST + k] = (n < N && k < K) ? g.B[k + (int64_t)g.ldb * n] : 0.0;
+  }
+  __syncthreads();
+  const Tin* A = static_cast<const Tin*>(g.A);
+  const int64_t rows = g.M * g.nbatch, ntile = (rows + 15) / 16;
+  const int64_t wstride = (int64_t)gridDim.x * TG_WAVES;
+  double2 cur[KJ], nxt[KJ];
+  // A fragments of the tile's rows (row tile*16 + cl of the lane; rows past
+  // the end read the last row and are not stored)
+  auto load = [&](int64_t tile, double2* f) {
+    const int64_t r = min(tile * 16 + cl, rows - 1);
+    const int64_t b = r / g.M, m = r - b * g.M;
+    const Tin* ab = A + b * g.sa + m * g.rs;
 #pragma unroll
     for (int j = 0; j < KJ; ++j) {
-      const int n = (wave + 4 * ct) * 16 + (lane & 15), k = 8 * j + 2 * (lane >> 4);
-      const bool nin = n < N;
-      const double* bp = g.B + (int64_t)g.ldb * min(n, N - 1);
-      bf[ct][j].x = (nin && k < K) ? bp[min(k, K - 1)] : 0.0;
-      bf[ct][j].y = (nin && k + 1 < K) ? bp[min(k + 1, K - 1)] : 0.0;
-    }
-  const Tin* A = static_cast<const Tin*>(g.A);
-  double ra[NL];
-  const int64_t spb = (g.M + TG_ROWS - 1) / TG_ROWS, nslab = spb * g.nbatch;
-  auto load = [&](int64_t slab) {
-    const int64_t b = slab / spb, r0 = (slab % spb) * TG_ROWS;
-    const Tin* ab = A + b * g.sa;
-#pragma unroll
-    for (int i = 0; i < NL; ++i) {
-      const int e = tid + 256 * i;
-      const int m = KFAST ? e / (16 * NB) : e % TG_ROWS;
-      const int k = KFAST ? e % (16 * NB) : e / TG_ROWS;
-      const int64_t r = r0 + m;
-      const double v = ttm_in(ab + g.rs * (r < g.M ? r : g.M - 1) + g.ks * min(k, K - 1));
-      ra[i] = (r < g.M && k < K) ? v : 0.0;
+      const int k = 8 * j + 2 * kq;
+      f[j].x = ttm_in(ab + g.ks * min(k, K - 1));
+      f[j].y = ttm_in(ab + g.ks * min(k + 1, K - 1));
     }
   };
-  int64_t slab = blockIdx.x;
-  if (slab < nslab) load(slab);
-  for (; slab < nslab; slab += gridDim.x) {
-    const int64_t b = slab / spb, r0 = (slab % spb) * TG_ROWS;
-    __syncthreads();
+  int64_t tile = (int64_t)blockIdx.x * TG_WAVES + wave;
+  if (tile < ntile) load(tile, cur);
+  for (; tile < ntile; tile += wstride) {
+    const int64_t tn = tile + wstride;
+    load(tn < ntile ? tn : tile, nxt);
+    f64x4 acc[NB];
 #pragma unroll
-    for (int i = 0; i < NL; ++i) {
-      const int e = tid + 256 * i;
-      const int m = KFAST ? e / (16 * NB) : e % TG_ROWS;
-      const int k = KFAST ? e % (16 * NB) : e / TG_ROWS;
-      tsm[m * AP + k] = ra[i];
-    }
-    __syncthreads();
-    if (slab + gridDim.x < nslab) load(slab + gridDim.x);
-    double* cb = g.C + b * g.sc;
+    for (int ct = 0; ct < NB; ++ct) acc[ct] = f64x4{0, 0, 0, 0};
+    // all 16*NB values of k and of n (padding is zero in B): fixed trip
+    // counts keep the fragments in fixed registers.  The B fragments of step
+    // j + 1 are read from LDS while step j's MFMAs run.
+    double2 bv[2][NB];
 #pragma unroll
-    for (int ct = 0; ct < CT; ++ct) {
-      const int c = wave + 4 * ct;
-      if (c >= nbn) continue;
-      f64x4 acc[4];
+    for (int ct = 0; ct < NB; ++ct)
+      bv[0][ct] = *reinterpret_cast<const double2*>(tsm + (16 * ct + cl) * BST + 2 * kq);
 #pragma unroll
-      for (int rt = 0; rt < 4; ++rt) acc[rt] = f64x4{0, 0, 0, 0};
+    for (int j = 0; j < KJ; ++j) {
+      if (j + 1 < KJ) {
 #pragma unroll
-      for (int j = 0; j < KJ; ++j) {
-        double2 av[4];
-#pragma unroll
-        for (int rt = 0; rt < 4; ++rt)
-          av[rt] = *reinterpret_cast<const double2*>(tsm + (rt * 16 + (lane & 15)) * AP + 8 * j + 2 * (lane >> 4));
-#pragma unroll
-        for (int rt = 0; rt < 4; ++rt) mma64(acc[rt], bf[ct][j].x, av[rt].x);
-#pragma unroll
-        for (int rt = 0; rt < 4; ++rt) mma64(acc[rt], bf[ct][j].y, av[rt].y);
+        for (int ct = 0; ct < NB; ++ct)
+          bv[(j + 1) & 1][ct] =
+              *reinterpret_cast<const double2*>(tsm + (16 * ct + cl) * BST + 8 * (j + 1) + 2 * kq);
       }
 #pragma unroll
-      for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int64_t r = r0 + rt * 16 + (lane & 15);
-          const int n = c * 16 + (lane >> 4) + 4 * v;
-          if (r < g.M && n < N) cb[r * g.crs + (int64_t)n * g.cns] = g.scale * acc[rt][v];
+      for (int ct = 0; ct < NB; ++ct) {
+        const double2 b = bv[j & 1][ct];
+        if (ROWOUT) {
+          mma64(acc[ct], cur[j].x, b.x);
+          mma64(acc[ct], cur[j].y, b.y);
+        } else {
+          mma64(acc[ct], b.x, cur[j].x);
+          mma64(acc[ct], b.y, cur[j].y);
         }
+      }
+      // keep later steps' LDS reads from being hoisted over these MFMAs (all
+      // of them at once would not fit the registers)
+      __builtin_amdgcn_sched_barrier(0);
     }
+    if (ROWOUT) {   // lane: rows tile*16 + kq + 4v, column 16ct + cl
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = tile * 16 + kq + 4 * v;
+        if (r < rows) {
+          const int64_t b = r / g.M, m = r - b * g.M;
+          double* cb = g.C + b * g.sc + m * g.crs;
+#pragma unroll
+          for (int ct = 0; ct < NB; ++ct) {
+            const int n = 16 * ct + cl;
+            if (n < N) cb[(int64_t)n * g.cns] = g.scale * acc[ct][v];
+          }
+        }
+      }
+    } else {        // lane: row tile*16 + cl, columns 16ct + kq + 4v
+      const int64_t r = tile * 16 + cl;
+      if (r < rows) {
+        const int64_t b = r / g.M, m = r - b * g.M;
+        double* cb = g.C + b * g.sc + m * g.crs;
+#pragma unroll
+        for (int ct = 0; ct < NB; ++ct)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int n = 16 * ct + kq + 4 * v;
+            if (n < N) cb[(int64_t)n * g.cns] = g.scale * acc[ct][v];
+          }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < KJ; ++j) cur[j] = nxt[j];
   }
 }
 
 template <typename Tin>
 hipError_t launch_tg(const TGArgs& g, hipStream_t s) {
   const int nb = max((g.K + 15) / 16, (g.N + 15) / 16);
-  const bool kfast = g.rs != 1 && g.ks == 1;
+  const bool rowout = g.cns == 1 && g.crs != 1;
   if (g.M <= 0 || g.K <= 0 || g.N <= 0 || g.nbatch <= 0 || nb > 7) return hipErrorInvalidValue;
-  const size_t lds = (size_t)TG_ROWS * (16 * nb + 2) * sizeof(double);
-  const int64_t nslab = (g.M + TG_ROWS - 1) / TG_ROWS * g.nbatch;
-  const dim3 grid((unsigned)std::min<int64_t>(nslab, 512));
-  switch (nb * 2 + (kfast ? 1 : 0)) {
+  const size_t lds = (size_t)16 * nb * (16 * nb + 2) * sizeof(double);
+  const int64_t ntile = (g.M * g.nbatch + 15) / 16;
+  const dim3 grid((unsigned)std::min<int64_t>((ntile + TG_WAVES - 1) / TG_WAVES, 256));
+  const void* k = nullptr;
+  switch (nb * 2 + (rowout ? 1 : 0)) {
 #define TG_CASE(NBV) \
-  case 2 * NBV: hipLaunchKernelGGL((tall_gemm_kernel<NBV, false, Tin>), grid, dim3(256), lds, s, g); break; \
-  case 2 * NBV + 1: hipLaunchKernelGGL((tall_gemm_kernel<NBV, true, Tin>), grid, dim3(256), lds, s, g); break;
+  case 2 * NBV: k = (const void*)tall_gemm_kernel<NBV, false, Tin>; break; \
+  case 2 * NBV + 1: k = (const void*)tall_gemm_kernel<NBV, true, Tin>; break;
     TG_CASE(1) TG_CASE(2) TG_CASE(3) TG_CASE(4) TG_CASE(5) TG_CASE(6) TG_CASE(7)
 #undef TG_CASE
   }
-  return hipGetLastError();
+  if (lds > 64 * 1024) {
+    const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  TGArgs a = g;
+  void* args[] = {(void*)&a};
+  return hipLaunchKernel(k, grid, dim3(64 * TG_WAVES), args, lds, s);
 }
 
 // core[a + Ra*(i + I*b)] = G2[i + I*(a + Ra*b)]  (inverse of the mode-2 unfolding)
@@ -899,6 +1078,37 @@ hipError_t launch_tall_atb(const double* A, int64_t lda, const double* B, int64_
     hipLaunchKernelGGL(sum_chunks_kernel, dim3(cdiv(n, 64)), dim3(256), 0, s, (const double*)part, (int)nchunk, n, C);
     return hipGetLastError();
   }
+  // two operands, fragments in registers: A strided (plain, a first-mode or
+  // last-mode unfolding) or in the Multi-TTM layout with L >= 4
+  AtbArgs fa{A, 1, lda, 1, 0, B, ldb, K, 0, P, Q, part};
+  bool frag = !gram && nb <= 7 && P > 0 && Q > 0;
+  if (mode == 1) {
+    if (L == 1) { fa.ks = Ip; fa.ps = 1; }
+    else if (T == 1) { fa.ks = 1; fa.ps = L; }
+    else if (L >= 4 && L < ((int64_t)1 << 31)) { fa.L = L; fa.LIp = L * Ip; fa.ps = L; }
+    else frag = false;
+  }
+  if (frag) {
+    nchunk = std::min<int64_t>(nchunk, ATB_CHUNKS);
+    fa.kc = cdiv(cdiv(K, nchunk), 16 * ATB_G) * (16 * ATB_G);
+    nchunk = cdiv(K, fa.kc);
+    const size_t lds = 0;
+    const bool bv = ldb % 2 == 0 && K % 2 == 0 && (reinterpret_cast<uintptr_t>(B) & 15) == 0;
+    const dim3 grid((unsigned)nchunk);
+    switch (nb * 4 + (fa.L > 1 ? 2 : 0) + (bv ? 1 : 0)) {
+#define ATB_FRAG(NBV) \
+  case 4 * NBV: hipLaunchKernelGGL((atb_frag_kernel<NBV, false, false>), grid, dim3(256), lds, s, fa); break; \
+  case 4 * NBV + 1: hipLaunchKernelGGL((atb_frag_kernel<NBV, false, true>), grid, dim3(256), lds, s, fa); break; \
+  case 4 * NBV + 2: hipLaunchKernelGGL((atb_frag_kernel<NBV, true, false>), grid, dim3(256), lds, s, fa); break; \
+  case 4 * NBV + 3: hipLaunchKernelGGL((atb_frag_kernel<NBV, true, true>), grid, dim3(256), lds, s, fa); break;
+      ATB_FRAG(1) ATB_FRAG(2) ATB_FRAG(3) ATB_FRAG(4) ATB_FRAG(5) ATB_FRAG(6) ATB_FRAG(7)
+#undef ATB_FRAG
+      default: return hipErrorInvalidValue;
+    }
+    const int64_t n = (int64_t)P * Q;
+    hipLaunchKernelGGL(sum_chunks_kernel, dim3(cdiv(n, 64)), dim3(256), 0, s, (const double*)part, (int)nchunk, n, C);
+    return hipGetLastError();
+  }
   const size_t lds = (size_t)(gram ? 1 : 2) * nb * 16 * GST * sizeof(double);
   if (nb <= 8 && lds <= 64 * 1024) {   // LDS-staged slabs
     g.kc = cdiv(cdiv(K, nchunk), GKS) * GKS;
@@ -933,7 +1143,7 @@ hipError_t launch_tall_atb(const double* A, int64_t lda, const double* B, int64_
 
 hipError_t launch_ttm(const void* in, int in_type, int64_t L, int64_t I, int64_t T, const double* Q, int R,
                       double scale, double* out, hipStream_t s) {
-  if (I <= 112 && R <= 112 && (L == 1 || L >= TG_ROWS)) {   // MFMA slabs
+  if (I <= 112 && R <= 112 && (L == 1 || L >= 16)) {   // MFMA tiles
     TGArgs g;
     if (L == 1) g = TGArgs{in, I, 1, 0, T, (int)I, Q, (int)I, R, out, R, 1, 0, 1, scale};
     else g = TGArgs{in, 1, L, L * I, L, (int)I, Q, (int)I, R, out, 1, L, L * R, T, scale};
