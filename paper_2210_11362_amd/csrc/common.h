@@ -187,6 +187,11 @@ hipError_t launch_transpose(const double* A, int64_t rows, int64_t cols, double*
 hipError_t launch_tall_gemm(const double* A, int64_t lda, int64_t M, int K, const double* B, int ldb, int N,
                             double* C, int64_t ldc, hipStream_t s);
 hipError_t launch_table_to_v2(const double* T, int64_t J, int64_t L, int Ra, int Rb, double* V2, hipStream_t s);
+// V2[k' + J*(a + Ra*b)] = sum_m Tp[j][b + Rb*m] core[m + Rm*(i + I*a)] with
+// j + Jp*i the subchain row of Multi-TTM row k' (J = Jp*I, L rows before n).
+hipError_t launch_v2_direct(const double* Tp, int64_t Jp, const double* core, int64_t I, int Rm, int Ra, int Rb,
+                            int64_t L, double* V2, hipStream_t s);
+inline bool v2_direct_fits(int Rm, int Ra, int Rb) { return ((Rb * Rm + Rm * Ra) | 1) * 8 <= 64 * 1024; }
 hipError_t launch_shift_and_add(double* G, int n, int64_t m, double* sbuf, hipStream_t s);
 hipError_t launch_core_fold(const double* G2, int64_t I, int Ra, int Rb, double* core, hipStream_t s);
 hipError_t launch_chol_inv(const double* S, int n, double* L, double* LT, double* LinvT, double* work, int* status,

@@ -852,6 +852,45 @@ __global__ __launch_bounds__(256) void table_to_v2_tiled_kernel(const double* T,
   }
 }
 
+// The last step of the subchain written straight in the V_n[2] layout: row
+// k' of V2 (Multi-TTM order) is table row src = v2_src_row(k') = j + Jp*i of
+// the full subchain, whose entry is Tp[j] (Rb x Rm, the subchain without its
+// last core) times the slice i of the last core (Rm x Ra):
+//   V2[k' + J*(a + Ra*b)] = sum_m Tp[j][b + Rb*m] * core[m + Rm*(i + I*a)],
+// summed over m in increasing order (the chain step's order, so the values
+// are those of the two-pass build).  A block stages ROWS rows' operands in
+// LDS, then each thread forms outputs of one row, a column at a time, so
+// consecutive lanes write consecutive rows of a column.
+__global__ __launch_bounds__(256) void v2_direct_kernel(const double* Tp, int64_t Jp, const double* core, int64_t I,
+                                                        int Rm, int Ra, int Rb, int64_t L, int rows, double* V2) {
+  extern __shared__ __align__(16) double vds[];
+  const int tc = Rb * Rm, gc = Rm * Ra, pitch = (tc + gc) | 1;   // odd pitch: rows spread over the banks
+  const int64_t J = Jp * I, C = (int64_t)Ra * Rb;
+  const int64_t k0 = (int64_t)blockIdx.x * rows;
+  const int nk = (int)min<int64_t>(rows, J - k0);
+  for (int kl = threadIdx.x / 64; kl < nk; kl += 4) {   // one wave per row
+    const int64_t src = v2_src_row(k0 + kl, J, L), j = src % Jp, i = src / Jp;
+    double* d = vds + (int64_t)kl * pitch;
+    const double* tp = Tp + j * tc;
+    for (int e = threadIdx.x & 63; e < tc; e += 64) d[e] = tp[e];
+    for (int e = threadIdx.x & 63; e < gc; e += 64) {
+      const int m = e % Rm, a = e / Rm;
+      d[tc + e] = core[m + Rm * (i + I * a)];
+    }
+  }
+  __syncthreads();
+  const int kl = threadIdx.x % rows, nq = 256 / rows;
+  if (kl >= nk) return;
+  const double* t = vds + (int64_t)kl * pitch;
+  const double* gsl = t + tc;
+  for (int64_t col = threadIdx.x / rows; col < C; col += nq) {
+    const int a = (int)(col % Ra), b = (int)(col / Ra);
+    double acc = 0.0;
+    for (int m = 0; m < Rm; ++m) acc += t[b + Rb * m] * gsl[m + Rm * a];
+    V2[k0 + kl + J * col] = acc;
+  }
+}
+
 // Batched C_b = scale * A_b B for tall A_b (M x K) and a small B (K x N, ld
 // ldb), K, N <= 16*NB.  Element (m, k) of A_b sits at A[b*sa + m*rs + k*ks]
 // and (m, n) of C_b at C[b*sc + m*crs + n*cns]: a column-major matrix, one
@@ -1204,6 +1243,19 @@ hipError_t launch_table_to_v2(const double* T, int64_t J, int64_t L, int Ra, int
     return hipGetLastError();
   }
   hipLaunchKernelGGL(table_to_v2_kernel, dim3(cdiv(J * Ra * Rb, 256)), dim3(256), 0, s, T, J, L, Ra, Rb, V2);
+  return hipGetLastError();
+}
+
+hipError_t launch_v2_direct(const double* Tp, int64_t Jp, const double* core, int64_t I, int Rm, int Ra, int Rb,
+                            int64_t L, double* V2, hipStream_t s) {
+  const int64_t J = Jp * I;
+  if (Jp <= 0 || I <= 0 || Rm <= 0 || Ra <= 0 || Rb <= 0 || L <= 0 || J % L != 0) return hipErrorInvalidValue;
+  if (!v2_direct_fits(Rm, Ra, Rb)) return hipErrorInvalidValue;
+  const size_t row_bytes = (size_t)((Rb * Rm + Rm * Ra) | 1) * sizeof(double);
+  int rows = 32;
+  while (rows > 1 && rows * row_bytes > 60 * 1024) rows /= 2;
+  hipLaunchKernelGGL(v2_direct_kernel, dim3((unsigned)cdiv(J, rows)), dim3(256), rows * row_bytes, s, Tp, Jp, core, I,
+                     Rm, Ra, Rb, L, rows, V2);
   return hipGetLastError();
 }
 

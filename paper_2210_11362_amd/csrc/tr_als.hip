@@ -1185,11 +1185,23 @@ int build_v2(tr_als_ctx* c, int m, int64_t* Jp_out) {
   for (int k = 1; k < N; ++k) chain.push_back((m + k) % N);
   int64_t Jp = 1;
   for (int j : chain) Jp *= c->qr_r[j];
-  int rc = build_table_ex(c, chain, c->R[m + 1], c->qT, c->qR, c->qr_r, c->qY0, c->qY1);
-  if (rc) return rc;
   int64_t Lrows = 1;
   for (int j = 0; j < m; ++j) Lrows *= c->qr_r[j];
-  HIPCHK(c, launch_table_to_v2(c->qT, Jp, Lrows, c->R[m], c->R[m + 1], c->qV2, c->stream));
+  const int last = chain.back();
+  if (!v2_direct_fits(c->R[last], c->R[m], c->R[m + 1])) {   // full table, then reordered
+    int rc = build_table_ex(c, chain, c->R[m + 1], c->qT, c->qR, c->qr_r, c->qY0, c->qY1);
+    if (rc) return rc;
+    HIPCHK(c, launch_table_to_v2(c->qT, Jp, Lrows, c->R[m], c->R[m + 1], c->qV2, c->stream));
+    *Jp_out = Jp;
+    return TR_OK;
+  }
+  // the subchain without its last core as a table, then the last step
+  // written straight in the V_n[2] layout
+  chain.pop_back();
+  int rc = build_table_ex(c, chain, c->R[m + 1], c->qT, c->qR, c->qr_r, c->qY0, c->qY1);
+  if (rc) return rc;
+  HIPCHK(c, launch_v2_direct(c->qT, Jp / c->qr_r[last], c->qR[last], c->qr_r[last], c->R[last], c->R[m], c->R[m + 1],
+                             Lrows, c->qV2, c->stream));
   *Jp_out = Jp;
   return TR_OK;
 }
@@ -1197,7 +1209,11 @@ int build_v2(tr_als_ctx* c, int m, int64_t* Jp_out) {
 // One QR-variant mode update (Alg. 3): V_n = subchain of the R-cores; QR of
 // V_n[2] = Q_0 R_[2] by shifted Cholesky-QR (three passes); Y = X x_{j!=n} Q_j^T
 // (most-compressing mode first); W_n = Y_[n] Q_0; G_n(2) R_[2]^T = W_n by
-// substitution; commit; re-factor core n.
+// substitution; commit; re-factor core n and refresh its R-core Gram.  The
+// first pass's Gram V_n[2]^T V_n[2] is the ring product of the R-cores' Grams
+// (Prop. 3.1 applied to the R-cores), as in Alg. 4: only its Cholesky factor,
+// taken with the shift, enters, as a preconditioner; the second and third
+// passes form their Grams from the rows.
 // The same update for n = R_n R_{n+1} > 128, its large products on rocBLAS:
 // the Grams split over chunks of rows, the shifted Cholesky-QR passes
 // A <- A L^{-T} as in-place triangular solves with the blocked Cholesky factor
@@ -1212,7 +1228,8 @@ int update_mode_qr_large(tr_als_ctx* c, int m, int prec, int64_t Jp) {
   if (rc) return rc;
   double* A = c->qV2;   // V_n[2], orthogonalised in place (two passes; Q_0 = A L_3^{-T})
   for (int it = 0; it < 3; ++it) {
-    rc = blas_long_product(c, true, A, Jp, A, Jp, Jp, n, n, c->qG, s);
+    // first pass: V_n[2]^T V_n[2] from the ring of the R-cores' Grams
+    rc = it == 0 ? compute_coef(c, m, c->qG, s) : blas_long_product(c, true, A, Jp, A, Jp, Jp, n, n, c->qG, s);
     if (rc) return rc;
     if (it == 0) HIPCHK(c, launch_shift_and_add(c->qG, n, Jp, c->qshift, s));
     rc = chol_lower_blocked(c, c->qG, n, c->qL[it], c->qLT, s);
@@ -1243,7 +1260,10 @@ int update_mode_qr_large(tr_als_ctx* c, int m, int prec, int64_t Jp) {
   BLASCHK(c, rocblas_dtrsm(c->blas, rocblas_side_right, rocblas_fill_lower, rocblas_operation_none,
                            rocblas_diagonal_non_unit, (int)I, n, &one, c->qLt, n, c->Gn, (int)I));
   HIPCHK(c, launch_commit_core(c->Gn, I, Ra, Rb, c->cores[m], c->status, s));
-  return qr_core(c, m);
+  rc = qr_core(c, m);
+  if (rc) return rc;
+  HIPCHK(c, launch_gram(c->qR[m], Ra, c->qr_r[m], Rb, c->gram[m], s));
+  return TR_OK;
 }
 
 int update_mode_qr(tr_als_ctx* c, int m, int prec) {
@@ -1260,7 +1280,12 @@ int update_mode_qr(tr_als_ctx* c, int m, int prec) {
   double* A = c->qV2;
   double* bufs[2] = {c->qQa, c->qQb};
   for (int it = 0; it < 3; ++it) {
-    HIPCHK(c, launch_tall_atb(A, Jp, A, Jp, Jp, n, n, 0, 1, 1, 1, c->qpart, c->qpart_elems, c->qG, s));
+    if (it == 0) {   // V_n[2]^T V_n[2] from the ring of the R-cores' Grams
+      rc = compute_coef(c, m, c->qG, s);
+      if (rc) return rc;
+    } else {
+      HIPCHK(c, launch_tall_atb(A, Jp, A, Jp, Jp, n, n, 0, 1, 1, 1, c->qpart, c->qpart_elems, c->qG, s));
+    }
     if (it == 0) HIPCHK(c, launch_shift_and_add(c->qG, n, Jp, c->qshift, s));
     HIPCHK(c, launch_chol_lds(c->qG, n, c->qL[it], c->qLT, c->rdiag, c->status, s));
     if (it == 2) break;   // Q_0 = A L_3^{-T} is applied to W_n instead
@@ -1289,7 +1314,10 @@ int update_mode_qr(tr_als_ctx* c, int m, int prec) {
   // G_n(2) = W_n R^{-T}: backward substitution with L = R^T
   HIPCHK(c, launch_trsm_rhs(c->qLt, nullptr, n, c->qW, c->dims[m], c->Gn, 0, c->status, s, 2));
   HIPCHK(c, launch_commit_core(c->Gn, c->dims[m], Ra, Rb, c->cores[m], c->status, s));
-  return qr_core(c, m);
+  rc = qr_core(c, m);
+  if (rc) return rc;
+  HIPCHK(c, launch_gram(c->qR[m], Ra, c->qr_r[m], Rb, c->gram[m], s));
+  return TR_OK;
 }
 
 // One QRNE mode update (Alg. 4): S_n from the ring of the R-cores' Grams and
@@ -1653,7 +1681,7 @@ int trx_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ranks,
     for (int k = 0; k < N && rc == TR_OK; ++k) rc = qr_core(c, k);
     if (rc) { tr_als_destroy(c); return rc; }
   }
-  if (variant == TR_QRNE)   // Alg. 4 keeps the Grams of the R-cores
+  if (variant == TR_QR || variant == TR_QRNE)   // kept as the Grams of the R-cores
     for (int k = 0; k < N; ++k)
       if (hipfail(launch_gram(c->qR[k], c->R[k], c->qr_r[k], c->R[k + 1], c->gram[k], s), "gram")) {
         tr_als_destroy(c);
@@ -2077,12 +2105,6 @@ int tr_als_set_solve(tr_als_ctx* c, int solve, double rcond) {
   for (int m = 0; m < c->N; ++m)
     if (solve == TR_SOLVE_PINV && !pinv_fits(c->R[m] * c->R[m + 1]))
       return fail(c, TR_EINVAL, "R_n R_{n+1} too large for the pseudo-inverse");
-  if (solve == TR_SOLVE_PINV && c->variant == TR_QR && c->solve != TR_SOLVE_PINV) {
-    // the QR context's Grams were formed from the initial cores only: refresh
-    // them from the current R-cores for Alg. 4's route
-    for (int k = 0; k < c->N; ++k)
-      HIPCHK(c, launch_gram(c->qR[k], c->R[k], c->qr_r[k], c->R[k + 1], c->gram[k], c->stream));
-  }
   c->solve = solve;
   c->rcond = rcond;
   // captured sweeps embed the solve: drop them

@@ -325,6 +325,12 @@ void check_extents(const std::string& full, const std::string& nm, void** a, std
     r->push_back({D(2), 8, "out"});
   } else if (nm == "zero_double_kernel") {   // (out)
     r->push_back({D(0), 8, "out"});
+  } else if (nm == "v2_direct_kernel") {   // (Tp, Jp, core, I, Rm, Ra, Rb, L, rows, V2)
+    const int64_t Jp = L(1), In = L(3), Rm = I(4), Ra = I(5), Rb = I(6), rows = I(8);
+    r->push_back({D(0), (size_t)(Jp * Rb * Rm * 8), "Tp"});
+    r->push_back({D(2), (size_t)(Rm * In * Ra * 8), "core"});
+    r->push_back({D(9), (size_t)(Jp * In * Ra * Rb * 8), "V2"});
+    if (rows < 1 || 256 % rows != 0) viol("v2_direct_kernel: rows %lld does not divide the block", (long long)rows);
   } else if (nm == "slice_transpose_kernel") {   // (in, L, I, T, out)
     const size_t b = (size_t)(L(1) * L(2) * L(3) * 8);
     r->push_back({D(0), b, "in"});
