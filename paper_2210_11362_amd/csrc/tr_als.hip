@@ -73,6 +73,10 @@ struct tr_als_ctx {
   int64_t qr_r[TR_MAXN] = {0};
   double *qA = nullptr, *qV = nullptr, *qtau = nullptr, *qRt = nullptr;
   double *qT = nullptr, *qV2 = nullptr, *qQa = nullptr, *qQb = nullptr, *qY0 = nullptr, *qY1 = nullptr, *qW = nullptr;
+  // Multi-TTM part shared by a pair of modes within a sweep (see multi_ttm_y)
+  double* qZ = nullptr;
+  int z_pair = -1, z_prec = -1;
+  int64_t z_cd[TR_MAXN] = {};
   double *qG = nullptr, *qL[3] = {nullptr, nullptr, nullptr}, *qLT = nullptr, *qRi = nullptr, *qLp = nullptr,
          *qLt = nullptr, *qshift = nullptr, *qpart = nullptr;
   int64_t qpart_elems = 0;
@@ -1117,15 +1121,62 @@ int qr_core(tr_als_ctx* c, int k) {
   return TR_OK;
 }
 
+// One mode product out = cur x_j Q_j^T of the Multi-TTM (cd: the extents of
+// cur, updated); cur is in type ctype, scaled by scale on the way in.
+int ttm_step(tr_als_ctx* c, const void* cur, int ctype, double scale, int j, int64_t* cd, double* out) {
+  hipStream_t s = c->stream;
+  const int N = c->N;
+  const int64_t L = prod(cd, 0, j), T = prod(cd, j + 1, N);
+  const int64_t I = c->dims[j], R = c->qr_r[j];
+  if (ctype == TR_F64 && scale == 1.0 && (I > 112 || R > 112)) {
+    // out(l, r, t) = sum_i in(l + L (i + I t)) Q(i, r): Q^T in_[j] per slice t
+    int rc = blas_on(c, s);
+    if (rc) return rc;
+    const double one = 1.0, zero = 0.0;
+    const double* in = (const double*)cur;
+    if (L == 1) {
+      BLASCHK(c, rocblas_dgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, (int)R, (int)T, (int)I,
+                               &one, c->qQ[j], (int)I, in, (int)I, &zero, out, (int)R));
+    } else {
+      BLASCHK(c, rocblas_dgemm_strided_batched(c->blas, rocblas_operation_none, rocblas_operation_none, (int)L,
+                                               (int)R, (int)I, &one, in, (int)L, L * I, c->qQ[j], (int)I, 0, &zero,
+                                               out, (int)L, L * R, (int)T));
+    }
+  } else {
+    HIPCHK(c, launch_ttm(cur, ctype, L, I, T, c->qQ[j], (int)R, scale, out, s));
+  }
+  cd[j] = c->qr_r[j];
+  return TR_OK;
+}
+
 // Multi-TTM Y = X x_{j!=m} Q_j^T of the QR-based variants (Alg. 3 and 4), the
 // most compressing mode first: the first TTM reads X in the contraction type
 // (the BF16/FP8 shadows), the rest run in FP64 on the compressed tensor.  *Y
 // is one of the ping-pong buffers; cd receives the extents of Y.
-int multi_ttm_y(tr_als_ctx* c, int m, int prec, const double** Y, int64_t* cd) {
-  hipStream_t s = c->stream;
+// Within a sweep (tree) the modes go in pairs (p, p+1), p even: mode p forms
+// Z = X x_{j not in {p, p+1}} Q_j^T once, keeps it, and takes Y = Z x_{p+1}
+// Q_{p+1}^T; mode p+1 takes Y = Z x_p Q_p^T with the Q_p of its update.  Z's
+// factors do not change between the two updates, so both Y are those of the
+// definition (the products taken in another order), with one TTM pass in
+// place of two at order 4.
+int multi_ttm_y(tr_als_ctx* c, int m, int prec, bool tree, const double** Y, int64_t* cd) {
   const int N = c->N;
+  const int p = m & ~1;
+  const bool paired = tree && N >= 3 && p + 1 < N && c->qZ;
+  if (paired && m == p + 1 && c->z_pair == p && c->z_prec == prec) {
+    for (int j = 0; j < N; ++j) cd[j] = c->z_cd[j];
+    c->z_pair = -1;
+    int rc = ttm_step(c, c->qZ, TR_F64, 1.0, p, cd, c->qY0);
+    if (rc) return rc;
+    *Y = c->qY0;
+    return TR_OK;
+  }
+  c->z_pair = -1;
   std::vector<int> order;
-  for (int k = 1; k < N; ++k) order.push_back((m + k) % N);
+  for (int k = 1; k < N; ++k) {
+    const int j = (m + k) % N;
+    if (!(paired && m == p && j == p + 1)) order.push_back(j);
+  }
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
     return (double)c->qr_r[a] / c->dims[a] < (double)c->qr_r[b] / c->dims[b];
   });
@@ -1139,7 +1190,7 @@ int multi_ttm_y(tr_als_ctx* c, int m, int prec, const double** Y, int64_t* cd) {
     // the second ping-pong buffer, free until the second product) for rocBLAS
     const int j = order[0];
     if (c->dims[j] > 112 || c->qr_r[j] > 112) {
-      HIPCHK(c, launch_widen_f32((const float*)c->X, c->numel, c->qY1, s));
+      HIPCHK(c, launch_widen_f32((const float*)c->X, c->numel, c->qY1, c->stream));
       cur = c->qY1;
       ctype = TR_F64;
     }
@@ -1147,31 +1198,24 @@ int multi_ttm_y(tr_als_ctx* c, int m, int prec, const double** Y, int64_t* cd) {
   double scale = prec == TR_FP8 ? 1.0 / (double)c->fp8_scale : 1.0;
   double* ybuf[2] = {c->qY0, c->qY1};
   int yi = 0;
-  for (int j : order) {
-    const int64_t L = prod(cd, 0, j), T = prod(cd, j + 1, N);
-    const int64_t I = c->dims[j], R = c->qr_r[j];
-    if (ctype == TR_F64 && scale == 1.0 && (I > 112 || R > 112)) {
-      // out(l, r, t) = sum_i in(l + L (i + I t)) Q(i, r): Q^T in_[j] per slice t
-      int rc = blas_on(c, s);
-      if (rc) return rc;
-      const double one = 1.0, zero = 0.0;
-      const double* in = (const double*)cur;
-      if (L == 1) {
-        BLASCHK(c, rocblas_dgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, (int)R, (int)T, (int)I,
-                                 &one, c->qQ[j], (int)I, in, (int)I, &zero, ybuf[yi], (int)R));
-      } else {
-        BLASCHK(c, rocblas_dgemm_strided_batched(c->blas, rocblas_operation_none, rocblas_operation_none, (int)L,
-                                                 (int)R, (int)I, &one, in, (int)L, L * I, c->qQ[j], (int)I, 0, &zero,
-                                                 ybuf[yi], (int)L, L * R, (int)T));
-      }
-    } else {
-      HIPCHK(c, launch_ttm(cur, ctype, L, I, T, c->qQ[j], (int)R, scale, ybuf[yi], s));
-    }
-    cd[j] = c->qr_r[j];
-    cur = ybuf[yi];
+  for (size_t q = 0; q < order.size(); ++q) {
+    // Z, the last product of mode p's shared part, goes to its own buffer
+    double* out = (paired && m == p && q + 1 == order.size()) ? c->qZ : ybuf[yi];
+    rc = ttm_step(c, cur, ctype, scale, order[q], cd, out);
+    if (rc) return rc;
+    cur = out;
     yi ^= 1;
     ctype = TR_F64;
     scale = 1.0;
+  }
+  if (paired && m == p) {
+    for (int j = 0; j < N; ++j) c->z_cd[j] = cd[j];
+    c->z_pair = p;
+    c->z_prec = prec;
+    double* out = cur == c->qY0 ? c->qY1 : c->qY0;
+    rc = ttm_step(c, cur, TR_F64, 1.0, p + 1, cd, out);
+    if (rc) return rc;
+    cur = out;
   }
   *Y = (const double*)cur;
   return TR_OK;
@@ -1219,7 +1263,7 @@ int build_v2(tr_als_ctx* c, int m, int64_t* Jp_out) {
 // A <- A L^{-T} as in-place triangular solves with the blocked Cholesky factor
 // (the third applied to W_n instead of V_n[2]), W_n = Y_[n] Q_0, and
 // G_n(2) = W_n R^{-T}.
-int update_mode_qr_large(tr_als_ctx* c, int m, int prec, int64_t Jp) {
+int update_mode_qr_large(tr_als_ctx* c, int m, int prec, bool in_sweep, int64_t Jp) {
   hipStream_t s = c->stream;
   const int N = c->N;
   const int Ra = c->R[m], Rb = c->R[m + 1], n = Ra * Rb;
@@ -1245,7 +1289,7 @@ int update_mode_qr_large(tr_als_ctx* c, int m, int prec, int64_t Jp) {
   }
   int64_t cd[TR_MAXN];
   const double* Y = nullptr;
-  rc = multi_ttm_y(c, m, prec, &Y, cd);
+  rc = multi_ttm_y(c, m, prec, in_sweep, &Y, cd);
   if (rc) return rc;
   rc = blas_on(c, s);
   if (rc) return rc;
@@ -1266,7 +1310,7 @@ int update_mode_qr_large(tr_als_ctx* c, int m, int prec, int64_t Jp) {
   return TR_OK;
 }
 
-int update_mode_qr(tr_als_ctx* c, int m, int prec) {
+int update_mode_qr(tr_als_ctx* c, int m, int prec, bool in_sweep) {
   hipStream_t s = c->stream;
   const int N = c->N;
   const int Ra = c->R[m], Rb = c->R[m + 1], n = Ra * Rb;
@@ -1274,7 +1318,7 @@ int update_mode_qr(tr_als_ctx* c, int m, int prec) {
   int64_t Jp = 1;
   int rc = build_v2(c, m, &Jp);
   if (rc) return rc;
-  if (n > 128) return update_mode_qr_large(c, m, prec, Jp);
+  if (n > 128) return update_mode_qr_large(c, m, prec, in_sweep, Jp);
   // shifted Cholesky-QR: passes A <- A L^{-T}, R^T = L1 L2 L3; the first two
   // are applied to V_n[2], the third to W_n
   double* A = c->qV2;
@@ -1305,7 +1349,7 @@ int update_mode_qr(tr_als_ctx* c, int m, int prec) {
   }
   int64_t cd[TR_MAXN];
   const double* Y = nullptr;
-  rc = multi_ttm_y(c, m, prec, &Y, cd);
+  rc = multi_ttm_y(c, m, prec, in_sweep, &Y, cd);
   if (rc) return rc;
   // W_n = Y_[n] Q_0 = (Y_[n] A) L_3^{-T} (I_n x n), Y_[n] A staged in M
   HIPCHK(c, launch_tall_atb(Y, 0, A, Jp, Jp, (int)c->dims[m], n, 1, prod(cd, 0, m), c->dims[m],
@@ -1325,7 +1369,7 @@ int update_mode_qr(tr_als_ctx* c, int m, int prec) {
 // G_n(2) = M_n S_n^{-1} with iterative refinement; commit; re-factor core n
 // and refresh its R-core Gram.  The Grams of the R-cores equal those of the
 // cores (Q_j has orthonormal columns); Alg. 4 forms them from the R-cores.
-int update_mode_qrne(tr_als_ctx* c, int m, int prec, int refine) {
+int update_mode_qrne(tr_als_ctx* c, int m, int prec, int refine, bool in_sweep) {
   hipStream_t s = c->stream;
   const int N = c->N;
   const int Ra = c->R[m], Rb = c->R[m + 1], n = Ra * Rb;
@@ -1344,7 +1388,7 @@ int update_mode_qrne(tr_als_ctx* c, int m, int prec, int refine) {
   if (rc) return rc;
   int64_t cd[TR_MAXN];
   const double* Y = nullptr;
-  rc = multi_ttm_y(c, m, prec, &Y, cd);
+  rc = multi_ttm_y(c, m, prec, in_sweep, &Y, cd);
   if (rc) return rc;
   // M_n = Y_[n] V_n[2] (I_n x n)
   if (n > 128) {
@@ -1617,6 +1661,7 @@ int trx_init(tr_als_ctx** out, int N, const int64_t* dims, const int64_t* ranks,
     A((void**)&c->qQb, (size_t)maxJ * 8);
     A((void**)&c->qY0, (size_t)std::max(numel, maxTT) * 8);
     A((void**)&c->qY1, (size_t)std::max(numel, maxTT) * 8);
+    if (N >= 3) A((void**)&c->qZ, (size_t)numel * 8);
     A((void**)&c->qW, (size_t)maxI * nq * 8);
     for (int it = 0; it < 3; ++it) A((void**)&c->qL[it], (size_t)nq * nq * 8);
     A((void**)&c->qG, (size_t)nq * nq * 8);
@@ -1965,8 +2010,8 @@ static int update_mode(tr_als_ctx* c, int m, int prec, int refine, bool in_sweep
   // a rank-deficient V_n[2] breaks the Cholesky-QR before R_[2] exists: with
   // the pseudo-inverse solve the QR variant takes Alg. 4's route (the same
   // half-size problem, min ||Y_[n] - G V_n[2]^T||, through V_n[2]^T V_n[2])
-  if (c->variant == TR_QR && c->solve != TR_SOLVE_PINV) return update_mode_qr(c, m, prec);
-  if (c->variant == TR_QR || c->variant == TR_QRNE) return update_mode_qrne(c, m, prec, refine);
+  if (c->variant == TR_QR && c->solve != TR_SOLVE_PINV) return update_mode_qr(c, m, prec, in_sweep);
+  if (c->variant == TR_QR || c->variant == TR_QRNE) return update_mode_qrne(c, m, prec, refine, in_sweep);
   return update_mode_ne(c, m, prec, refine, in_sweep);
 }
 
