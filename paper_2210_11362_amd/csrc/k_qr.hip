@@ -694,6 +694,136 @@ __global__ __launch_bounds__(256) void atb_frag_kernel(AtbArgs g) {
   }
 }
 
+// The same product with both operands staged through LDS: a workgroup copies
+// each 16-row step of A and B (coalesced, every element read once) into LDS
+// as [column][row] (row pitch AL_KP, conflict-free 16-byte fragment reads),
+// double-buffered with one barrier per step, and each wave forms its run of
+// output tiles from the LDS fragments, as above.  Lane (c, kq) takes rows
+// 4kq + j, j = 0..3, of the step.
+constexpr int AL_ROWS = 16, AL_KP = AL_ROWS + 2;
+template <int NB, int W>
+__device__ __forceinline__ void atb_lds_mma(const double* As, const double* Bs, f64x4* acc) {
+  constexpr int NT = NB * NB, TW = (NT + 3) / 4, T0 = W * TW < NT ? W * TW : NT;
+  constexpr int T1 = T0 + TW < NT ? T0 + TW : NT;
+  constexpr int BQ0 = T0 / NB, NQ = T1 > T0 ? (T1 - 1) / NB - BQ0 + 1 : 1;
+  if (T1 <= T0) return;
+  const int lane = threadIdx.x & 63, cl = lane & 15, kq = lane >> 4;
+  double fa[NB][4], fb[NQ][4];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const double* q = As + (16 * b + cl) * AL_KP + 4 * kq;
+    const double2 x = *reinterpret_cast<const double2*>(q), y = *reinterpret_cast<const double2*>(q + 2);
+    fa[b][0] = x.x; fa[b][1] = x.y; fa[b][2] = y.x; fa[b][3] = y.y;
+  }
+#pragma unroll
+  for (int u = 0; u < NQ; ++u) {
+    const double* q = Bs + (16 * (BQ0 + u) + cl) * AL_KP + 4 * kq;
+    const double2 x = *reinterpret_cast<const double2*>(q), y = *reinterpret_cast<const double2*>(q + 2);
+    fb[u][0] = x.x; fb[u][1] = x.y; fb[u][2] = y.x; fb[u][3] = y.y;
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int t = T0; t < T1; ++t) mma64(acc[t - T0], fa[t % NB][j], fb[t / NB - BQ0][j]);
+}
+
+template <int NB, int W>
+__device__ __forceinline__ void atb_lds_store(const AtbArgs& g, const f64x4* acc) {
+  constexpr int NT = NB * NB, TW = (NT + 3) / 4, T0 = W * TW < NT ? W * TW : NT;
+  constexpr int T1 = T0 + TW < NT ? T0 + TW : NT;
+  const int lane = threadIdx.x & 63;
+  double* out = g.part + (size_t)blockIdx.x * g.P * g.Q;
+#pragma unroll
+  for (int t = T0; t < T1; ++t) {
+    const int bp = t % NB, bq = t / NB;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = bp * 16 + (lane >> 4) + 4 * v, col = bq * 16 + (lane & 15);
+      if (row < g.P && col < g.Q) out[row + (int64_t)g.P * col] = acc[t - T0][v];
+    }
+  }
+}
+
+// LAY: A in the Multi-TTM layout (else column-major: k contiguous).
+template <int NB, bool LAY>
+__global__ __launch_bounds__(256) void atb_lds_kernel(AtbArgs g) {
+  constexpr int NP = 16 * NB, OPS = NP * AL_KP, TW = (NB * NB + 3) / 4;
+  extern __shared__ __align__(16) double als[];   // 2 buffers x (A, B) x NP x AL_KP
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const int kk = tid % AL_ROWS, pp = tid / AL_ROWS;   // this thread's row of a step, first column
+  const int64_t k0 = (int64_t)blockIdx.x * g.kc;
+  const int64_t k1 = min(g.K, k0 + g.kc);
+  const int nsteps = (int)((k1 - k0 + AL_ROWS - 1) / AL_ROWS);
+  // position of the thread's row in A's layout, advanced AL_ROWS rows a step
+  // (L below 2^31 here)
+  uint32_t lr = 0;
+  int64_t ro = 0;
+  {
+    const int64_t r0 = k0 + kk;
+    if (LAY) { lr = (uint32_t)(r0 % g.L); ro = lr + g.LIp * (r0 / g.L); }
+    else ro = r0 * g.ks;
+  }
+  const int64_t ps = LAY ? g.L : g.ps;
+  double ra[NB], rb[NB];
+  auto load = [&](int st) {
+    const int64_t r = k0 + (int64_t)st * AL_ROWS + kk;
+    const bool rin = r < k1;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int p = pp + 16 * i;
+      ra[i] = (rin && p < g.P) ? g.A[ro + ps * p] : 0.0;
+      rb[i] = (rin && p < g.Q) ? g.B[r + g.ldb * p] : 0.0;
+    }
+  };
+  auto advance = [&]() {
+    if (LAY) {
+      const uint32_t L32 = (uint32_t)g.L, w = (lr + (uint32_t)AL_ROWS) / L32;
+      lr = lr + (uint32_t)AL_ROWS - w * L32;
+      ro += AL_ROWS + (int64_t)w * (g.LIp - g.L);
+    } else {
+      ro += AL_ROWS * g.ks;
+    }
+  };
+  auto stash = [&](int buf) {
+    double* As = als + buf * 2 * OPS;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      As[(pp + 16 * i) * AL_KP + kk] = ra[i];
+      As[OPS + (pp + 16 * i) * AL_KP + kk] = rb[i];
+    }
+  };
+  f64x4 acc[TW];
+#pragma unroll
+  for (int t = 0; t < TW; ++t) acc[t] = f64x4{0, 0, 0, 0};
+  if (nsteps > 0) {
+    load(0);
+    stash(0);
+  }
+  __syncthreads();
+  for (int st = 0; st < nsteps; ++st) {
+    const bool more = st + 1 < nsteps;
+    if (more) {
+      advance();
+      load(st + 1);
+    }
+    const double* As = als + (st & 1) * 2 * OPS;
+    switch (wave) {
+      case 0: atb_lds_mma<NB, 0>(As, As + OPS, acc); break;
+      case 1: atb_lds_mma<NB, 1>(As, As + OPS, acc); break;
+      case 2: atb_lds_mma<NB, 2>(As, As + OPS, acc); break;
+      default: atb_lds_mma<NB, 3>(As, As + OPS, acc); break;
+    }
+    if (more) stash((st + 1) & 1);
+    __syncthreads();
+  }
+  switch (wave) {
+    case 0: atb_lds_store<NB, 0>(g, acc); break;
+    case 1: atb_lds_store<NB, 1>(g, acc); break;
+    case 2: atb_lds_store<NB, 2>(g, acc); break;
+    default: atb_lds_store<NB, 3>(g, acc); break;
+  }
+}
+
 // C = sum over chunks; a block takes 64 outputs, its four waves each sum a
 // contiguous quarter of the chunks, and the quarters are added in order.
 __global__ __launch_bounds__(256) void sum_chunks_kernel(const double* part, int nchunk, int64_t n, double* C) {
@@ -1134,6 +1264,26 @@ hipError_t launch_tall_atb(const double* A, int64_t lda, const double* B, int64_
     const size_t lds = 0;
     const bool bv = ldb % 2 == 0 && K % 2 == 0 && (reinterpret_cast<uintptr_t>(B) & 15) == 0;
     const dim3 grid((unsigned)nchunk);
+    // A read with k contiguous over long runs: staged through LDS; a
+    // row-major A or short runs (L < 1024): fragments straight from memory
+    // (at 10^6 x 100: L = 10^4 680 against 850 us, column-major 640 against
+    // 870; row-major 640 against 700, L = 100 690 against 710)
+    const bool use_lds = fa.L > 1 ? fa.L >= 1024 : fa.ks == 1;
+    if (use_lds) {
+      const size_t ldsb = (size_t)4 * 16 * nb * AL_KP * sizeof(double);
+      switch (nb * 2 + (fa.L > 1 ? 1 : 0)) {
+#define ATB_LDS_CASE(NBV) \
+  case 2 * NBV: hipLaunchKernelGGL((atb_lds_kernel<NBV, false>), grid, dim3(256), ldsb, s, fa); break; \
+  case 2 * NBV + 1: hipLaunchKernelGGL((atb_lds_kernel<NBV, true>), grid, dim3(256), ldsb, s, fa); break;
+        ATB_LDS_CASE(1) ATB_LDS_CASE(2) ATB_LDS_CASE(3) ATB_LDS_CASE(4) ATB_LDS_CASE(5) ATB_LDS_CASE(6) ATB_LDS_CASE(7)
+#undef ATB_LDS_CASE
+        default: return hipErrorInvalidValue;
+      }
+      const int64_t n = (int64_t)P * Q;
+      hipLaunchKernelGGL(sum_chunks_kernel, dim3(cdiv(n, 64)), dim3(256), 0, s, (const double*)part, (int)nchunk, n,
+                         C);
+      return hipGetLastError();
+    }
     switch (nb * 4 + (fa.L > 1 ? 2 : 0) + (bv ? 1 : 0)) {
 #define ATB_FRAG(NBV) \
   case 4 * NBV: hipLaunchKernelGGL((atb_frag_kernel<NBV, false, false>), grid, dim3(256), lds, s, fa); break; \
