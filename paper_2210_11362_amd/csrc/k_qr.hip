@@ -104,10 +104,30 @@ __global__ __launch_bounds__(1024) void householder_qr_kernel(double* A, int64_t
   }
 }
 
-// Sum over the 64 lanes of a wave; the butterfly leaves the same bits in every lane.
+// A double moved across lanes by one DPP pattern (both 32-bit halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+// Sum over the 64 lanes of a wave (all lanes active): pairwise within each row
+// of 16 lanes by DPP (swap neighbours, swap pairs, mirror the half rows, mirror
+// the rows; every lane of a row then holds the same bits), then the four row
+// sums read out and added in a fixed order, so every lane gets the same bits.
 __device__ __forceinline__ double wave_sum64(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  return v;
+  v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v);   // row_half_mirror
+  v += dpp_f64<0x140>(v);   // row_mirror
+  return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
 }
 
 // The same factorization for small unfoldings (m <= 64*RT, n <= 16*CW, the
@@ -152,7 +172,7 @@ __global__ __launch_bounds__(1024) void householder_qr_reg_kernel(const double* 
         if (i == k) x0p = col[t];
       }
       const double nrm2 = wave_sum64(s);
-      const double x0 = __shfl(x0p, k & 63);
+      const double x0 = readlane_f64(x0p, k & 63);
       const double nrm = sqrt(nrm2);
       const double alpha = (x0 >= 0.0) ? -nrm : nrm;
       const double v0 = x0 - alpha;
@@ -1041,9 +1061,10 @@ struct TGArgs {
   double scale;
 };
 constexpr int TG_WAVES = 4;
-template <int NB, bool ROWOUT, typename Tin>
+template <int NB, bool TRIM, bool ROWOUT, typename Tin>
 __global__ __launch_bounds__(64 * TG_WAVES) void tall_gemm_kernel(TGArgs g) {
-  constexpr int NP = 16 * NB, BST = NP + 2, KJ = 2 * NB;
+  // k steps of 8: all 16*NB values of k, or (TRIM, K <= 16*NB - 8) one fewer
+  constexpr int NP = 16 * NB, BST = NP + 2, KJ = 2 * NB - (TRIM ? 1 : 0);
   extern __shared__ __align__(16) double tsm[];   // B as [n][k], NP x BST
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int cl = lane & 15, kq = lane >> 4;
@@ -1078,7 +1099,7 @@ __global__ __launch_bounds__(64 * TG_WAVES) void tall_gemm_kernel(TGArgs g) {
     f64x4 acc[NB];
 #pragma unroll
     for (int ct = 0; ct < NB; ++ct) acc[ct] = f64x4{0, 0, 0, 0};
-    // all 16*NB values of k and of n (padding is zero in B): fixed trip
+    // KJ steps of k and all 16*NB values of n (padding is zero in B): fixed trip
     // counts keep the fragments in fixed registers.  The B fragments of step
     // j + 1 are read from LDS while step j's MFMAs run.
     double2 bv[2][NB];
@@ -1150,10 +1171,13 @@ hipError_t launch_tg(const TGArgs& g, hipStream_t s) {
   const int64_t ntile = (g.M * g.nbatch + 15) / 16;
   const dim3 grid((unsigned)std::min<int64_t>((ntile + TG_WAVES - 1) / TG_WAVES, 256));
   const void* k = nullptr;
-  switch (nb * 2 + (rowout ? 1 : 0)) {
+  const bool trim = g.K <= 16 * nb - 8;
+  switch (nb * 4 + (trim ? 2 : 0) + (rowout ? 1 : 0)) {
 #define TG_CASE(NBV) \
-  case 2 * NBV: k = (const void*)tall_gemm_kernel<NBV, false, Tin>; break; \
-  case 2 * NBV + 1: k = (const void*)tall_gemm_kernel<NBV, true, Tin>; break;
+  case 4 * NBV: k = (const void*)tall_gemm_kernel<NBV, false, false, Tin>; break; \
+  case 4 * NBV + 1: k = (const void*)tall_gemm_kernel<NBV, false, true, Tin>; break; \
+  case 4 * NBV + 2: k = (const void*)tall_gemm_kernel<NBV, true, false, Tin>; break; \
+  case 4 * NBV + 3: k = (const void*)tall_gemm_kernel<NBV, true, true, Tin>; break;
     TG_CASE(1) TG_CASE(2) TG_CASE(3) TG_CASE(4) TG_CASE(5) TG_CASE(6) TG_CASE(7)
 #undef TG_CASE
   }
