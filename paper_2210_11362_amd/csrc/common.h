@@ -169,6 +169,13 @@ hipError_t launch_trsm_rhs(const double* L, const double* rdiag, int n, const do
 // QR variant
 hipError_t launch_householder_qr(double* A, int64_t m, int n, double* V, double* tau, double* Q, double* R,
                                  hipStream_t s);
+// Whether launch_householder_qr factors an m x n matrix in one workgroup's
+// registers (m <= 256, n <= 128, the reflectors within 128 KB of LDS).
+bool householder_in_registers(int64_t m, int n);
+// dst (rows x cols, ld ldd) = src (ld lds), or dst += src with add; src null
+// writes zeros.
+hipError_t launch_block_copy(const double* src, int64_t lds, double* dst, int64_t ldd, int rows, int cols, bool add,
+                             hipStream_t s);
 // out[e] = (double)x[e], e < n.
 hipError_t launch_widen_f32(const float* x, int64_t n, double* out, hipStream_t s);
 // C[e] = sum over the nchunk partials part[c * n + e] (fixed summation order).

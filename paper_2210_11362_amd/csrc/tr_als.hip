@@ -1114,6 +1114,35 @@ int qr_core(tr_als_ctx* c, int k) {
     HIPCHK(c, launch_gemm64(n, n, n, 1.0, Lp, L3, 0.0, nullptr, 0, c->qLt, n, s));
     HIPCHK(c, hipMemcpyAsync(c->qQ[k], c->qA, (size_t)I * n * sizeof(double), hipMemcpyDeviceToDevice, s));
     HIPCHK(c, launch_transpose(c->qLt, n, n, c->qRt, s));
+  } else if (n > 128 && I < n && householder_in_registers(I, 16)) {
+    // a wide unfolding (Q_k square): Householder on panels of w columns in
+    // one workgroup's registers, each panel's factor Q_p taken out of the
+    // columns to its right by block Gram-Schmidt applied twice (the second
+    // pass restores orthogonality to rounding), so Q = [Q_1 ... Q_p] and
+    // R = [R_pp on the diagonal, Q_p^T A on its right, zeros below]
+    int w = 128;
+    while (!householder_in_registers(I, w)) w /= 2;
+    const int ni = (int)I;
+    double* T1 = c->qV;    // w x (n - w) at most: within I x n
+    double* T2 = c->qRi;   // within n x n
+    HIPCHK(c, launch_block_copy(nullptr, 0, c->qRt, r, (int)r, n, false, s));
+    for (int c0 = 0; c0 < (int)r; c0 += w) {
+      const int wp = std::min<int>(w, (int)r - c0), rest = n - c0 - wp;
+      double* Qp = c->qQ[k] + (int64_t)c0 * I;
+      double* Ar = c->qA + (int64_t)(c0 + wp) * I;   // the columns right of the panel
+      HIPCHK(c, launch_householder_qr(c->qA + (int64_t)c0 * I, I, wp, c->qV, c->qtau, Qp, c->qLT, s));
+      HIPCHK(c, launch_block_copy(c->qLT, wp, c->qRt + c0 + r * c0, r, wp, wp, false, s));
+      if (rest == 0) continue;
+      const MatView Qt{Qp, I, 2, 0, 0}, Qv{Qp, I, 0, 0, 0};
+      for (int pass = 0; pass < 2; ++pass) {
+        double* T = pass == 0 ? T1 : T2;
+        const MatView Av{Ar, I, 0, 0, 0}, Tv{T, wp, 0, 0, 0};
+        HIPCHK(c, launch_gemm64(wp, rest, ni, 1.0, Qt, Av, 0.0, nullptr, 0, T, wp, s));        // T = Q_p^T A_r
+        HIPCHK(c, launch_gemm64(ni, rest, wp, -1.0, Qv, Tv, 1.0, Ar, I, Ar, I, s));          // A_r -= Q_p T
+      }
+      HIPCHK(c, launch_block_copy(T2, wp, T1, wp, wp, rest, true, s));
+      HIPCHK(c, launch_block_copy(T1, wp, c->qRt + c0 + r * (c0 + wp), r, wp, rest, false, s));
+    }
   } else {
     HIPCHK(c, launch_householder_qr(c->qA, I, n, c->qV, c->qtau, c->qQ[k], c->qRt, s));
   }
