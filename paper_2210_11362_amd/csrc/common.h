@@ -159,9 +159,9 @@ bool solve_in_lds(int n);
 // workgroup, registers); a non-positive pivot latches ST_SINGULAR.
 bool spd_inverse_fits(int n);
 // dst[r + ld_dst c] = src[r + ld_src c] for a rows x cols block (trans = 1:
-// src[c + ld_src r]; src == nullptr: zeros)
+// src[c + ld_src r]; src == nullptr: zeros; add: dst += the value)
 hipError_t launch_copy_block(const double* src, int64_t ld_src, int rows, int cols, double* dst, int64_t ld_dst,
-                             hipStream_t s, int trans = 0);
+                             hipStream_t s, int trans = 0, bool add = false);
 hipError_t launch_spd_inverse(const double* S, int n, double* Sinv, int* status, hipStream_t s);
 hipError_t launch_chol_lds(const double* S, int n, double* L, double* LT, double* rdiag, int* status, hipStream_t s);
 hipError_t launch_trsm_rhs(const double* L, const double* rdiag, int n, const double* Rhs, int64_t I, double* G,
@@ -172,10 +172,6 @@ hipError_t launch_householder_qr(double* A, int64_t m, int n, double* V, double*
 // Whether launch_householder_qr factors an m x n matrix in one workgroup's
 // registers (m <= 256, n <= 128, the reflectors within 128 KB of LDS).
 bool householder_in_registers(int64_t m, int n);
-// dst (rows x cols, ld ldd) = src (ld lds), or dst += src with add; src null
-// writes zeros.
-hipError_t launch_block_copy(const double* src, int64_t lds, double* dst, int64_t ldd, int rows, int cols, bool add,
-                             hipStream_t s);
 // out[e] = (double)x[e], e < n.
 hipError_t launch_widen_f32(const float* x, int64_t n, double* out, hipStream_t s);
 // C[e] = sum over the nchunk partials part[c * n + e] (fixed summation order).

@@ -1201,17 +1201,6 @@ __global__ void core_fold_kernel(const double* G2, int64_t I, int Ra, int Rb, do
   core[e] = G2[i + I * (a + (int64_t)Ra * b)];
 }
 
-// dst (rows x cols, ld ldd) = src (ld lds), or += with add; zero with src null.
-__global__ void block_copy_kernel(const double* src, int64_t lds, double* dst, int64_t ldd, int rows, int cols,
-                                  int add) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)rows * cols) return;
-  const int64_t i = e % rows, j = e / rows;
-  const double v = src ? src[i + lds * j] : 0.0;
-  double* d = dst + i + ldd * j;
-  *d = add ? *d + v : v;
-}
-
 // A + s*I in place on the diagonal.
 __global__ void add_diag_kernel(double* A, int n, const double* s) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1232,15 +1221,6 @@ __global__ void shift_kernel(const double* G, int n, int64_t m, double* s) {
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 }  // namespace
-
-hipError_t launch_block_copy(const double* src, int64_t lds, double* dst, int64_t ldd, int rows, int cols, bool add,
-                             hipStream_t s) {
-  const int64_t n = (int64_t)rows * cols;
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(block_copy_kernel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, src, lds, dst, ldd, rows, cols,
-                     add ? 1 : 0);
-  return hipGetLastError();
-}
 
 bool householder_in_registers(int64_t m, int n) {
   return m <= 256 && n <= 128 && (size_t)(m * std::min<int64_t>(m, n)) * sizeof(double) <= 128 * 1024;

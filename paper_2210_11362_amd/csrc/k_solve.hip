@@ -502,23 +502,25 @@ hipError_t launch_trsm_rhs(const double* L, const double* rdiag, int n, const do
 }
 
 namespace {
-// dst[r + ldd c] = src[r + lds c] (trans: src[c + lds r]; src == nullptr: 0)
+// dst[r + ldd c] = src[r + lds c] (trans: src[c + lds r]; src == nullptr: 0;
+// add: dst += the value)
 __global__ void copy_block_kernel(const double* src, int64_t lds_, int rows, int cols, double* dst, int64_t ldd,
-                                  int trans) {
+                                  int trans, int add) {
   const int64_t n = (int64_t)rows * cols;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = e % rows, c = e / rows;
-    dst[r + ldd * c] = src ? (trans ? src[c + lds_ * r] : src[r + lds_ * c]) : 0.0;
+    const double v = src ? (trans ? src[c + lds_ * r] : src[r + lds_ * c]) : 0.0;
+    dst[r + ldd * c] = add ? dst[r + ldd * c] + v : v;
   }
 }
 }  // namespace
 
 hipError_t launch_copy_block(const double* src, int64_t ld_src, int rows, int cols, double* dst, int64_t ld_dst,
-                             hipStream_t s, int trans) {
+                             hipStream_t s, int trans, bool add) {
   const int64_t n = (int64_t)rows * cols;
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(copy_block_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024)), dim3(256), 0, s,
-                     src, ld_src, rows, cols, dst, ld_dst, trans);
+                     src, ld_src, rows, cols, dst, ld_dst, trans, add ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -1125,13 +1125,13 @@ int qr_core(tr_als_ctx* c, int k) {
     const int ni = (int)I;
     double* T1 = c->qV;    // w x (n - w) at most: within I x n
     double* T2 = c->qRi;   // within n x n
-    HIPCHK(c, launch_block_copy(nullptr, 0, c->qRt, r, (int)r, n, false, s));
+    HIPCHK(c, launch_copy_block(nullptr, 0, (int)r, n, c->qRt, r, s));
     for (int c0 = 0; c0 < (int)r; c0 += w) {
       const int wp = std::min<int>(w, (int)r - c0), rest = n - c0 - wp;
       double* Qp = c->qQ[k] + (int64_t)c0 * I;
       double* Ar = c->qA + (int64_t)(c0 + wp) * I;   // the columns right of the panel
       HIPCHK(c, launch_householder_qr(c->qA + (int64_t)c0 * I, I, wp, c->qV, c->qtau, Qp, c->qLT, s));
-      HIPCHK(c, launch_block_copy(c->qLT, wp, c->qRt + c0 + r * c0, r, wp, wp, false, s));
+      HIPCHK(c, launch_copy_block(c->qLT, wp, wp, wp, c->qRt + c0 + r * c0, r, s));
       if (rest == 0) continue;
       const MatView Qt{Qp, I, 2, 0, 0}, Qv{Qp, I, 0, 0, 0};
       for (int pass = 0; pass < 2; ++pass) {
@@ -1140,8 +1140,8 @@ int qr_core(tr_als_ctx* c, int k) {
         HIPCHK(c, launch_gemm64(wp, rest, ni, 1.0, Qt, Av, 0.0, nullptr, 0, T, wp, s));        // T = Q_p^T A_r
         HIPCHK(c, launch_gemm64(ni, rest, wp, -1.0, Qv, Tv, 1.0, Ar, I, Ar, I, s));          // A_r -= Q_p T
       }
-      HIPCHK(c, launch_block_copy(T2, wp, T1, wp, wp, rest, true, s));
-      HIPCHK(c, launch_block_copy(T1, wp, c->qRt + c0 + r * (c0 + wp), r, wp, rest, false, s));
+      HIPCHK(c, launch_copy_block(T2, wp, wp, rest, T1, wp, s, 0, true));
+      HIPCHK(c, launch_copy_block(T1, wp, wp, rest, c->qRt + c0 + r * (c0 + wp), r, s));
     }
   } else {
     HIPCHK(c, launch_householder_qr(c->qA, I, n, c->qV, c->qtau, c->qQ[k], c->qRt, s));

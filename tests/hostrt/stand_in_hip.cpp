@@ -325,12 +325,6 @@ void check_extents(const std::string& full, const std::string& nm, void** a, std
     r->push_back({D(2), 8, "out"});
   } else if (nm == "zero_double_kernel") {   // (out)
     r->push_back({D(0), 8, "out"});
-  } else if (nm == "block_copy_kernel") {   // (src, lds, dst, ldd, rows, cols, add)
-    const int64_t rows = I(4), cols = I(5);
-    if (rows > 0 && cols > 0) {
-      if (D(0)) r->push_back({D(0), (size_t)((L(1) * (cols - 1) + rows) * 8), "src"});
-      r->push_back({D(2), (size_t)((L(3) * (cols - 1) + rows) * 8), "dst"});
-    }
   } else if (nm == "v2_direct_kernel") {   // (Tp, Jp, core, I, Rm, Ra, Rb, L, rows, V2)
     const int64_t Jp = L(1), In = L(3), Rm = I(4), Ra = I(5), Rb = I(6), rows = I(8);
     r->push_back({D(0), (size_t)(Jp * Rb * Rm * 8), "Tp"});
@@ -412,7 +406,7 @@ void check_extents(const std::string& full, const std::string& nm, void** a, std
       r->push_back({D(2), (size_t)x.n_g * x.TWg * x.ldb * (es == 2 ? 4 : es), "table"});   // BF16: hi and lo
       r->push_back({D(1), (size_t)x.Rm * x.Ik * x.Rg * 8, "core"});
     }
-  } else if (nm == "copy_block_kernel") {   // (src, lds, rows, cols, dst, ldd, trans)
+  } else if (nm == "copy_block_kernel") {   // (src, lds, rows, cols, dst, ldd, trans, add)
     const int64_t rows = I(2), cols = I(3), lds_ = L(1), ldd = L(5);
     if (D(0)) r->push_back({D(0), (size_t)((arg<int>(a, 6) ? lds_ * (rows - 1) + cols : lds_ * (cols - 1) + rows) * 8),
                             "src"});
