@@ -477,10 +477,13 @@ __global__ __launch_bounds__(256) void tall_atb_lds_kernel(TallArgs g) {
 // of the block upper triangle, loading the next group while the MFMAs run.
 // Waves take interleaved 16-row groups of the workgroup's chunk; their sums are
 // added in LDS in wave order, so the result does not depend on timing.
+// 16-row groups a wave holds (GF_G * 64 rows per step of the workgroup): two
+// measured slower (366 against 316 us for 10^6 x 100)
+constexpr int GF_G = 1;
 template <int NB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void gram_frag_kernel(
     const double* A, int64_t lda, int64_t K, int P, int64_t kc, double* part) {
-  constexpr int NT = NB * (NB + 1) / 2;
+  constexpr int NT = NB * (NB + 1) / 2, RS = 64 * GF_G;
   extern __shared__ __align__(16) double gred[];   // NT * 256 doubles
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int cl = lane & 15, kq = lane >> 4;
@@ -497,45 +500,53 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   f64x4 acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = f64x4{0, 0, 0, 0};
-  double2 f[NB][2];
-  // half h of the fragments of the 16-row group at g: rows g + 4kq + 2h, +1
-  auto load = [&](int64_t g, int h) {
+  double2 f[GF_G][NB][2];
+  // half h of the fragments of group s, the 16 rows at g + 16 s: rows
+  // g + 16 s + 4kq + 2h, +1
+  auto load = [&](int64_t g, int s, int h) {
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-      const int64_t k = g + 4 * kq + 2 * h;
+      const int64_t k = g + 16 * s + 4 * kq + 2 * h;
       if (cin[b] && k + 1 < k1) {
-        f[b][h] = *reinterpret_cast<const double2*>(pc[b] + k);
+        f[s][b][h] = *reinterpret_cast<const double2*>(pc[b] + k);
       } else {
-        f[b][h].x = (cin[b] && k < k1) ? pc[b][k] : 0.0;
-        f[b][h].y = 0.0;
+        f[s][b][h].x = (cin[b] && k < k1) ? pc[b][k] : 0.0;
+        f[s][b][h].y = 0.0;
       }
     }
   };
-  auto mfma = [&](int h) {
+  auto mfma = [&](int s, int h) {
     int t = 0;
 #pragma unroll
     for (int bq = 0; bq < NB; ++bq)
 #pragma unroll
-      for (int bp = 0; bp <= bq; ++bp, ++t) mma64(acc[t], f[bp][h].x, f[bq][h].x);
+      for (int bp = 0; bp <= bq; ++bp, ++t) mma64(acc[t], f[s][bp][h].x, f[s][bq][h].x);
     t = 0;
 #pragma unroll
     for (int bq = 0; bq < NB; ++bq)
 #pragma unroll
-      for (int bp = 0; bp <= bq; ++bp, ++t) mma64(acc[t], f[bp][h].y, f[bq][h].y);
+      for (int bp = 0; bp <= bq; ++bp, ++t) mma64(acc[t], f[s][bp][h].y, f[s][bq][h].y);
   };
-  // each half is reloaded for the next group as soon as its MFMAs are issued,
-  // so the loads overlap the other half's MFMAs without a second buffer
-  int64_t g = k0 + 16 * wave;
+  // a wave takes GF_G consecutive 16-row groups of each RS-row step; each
+  // half is reloaded for the next step as soon as its MFMAs are issued, so a
+  // load has the other halves' MFMAs to arrive
+  int64_t g = k0 + 16 * GF_G * wave;
   if (g < k1) {
-    load(g, 0);
-    load(g, 1);
+#pragma unroll
+    for (int s = 0; s < GF_G; ++s) {
+      load(g, s, 0);
+      load(g, s, 1);
+    }
   }
-  for (; g < k1; g += 64) {
-    const bool more = g + 64 < k1;
-    mfma(0);
-    if (more) load(g + 64, 0);
-    mfma(1);
-    if (more) load(g + 64, 1);
+  // (past the chunk end the loads return zeros, so they need no branch)
+  for (; g < k1; g += RS) {
+#pragma unroll
+    for (int s = 0; s < GF_G; ++s)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        mfma(s, h);
+        load(g + RS, s, h);
+      }
   }
   for (int w = 0; w < 4; ++w) {
     if (wave == w) {
@@ -1008,7 +1019,7 @@ __global__ __launch_bounds__(256) void table_to_v2_tiled_kernel(const double* T,
 // last core) times the slice i of the last core (Rm x Ra):
 //   V2[k' + J*(a + Ra*b)] = sum_m Tp[j][b + Rb*m] * core[m + Rm*(i + I*a)],
 // summed over m in increasing order (the chain step's order, so the values
-// are those of the two-pass build).  A block stages ROWS rows' operands in
+// are those of the two-pass build).  A block stages its rows' operands in
 // LDS, then each thread forms outputs of one row, a column at a time, so
 // consecutive lanes write consecutive rows of a column.
 __global__ __launch_bounds__(256) void v2_direct_kernel(const double* Tp, int64_t Jp, const double* core, int64_t I,
@@ -1260,7 +1271,7 @@ hipError_t launch_tall_atb(const double* A, int64_t lda, const double* B, int64_
   const int nb = std::max((P + 15) / 16, (Q + 15) / 16);
   if (gram && nb <= 7 && lda % 2 == 0 && (reinterpret_cast<uintptr_t>(A) & 15) == 0) {   // fragments in registers
     nchunk = std::min<int64_t>(nchunk, 256);
-    const int64_t kc = cdiv(cdiv(K, nchunk), 64) * 64;
+    const int64_t kc = cdiv(cdiv(K, nchunk), 64 * GF_G) * (64 * GF_G);
     nchunk = cdiv(K, kc);
     const size_t lds = (size_t)(nb * (nb + 1) / 2) * 256 * sizeof(double);
     const dim3 grid((unsigned)nchunk);
@@ -1430,7 +1441,10 @@ hipError_t launch_v2_direct(const double* Tp, int64_t Jp, const double* core, in
   if (Jp <= 0 || I <= 0 || Rm <= 0 || Ra <= 0 || Rb <= 0 || L <= 0 || J % L != 0) return hipErrorInvalidValue;
   if (!v2_direct_fits(Rm, Ra, Rb)) return hipErrorInvalidValue;
   const size_t row_bytes = (size_t)((Rb * Rm + Rm * Ra) | 1) * sizeof(double);
-  int rows = 32;
+  // 16 rows a block: six blocks a CU keep more rows' loads in flight than
+  // three of 32 rows (10^6 x 100: 460-560 us against 570-700 us; 8 rows
+  // 490-580 us, 64 rows 1440-1680 us)
+  int rows = 16;
   while (rows > 1 && rows * row_bytes > 60 * 1024) rows /= 2;
   hipLaunchKernelGGL(v2_direct_kernel, dim3((unsigned)cdiv(J, rows)), dim3(256), rows * row_bytes, s, Tp, Jp, core, I,
                      Rm, Ra, Rb, L, rows, V2);
