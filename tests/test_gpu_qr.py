@@ -48,6 +48,8 @@ LARGE_QR_SHAPES = [
     ((40, 36, 30), (12, 11, 13)),          # n = 132, 143, 156; the middle mode sums slice products
     ((30, 28, 26, 12), (12, 12, 11, 2)),   # order 4: n = 144, 132 beside n = 22, 24
     ((150, 150, 20), (12, 12, 2)),         # core 1 unfolding 150 x 144: Cholesky-QR of a tall core
+    ((150, 30, 28), (20, 20, 20)),         # core 1 unfolding 150 x 400: register-Householder panels of
+                                           # 64, 64 and 22 columns with block Gram-Schmidt between them
 ]
 
 
