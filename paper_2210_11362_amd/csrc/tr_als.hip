@@ -965,63 +965,36 @@ int update_mode_ne(tr_als_ctx* c, int m, int prec, int refine, bool in_sweep) {
   hipStream_t s = c->stream, s2 = c->stream2;
   const Plan& p = c->plan[m];
   const int n = p.Ra * p.Rb;
+  HIPCHK(c, hipEventRecord(c->ev_fork, s));
+  // coefficient branch on the second stream, forked after the X-contraction
+  // launch (it needs only the Grams, which are ready at the fork)
   // within a sweep of order >= 4 the previous mode formed this mode's ring
   // prefix (mode 1 of a sweep starts from scratch: nothing crosses sweeps)
   const bool prefix = in_sweep && c->N >= 4;
-  // order 4: the next mode's prefix K_{m+2} K_{m+3} is one product of Grams
-  // that are final here; it goes into the same launch as this mode's last
-  // ring GEMM (its ring has at least one GEMM at order 4)
-  Gemm64Desc pd;
-  const bool pair = prefix && m + 1 < c->N && ring_prefix_single(c, m + 1, &pd);
-  // the coefficient branch: Gram ring -> S_n -> S_n^{-1}, on stream bs
-  auto coef = [&](hipStream_t bs) -> int {
-    const int r = compute_coef(c, m, c->S, bs, prefix && m > 0, pair ? &pd : nullptr);
+  auto branch = [&]() -> int {
+    HIPCHK(c, hipStreamWaitEvent(s2, c->ev_fork, 0));
+    // order 4: the next mode's prefix K_{m+2} K_{m+3} is one product of Grams
+    // that are final here; it goes into the same launch as this mode's last
+    // ring GEMM (its ring has at least one GEMM at order 4)
+    Gemm64Desc pd;
+    const bool pair = prefix && m + 1 < c->N && ring_prefix_single(c, m + 1, &pd);
+    const int r = compute_coef(c, m, c->S, s2, prefix && m > 0, pair ? &pd : nullptr);
     if (r) return r;
     if (c->solve == TR_SOLVE_PINV) {
-      HIPCHK(c, launch_pinv(c->S, n, pinv_rcond(c, n), c->Sinv, c->pinvw, c->status, bs));
+      HIPCHK(c, launch_pinv(c->S, n, pinv_rcond(c, n), c->Sinv, c->pinvw, c->status, s2));
     } else if (spd_inverse_fits(n)) {
-      HIPCHK(c, launch_spd_inverse(c->S, n, c->Sinv, c->status, bs));
+      HIPCHK(c, launch_spd_inverse(c->S, n, c->Sinv, c->status, s2));
     } else {
-      const int r2 = spd_inverse_blocked(c, c->S, n, c->Sinv, c->blkw, bs);
+      const int r2 = spd_inverse_blocked(c, c->S, n, c->Sinv, c->blkw, s2);
       if (r2) return r2;
     }
+    HIPCHK(c, hipEventRecord(c->ev_join, s2));
+    // after the join: the next mode's prefix excludes this mode's core
+    if (prefix && m + 1 < c->N && !pair) return ring_prefix(c, m + 1, s2);
     return TR_OK;
   };
-  // A mode that reuses the previous mode's stage-1 result has only the
-  // absorptions on the X side, shorter than the branch: the branch then stays
-  // on the main stream and the absorptions fork, so the fork's start-up delay
-  // falls on the shorter path.  (It needs this mode's ring prefix to have been
-  // formed before the previous join: by the paired launch, or none at all.)
-  Gemm64Desc prev;
-  const bool reuse_x = in_sweep && p.regime == 1 && p.reuse_prev && p.reuse_y;
-  if (reuse_x && (!(prefix && m > 0) || ring_prefix_single(c, m, &prev))) {
-    HIPCHK(c, hipEventRecord(c->ev_fork, s));
-    HIPCHK(c, hipStreamWaitEvent(s2, c->ev_fork, 0));
-    int rc = absorb_steps(c, p, c->Y0, c->M, s2);
-    if (rc) return rc;
-    HIPCHK(c, hipEventRecord(c->ev_join, s2));
-    rc = coef(s);
-    if (rc) return rc;
-    if (prefix && m + 1 < c->N && !pair) {
-      rc = ring_prefix(c, m + 1, s);
-      if (rc) return rc;
-    }
-  } else {
-    HIPCHK(c, hipEventRecord(c->ev_fork, s));
-    // coefficient branch on the second stream, forked after the X-contraction
-    // launch (it needs only the Grams, which are ready at the fork)
-    auto branch = [&]() -> int {
-      HIPCHK(c, hipStreamWaitEvent(s2, c->ev_fork, 0));
-      const int r = coef(s2);
-      if (r) return r;
-      HIPCHK(c, hipEventRecord(c->ev_join, s2));
-      // after the join: the next mode's prefix excludes this mode's core
-      if (prefix && m + 1 < c->N && !pair) return ring_prefix(c, m + 1, s2);
-      return TR_OK;
-    };
-    int rc = compute_mttsp(c, m, prec, c->M, in_sweep, branch);
-    if (rc) return rc;
-  }
+  int rc = compute_mttsp(c, m, prec, c->M, in_sweep, branch);
+  if (rc) return rc;
   HIPCHK(c, hipStreamWaitEvent(s, c->ev_join, 0));
   // G = M S^{-1} with refinement; the apply latches any non-finite entry, and
   // the commit keeps the old core (and its Gram) when the status word is set
