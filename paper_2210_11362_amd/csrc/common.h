@@ -158,6 +158,15 @@ bool solve_in_lds(int n);
 // S^{-1} of an SPD matrix with n <= 128 by the symmetric sweep operator (one
 // workgroup, registers); a non-positive pivot latches ST_SINGULAR.
 bool spd_inverse_fits(int n);
+// Raises kernel k's dynamic-LDS limit when it needs more than the default 64 KB.
+inline hipError_t allow_lds(const void* k, size_t lds) {
+  return lds > 64 * 1024 ? hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) : hipSuccess;
+}
+#define LDSCHK(k, lds)                                   \
+  do {                                                   \
+    const hipError_t lds_e_ = allow_lds((k), (lds));     \
+    if (lds_e_ != hipSuccess) return lds_e_;             \
+  } while (0)
 // dst[r + ld_dst c] = src[r + ld_src c] for a rows x cols block (trans = 1:
 // src[c + ld_src r]; src == nullptr: zeros; add: dst += the value)
 hipError_t launch_copy_block(const double* src, int64_t ld_src, int rows, int cols, double* dst, int64_t ld_dst,

@@ -173,10 +173,8 @@ hipError_t launch_gen_planted(void* X, int xdt, int64_t I, int64_t K, const doub
   const int noise = eta != 0.0 ? 1 : 0;
   double* pt = partials;
   double* pn = partials + nblk;
-  if (lds > 64 * 1024) {
-    hipFuncSetAttribute((const void*)gen_pass1_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipFuncSetAttribute((const void*)gen_pass1_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  }
+  LDSCHK((const void*)gen_pass1_kernel<double>, lds);
+  LDSCHK((const void*)gen_pass1_kernel<float>, lds);
   const int64_t n = I * K;
   const int64_t grid2 = std::min<int64_t>(cdiv(n, 256), 16384);
   if (xdt == TR_F64) {

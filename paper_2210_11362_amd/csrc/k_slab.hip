@@ -60,7 +60,6 @@ template <> __device__ __forceinline__ double cvt<TR_F64, double>(double v) { re
 template <> __device__ __forceinline__ double cvt<TR_F64, float>(float v) { return (double)v; }
 template <> __device__ __forceinline__ float cvt<TR_F32, float>(float v) { return v; }
 template <> __device__ __forceinline__ float cvt<TR_F32, double>(double v) { return (float)v; }
-template <> __device__ __forceinline__ __bf16 cvt<TR_BF16, __bf16>(__bf16 v) { return v; }
 
 constexpr int NTHR = 256;
 constexpr int MTX = 128;     // rows per tile
@@ -391,7 +390,7 @@ template <int P, typename Tin>
 hipError_t launch_kt(const XslabArgs& a, size_t lds, hipStream_t s) {
   constexpr int KT = P == TR_BF16 ? 64 : (P == TR_F32 ? 32 : 16);
   auto k = xslab_kernel<P, Tin, KT>;
-  if (lds > 64 * 1024) hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  LDSCHK((const void*)k, lds);
   hipLaunchKernelGGL(k, dim3(a.n_mt * a.n_g, a.nsplit), dim3(NTHR), lds, s, a);
   return hipGetLastError();
 }

@@ -795,8 +795,7 @@ hipError_t launch_realign_S(MatView W, int Ra, int Rb, double* S, hipStream_t s)
 hipError_t launch_chol(const double* S, int n, double* L, double* LT, double* work, int* status, hipStream_t s) {
   const size_t bytes = (size_t)n * n * sizeof(double);
   if (bytes <= 150 * 1024) {
-    if (bytes > 64 * 1024)
-      hipFuncSetAttribute((const void*)chol_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    LDSCHK((const void*)chol_kernel<true>, bytes);
     hipLaunchKernelGGL(chol_kernel<true>, dim3(1), dim3(1024), bytes, s, S, n, L, LT, work, status);
   } else {
     hipLaunchKernelGGL(chol_kernel<false>, dim3(1), dim3(1024), 0, s, S, n, L, LT, work, status);
@@ -888,10 +887,8 @@ hipError_t launch_fit(const void* X, int xdt, int64_t I, int64_t K, const double
   const int RR4 = (Ra * Rb + 3) & ~3;
   const int kt = RR4 > 448 ? 16 : 32;
   const size_t lds = (size_t)kt * (RR4 + 1) * sizeof(double);
-  if (lds > 64 * 1024) {
-    hipFuncSetAttribute((const void*)fit_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipFuncSetAttribute((const void*)fit_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  }
+  LDSCHK((const void*)fit_kernel<double>, lds);
+  LDSCHK((const void*)fit_kernel<float>, lds);
   if (xdt == TR_F64)
     hipLaunchKernelGGL(fit_kernel<double>, dim3(nblk), dim3(256), lds, s, (const double*)X, I, K, G0, F1, F2, d1, m1,
                        d2, m2, Rb, Rmid, Ra, kt, partials);
@@ -907,7 +904,7 @@ hipError_t launch_ne_apply(const double* M, int64_t I, int n, const double* S, c
   const size_t lds = (size_t)3 * NE_APPLY_ROWS * n * sizeof(double);
   const dim3 grid((unsigned)cdiv(I, NE_APPLY_ROWS));
   const void* k = n <= 64 ? (const void*)ne_apply_kernel<4> : (const void*)ne_apply_kernel<2>;
-  if (lds > 64 * 1024) hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  LDSCHK(k, lds);
   void* args[] = {(void*)&M, (void*)&I, (void*)&n, (void*)&S, (void*)&Sinv, (void*)&refine, (void*)&G, (void*)&status};
   return hipLaunchKernel(k, grid, dim3(256), args, lds, s);
 }

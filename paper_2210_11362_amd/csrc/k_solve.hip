@@ -27,12 +27,6 @@ __device__ __forceinline__ double bcast(double v, int src) {
   return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
 }
 
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-}
-
 // Right-looking blocked Cholesky.  The matrix is padded in LDS to np (a
 // multiple of 16) with an identity block, so every block has 16 columns and
 // the inner loops have fixed trip counts: blockdiag(S, I) = blockdiag(L, I) L^T.
@@ -486,7 +480,11 @@ bool solve_in_lds(int n) { return n <= 128; }
 hipError_t launch_chol_lds(const double* S, int n, double* L, double* LT, double* rdiag, int* status, hipStream_t s) {
   const int np = (n + NB - 1) / NB * NB;
   const size_t lds = (size_t)np * np * sizeof(double);
-  if (lds > 64 * 1024) hipFuncSetAttribute((const void*)chol_lds_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (lds > 64 * 1024) {
+    const hipError_t e =
+        hipFuncSetAttribute((const void*)chol_lds_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(chol_lds_kernel, dim3(1), dim3(256), lds, s, S, n, L, LT, status, rdiag);
   return hipGetLastError();
 }
@@ -495,7 +493,11 @@ hipError_t launch_trsm_rhs(const double* L, const double* rdiag, int n, const do
                            int accumulate, const int* status, hipStream_t s, int mode) {
   const int np = (n + NB - 1) / NB * NB;
   const size_t lds = ((size_t)np * np + (size_t)NRHS * np) * sizeof(double);
-  if (lds > 64 * 1024) hipFuncSetAttribute((const void*)trsm_rhs_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (lds > 64 * 1024) {
+    const hipError_t e =
+        hipFuncSetAttribute((const void*)trsm_rhs_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(trsm_rhs_kernel, dim3((unsigned)((I + NRHS - 1) / NRHS)), dim3(256), lds, s, L, rdiag, n, Rhs,
                      I, G, accumulate, status, mode);
   return hipGetLastError();

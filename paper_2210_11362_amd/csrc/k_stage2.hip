@@ -500,9 +500,7 @@ hipError_t launch_absorb2(const Absorb2& a, hipStream_t s) {
   if (a.lo >= 32) {
     const int64_t chunk = cdiv(a.I, a.S);
     const size_t lds = std::max((size_t)chunk * row, (size_t)AW_WAVES * B * 64 * sizeof(double));
-    if (lds > 64 * 1024)
-      hipFuncSetAttribute((const void*)absorb_wide_kernel<B, SIDE0, EXACT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)lds);
+    LDSCHK(((const void*)absorb_wide_kernel<B, SIDE0, EXACT>), lds);
     dim3 grid((unsigned)cdiv(a.lo, 64), (unsigned)(a.hi * Rp), (unsigned)cdiv(a.I, chunk));
     hipLaunchKernelGGL((absorb_wide_kernel<B, SIDE0, EXACT>), grid, dim3(64 * AW_WAVES), lds, s, a, chunk);
     if (a.S > 1)

@@ -260,7 +260,6 @@ __global__ __launch_bounds__(NTHR) void xgemm_kernel(XgArgs g) {
 }
 
 
-inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 template <int P, typename Tin, bool NN, bool VEC, int MT, int KT>
 hipError_t launch_g(const XgArgs& g, hipStream_t s) {
@@ -268,7 +267,7 @@ hipError_t launch_g(const XgArgs& g, hipStream_t s) {
   const size_t lds = (size_t)(MT + (P == TR_FP8 ? 2 : 1) * g.NT) * (KT + Pad<P>::v) * sizeof(op_t);
   const dim3 grid = g.xcd_map ? dim3((unsigned)(g.n_mt * g.n_nt * g.nsplit)) : dim3(g.n_mt * g.n_nt, g.nsplit);
   auto k = xgemm_kernel<P, Tin, NN, VEC, MT, KT, 8>;
-  if (lds > 64 * 1024) hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  LDSCHK((const void*)k, lds);
   hipLaunchKernelGGL(k, grid, dim3(NTHR), lds, s, g);
   return hipGetLastError();
 }

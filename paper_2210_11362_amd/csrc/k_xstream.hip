@@ -103,7 +103,6 @@ __global__ __launch_bounds__(NTHR) void xstream_kernel(XsArgs a) {
   const int Bw4 = (a.NTb + 3) & ~3, Ra4 = (a.Ra + 3) & ~3;
   const int row1 = a.Rmid * Bw4, row2 = a.Rmid * Ra4;
   const int s1max = (a.d1 == 1) ? KT : min((int64_t)KT, (KT + a.d1 - 1) / a.d1 + 1);
-  const int s2max = (a.d2 == 1) ? KT : min((int64_t)KT, (KT + a.d2 - 1) / a.d2 + 1);
 
   // FP8: the generated subchain rows are stored as hi and lo E4M3 parts
   // (NT rows each), both contracted into the same accumulators
@@ -343,24 +342,20 @@ __global__ void xs_reduce_kernel(XsArgs a, double out_scale, double* M, int* sta
   M[i + a.I * (int64_t)(aa + a.Ra * b)] = s;
 }
 
-inline void set_lds_attr(const void* k, size_t lds) {
-  if (lds > 64 * 1024) hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-}
-
 template <int P, typename Tin, int KT>
 hipError_t launch_t(const XsArgs& a, int wlay, size_t lds, hipStream_t s) {
   dim3 grid(a.n_mt * a.n_nt, a.nsplit);
   if (wlay == 0) {
     auto k = xstream_kernel<P, Tin, KT, 4, 4>;
-    set_lds_attr((const void*)k, lds);
+    LDSCHK((const void*)k, lds);
     hipLaunchKernelGGL(k, grid, dim3(NTHR), lds, s, a);
   } else if (wlay == 1) {
     auto k = xstream_kernel<P, Tin, KT, 8, 2>;
-    set_lds_attr((const void*)k, lds);
+    LDSCHK((const void*)k, lds);
     hipLaunchKernelGGL(k, grid, dim3(NTHR), lds, s, a);
   } else {
     auto k = xstream_kernel<P, Tin, KT, 2, 8>;
-    set_lds_attr((const void*)k, lds);
+    LDSCHK((const void*)k, lds);
     hipLaunchKernelGGL(k, grid, dim3(NTHR), lds, s, a);
   }
   return hipGetLastError();

@@ -1294,9 +1294,8 @@ int build_v2(tr_als_ctx* c, int m, int64_t* Jp_out) {
 // G_n(2) = W_n R^{-T}.
 int update_mode_qr_large(tr_als_ctx* c, int m, int prec, bool in_sweep, int64_t Jp) {
   hipStream_t s = c->stream;
-  const int N = c->N;
   const int Ra = c->R[m], Rb = c->R[m + 1], n = Ra * Rb;
-  const double one = 1.0, zero = 0.0;
+  const double one = 1.0;
   int rc = blas_on(c, s);
   if (rc) return rc;
   double* A = c->qV2;   // V_n[2], orthogonalised in place (two passes; Q_0 = A L_3^{-T})
