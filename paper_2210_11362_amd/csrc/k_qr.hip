@@ -580,15 +580,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 
 // C (P x Q) = A^T B for two different tall operands (K rows, P, Q <= 16*NB)
 // with the MFMA fragments loaded straight into registers, as in the Gram
-// kernel above.  Element (k, p) of A sits at A[k*ks + p*ps] (column-major,
-// or the row-major layout of a first-mode unfolding), or, when L > 1, at
-// A[l + LIp*t + L*p] with k = l + L*t (mode n of a Multi-TTM result, L >= 4);
-// B is column-major (ld ldb).  The NB x NB output tiles, in column-major tile
-// order, are dealt to the four waves in runs of ceil(NB^2/4), so a wave's
-// accumulators fit its registers; every wave runs over the whole chunk (the
-// repeated fragment loads hit the caches) and stores its own tiles.  In the
-// group of 16 rows starting at row g, lane (c, kq) holds rows g + 4kq + j,
-// j = 0..3, of both operands.
+// kernel above.  Element (k, p) of A sits at A[k*ks + p*ps] (used for the
+// row-major layout of a first-mode unfolding; k-contiguous operands take the
+// LDS-staged kernel below); B is column-major (ld ldb).  The NB x NB output
+// tiles, in column-major tile order, are dealt to the four waves in runs of
+// ceil(NB^2/4), so a wave's accumulators fit its registers; every wave runs
+// over the whole chunk (the repeated fragment loads hit the caches) and
+// stores its own tiles.  In the group of 16 rows starting at row g, lane
+// (c, kq) holds rows g + 4kq + j, j = 0..3, of both operands.
+// (AtbArgs' L and LIp describe A in the Multi-TTM layout for the LDS-staged
+// kernel: element (k, p) at A[l + LIp*t + L*p], k = l + L*t.)
 struct AtbArgs {
   const double* A; int64_t ks, ps, L, LIp;
   const double* B; int64_t ldb;
@@ -596,7 +597,7 @@ struct AtbArgs {
   double* part;
 };
 
-template <int NB, int W, int G, bool LAY, bool BV>
+template <int NB, int W, int G, bool BV>
 __device__ __forceinline__ void atb_frag_wave(const AtbArgs& g) {
   constexpr int NT = NB * NB, TW = (NT + 3) / 4, T0 = W * TW < NT ? W * TW : NT;
   constexpr int T1 = T0 + TW < NT ? T0 + TW : NT;
@@ -612,7 +613,7 @@ __device__ __forceinline__ void atb_frag_wave(const AtbArgs& g) {
   // load is unconditional (no branch around it).
   const double* acol[NB];
 #pragma unroll
-  for (int b = 0; b < NB; ++b) acol[b] = g.A + (int64_t)min(16 * b + cl, g.P - 1) * (LAY ? g.L : g.ps);
+  for (int b = 0; b < NB; ++b) acol[b] = g.A + (int64_t)min(16 * b + cl, g.P - 1) * g.ps;
   const double* bcol[NQ];
 #pragma unroll
   for (int u = 0; u < NQ; ++u) bcol[u] = g.B + g.ldb * min(16 * (BQ0 + u) + cl, g.Q - 1);
@@ -625,17 +626,11 @@ __device__ __forceinline__ void atb_frag_wave(const AtbArgs& g) {
   // measured fastest (100 x 100 result, 10^6 rows: 630-870 us against
   // 950-1350 us for two and 720-1130 us for three).
   double fa[NB][4 * G], fb[NQ][4 * G];
-  // per group s: the lane's first row's position in the layout (l, and the
-  // element offset ro = l + LIp*t, or row*ks), advanced with the rows; L is
-  // below 2^31 here, so l and the wrap count are 32-bit
-  uint32_t lg[G];
+  // per group s: the element offset of the lane's first row, advanced with
+  // the rows
   int64_t rg[G];
 #pragma unroll
-  for (int sg = 0; sg < G; ++sg) {
-    const int64_t r0 = k0 + 16 * sg + 4 * kq;
-    if (LAY) { lg[sg] = (uint32_t)(r0 % g.L); rg[sg] = lg[sg] + g.LIp * (r0 / g.L); }
-    else { lg[sg] = 0; rg[sg] = r0 * g.ks; }
-  }
+  for (int sg = 0; sg < G; ++sg) rg[sg] = (k0 + 16 * sg + 4 * kq) * g.ks;
   auto load = [&](int64_t gg, int q) {
     const int sg = q >> 1, h = q & 1;
     const int64_t rb = gg + 16 * sg + 4 * kq;
@@ -643,10 +638,7 @@ __device__ __forceinline__ void atb_frag_wave(const AtbArgs& g) {
     for (int e = 0; e < 2; ++e) {
       const int jj = 2 * h + e;
       const int64_t r = rb + jj;
-      int64_t ro;
-      if (LAY) ro = rg[sg] + jj + ((int64_t)lg[sg] + jj >= g.L ? g.LIp - g.L : 0);
-      else ro = rg[sg] + jj * g.ks;
-      ro = r < k1 ? ro : 0;
+      const int64_t ro = r < k1 ? rg[sg] + jj * g.ks : 0;
 #pragma unroll
       for (int b = 0; b < NB; ++b) fa[b][4 * sg + jj] = acol[b][ro];
     }
@@ -684,15 +676,7 @@ __device__ __forceinline__ void atb_frag_wave(const AtbArgs& g) {
   // branches around them
   for (; gg < k1; gg += RS) {
 #pragma unroll
-    for (int sg = 0; sg < G; ++sg) {
-      if (LAY) {   // advance RS rows: w wraps of l past L, each a step of LIp - L
-        const uint32_t L32 = (uint32_t)g.L, w = (lg[sg] + (uint32_t)RS) / L32;
-        lg[sg] = lg[sg] + (uint32_t)RS - w * L32;
-        rg[sg] += RS + (int64_t)w * (g.LIp - g.L);
-      } else {
-        rg[sg] += RS * g.ks;
-      }
-    }
+    for (int sg = 0; sg < G; ++sg) rg[sg] += RS * g.ks;
 #pragma unroll
     for (int q = 0; q < 2 * G; ++q) {
       mfma(q);
@@ -715,13 +699,13 @@ __device__ __forceinline__ void atb_frag_wave(const AtbArgs& g) {
 // atb_frag_kernel.
 constexpr int ATB_G = 1, ATB_CHUNKS = 512;
 
-template <int NB, bool LAY, bool BV>
+template <int NB, bool BV>
 __global__ __launch_bounds__(256) void atb_frag_kernel(AtbArgs g) {
   switch (threadIdx.x >> 6) {
-    case 0: atb_frag_wave<NB, 0, ATB_G, LAY, BV>(g); break;
-    case 1: atb_frag_wave<NB, 1, ATB_G, LAY, BV>(g); break;
-    case 2: atb_frag_wave<NB, 2, ATB_G, LAY, BV>(g); break;
-    default: atb_frag_wave<NB, 3, ATB_G, LAY, BV>(g); break;
+    case 0: atb_frag_wave<NB, 0, ATB_G, BV>(g); break;
+    case 1: atb_frag_wave<NB, 1, ATB_G, BV>(g); break;
+    case 2: atb_frag_wave<NB, 2, ATB_G, BV>(g); break;
+    default: atb_frag_wave<NB, 3, ATB_G, BV>(g); break;
   }
 }
 
@@ -777,7 +761,7 @@ __device__ __forceinline__ void atb_lds_store(const AtbArgs& g, const f64x4* acc
 
 // LAY: A in the Multi-TTM layout (else column-major: k contiguous).
 template <int NB, bool LAY>
-__global__ __launch_bounds__(256) void atb_lds_kernel(AtbArgs g) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void atb_lds_kernel(AtbArgs g) {
   constexpr int NP = 16 * NB, OPS = NP * AL_KP, TW = (NB * NB + 3) / 4;
   extern __shared__ __align__(16) double als[];   // 2 buffers x (A, B) x NP x AL_KP
   const int tid = threadIdx.x, wave = tid >> 6;
@@ -1286,14 +1270,14 @@ hipError_t launch_tall_atb(const double* A, int64_t lda, const double* B, int64_
     hipLaunchKernelGGL(sum_chunks_kernel, dim3(cdiv(n, 64)), dim3(256), 0, s, (const double*)part, (int)nchunk, n, C);
     return hipGetLastError();
   }
-  // two operands, fragments in registers: A strided (plain, a first-mode or
-  // last-mode unfolding) or in the Multi-TTM layout with L >= 4
+  // two operands: A strided (plain, a first-mode or last-mode unfolding) or
+  // in the Multi-TTM layout
   AtbArgs fa{A, 1, lda, 1, 0, B, ldb, K, 0, P, Q, part};
   bool frag = !gram && nb <= 7 && P > 0 && Q > 0;
   if (mode == 1) {
     if (L == 1) { fa.ks = Ip; fa.ps = 1; }
     else if (T == 1) { fa.ks = 1; fa.ps = L; }
-    else if (L >= 4 && L < ((int64_t)1 << 31)) { fa.L = L; fa.LIp = L * Ip; fa.ps = L; }
+    else if (L < ((int64_t)1 << 31)) { fa.L = L; fa.LIp = L * Ip; fa.ps = L; }
     else frag = false;
   }
   if (frag) {
@@ -1303,11 +1287,11 @@ hipError_t launch_tall_atb(const double* A, int64_t lda, const double* B, int64_
     const size_t lds = 0;
     const bool bv = ldb % 2 == 0 && K % 2 == 0 && (reinterpret_cast<uintptr_t>(B) & 15) == 0;
     const dim3 grid((unsigned)nchunk);
-    // A read with k contiguous over long runs: staged through LDS; a
-    // row-major A or short runs (L < 1024): fragments straight from memory
-    // (at 10^6 x 100: L = 10^4 680 against 850 us, column-major 640 against
-    // 870; row-major 640 against 700, L = 100 690 against 710)
-    const bool use_lds = fa.L > 1 ? fa.L >= 1024 : fa.ks == 1;
+    // A with k contiguous (column-major or the Multi-TTM layout): staged
+    // through LDS, two workgroups a CU; a row-major A: fragments straight
+    // from memory (at 10^6 x 100: L = 10^4 509 against 850 us, L = 100 586
+    // against 690, column-major 481 against 870; row-major 640 against 700)
+    const bool use_lds = fa.L > 1 || fa.ks == 1;
     if (use_lds) {
       const size_t ldsb = (size_t)4 * 16 * nb * AL_KP * sizeof(double);
       switch (nb * 2 + (fa.L > 1 ? 1 : 0)) {
@@ -1323,12 +1307,10 @@ hipError_t launch_tall_atb(const double* A, int64_t lda, const double* B, int64_
                          C);
       return hipGetLastError();
     }
-    switch (nb * 4 + (fa.L > 1 ? 2 : 0) + (bv ? 1 : 0)) {
+    switch (nb * 2 + (bv ? 1 : 0)) {
 #define ATB_FRAG(NBV) \
-  case 4 * NBV: hipLaunchKernelGGL((atb_frag_kernel<NBV, false, false>), grid, dim3(256), lds, s, fa); break; \
-  case 4 * NBV + 1: hipLaunchKernelGGL((atb_frag_kernel<NBV, false, true>), grid, dim3(256), lds, s, fa); break; \
-  case 4 * NBV + 2: hipLaunchKernelGGL((atb_frag_kernel<NBV, true, false>), grid, dim3(256), lds, s, fa); break; \
-  case 4 * NBV + 3: hipLaunchKernelGGL((atb_frag_kernel<NBV, true, true>), grid, dim3(256), lds, s, fa); break;
+  case 2 * NBV: hipLaunchKernelGGL((atb_frag_kernel<NBV, false>), grid, dim3(256), lds, s, fa); break; \
+  case 2 * NBV + 1: hipLaunchKernelGGL((atb_frag_kernel<NBV, true>), grid, dim3(256), lds, s, fa); break;
       ATB_FRAG(1) ATB_FRAG(2) ATB_FRAG(3) ATB_FRAG(4) ATB_FRAG(5) ATB_FRAG(6) ATB_FRAG(7)
 #undef ATB_FRAG
       default: return hipErrorInvalidValue;
