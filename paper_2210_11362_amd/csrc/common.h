@@ -195,9 +195,10 @@ hipError_t launch_tall_atb(const double* A, int64_t lda, const double* B, int64_
 hipError_t launch_ttm(const void* in, int in_type, int64_t L, int64_t I, int64_t T, const double* Q, int R,
                       double scale, double* out, hipStream_t s);
 hipError_t launch_transpose(const double* A, int64_t rows, int64_t cols, double* At, hipStream_t s);
-// C = A B for a tall column-major A (M x K) and a small B (K x N), K, N <= 112.
+// C = A B for a tall column-major A (M x K) and a small B (K x N), K, N <= 112;
+// b_upper: B is upper triangular (its zero blocks below the diagonal are skipped).
 hipError_t launch_tall_gemm(const double* A, int64_t lda, int64_t M, int K, const double* B, int ldb, int N,
-                            double* C, int64_t ldc, hipStream_t s);
+                            double* C, int64_t ldc, hipStream_t s, bool b_upper = false);
 hipError_t launch_table_to_v2(const double* T, int64_t J, int64_t L, int Ra, int Rb, double* V2, hipStream_t s);
 // V2[k' + J*(a + Ra*b)] = sum_m Tp[j][b + Rb*m] core[m + Rm*(i + I*a)] with
 // j + Jp*i the subchain row of Multi-TTM row k' (J = Jp*I, L rows before n).

@@ -6,6 +6,7 @@
 //     shifted Cholesky-QR, and W_n = Y_[n] Q_0) on FP64 MFMA with ordered split-K;
 //   - mode products (TTM, Sec. 2) for the Multi-TTM Y = X x_{j != n} Q_j^T.
 #include <algorithm>
+#include <type_traits>
 
 #include "common.h"
 #include "../../include/tr_als.h"
@@ -1049,6 +1050,11 @@ __global__ __launch_bounds__(256) void v2_direct_kernel(const double* Tp, int64_
 // row-major C (ROWOUT) it forms C = A B, so a store covers 16 consecutive
 // columns.  Step (j, e) takes from lane group kq the inner index
 // k = 8j + 2kq + e; k past K reads A at k = K-1 against zero rows of B.
+// UPPER: B is upper triangular (B[k, n] = 0 for k > n, as L^{-T} in the
+// Cholesky-QR passes), so step j skips the column tiles whose columns all lie
+// below k = 8j (tile ct needs 8j <= 16ct + 15, i.e. ct >= j/2): about 60 % of
+// the MFMAs at K = N = 100, with the same sums (the skipped terms are
+// products with exact zeros).
 struct TGArgs {
   const void* A; int64_t rs, ks, sa, M; int K;
   const double* B; int ldb, N;
@@ -1056,7 +1062,7 @@ struct TGArgs {
   double scale;
 };
 constexpr int TG_WAVES = 4;
-template <int NB, bool TRIM, bool ROWOUT, typename Tin>
+template <int NB, bool TRIM, bool ROWOUT, bool UPPER, typename Tin>
 __global__ __launch_bounds__(64 * TG_WAVES) void tall_gemm_kernel(TGArgs g) {
   // k steps of 8: all 16*NB values of k, or (TRIM, K <= 16*NB - 8) one fewer
   constexpr int NP = 16 * NB, BST = NP + 2, KJ = 2 * NB - (TRIM ? 1 : 0);
@@ -1105,12 +1111,12 @@ __global__ __launch_bounds__(64 * TG_WAVES) void tall_gemm_kernel(TGArgs g) {
     for (int j = 0; j < KJ; ++j) {
       if (j + 1 < KJ) {
 #pragma unroll
-        for (int ct = 0; ct < NB; ++ct)
+        for (int ct = UPPER ? (j + 1) / 2 : 0; ct < NB; ++ct)
           bv[(j + 1) & 1][ct] =
               *reinterpret_cast<const double2*>(tsm + (16 * ct + cl) * BST + 8 * (j + 1) + 2 * kq);
       }
 #pragma unroll
-      for (int ct = 0; ct < NB; ++ct) {
+      for (int ct = UPPER ? j / 2 : 0; ct < NB; ++ct) {
         const double2 b = bv[j & 1][ct];
         if (ROWOUT) {
           mma64(acc[ct], cur[j].x, b.x);
@@ -1158,23 +1164,34 @@ __global__ __launch_bounds__(64 * TG_WAVES) void tall_gemm_kernel(TGArgs g) {
 }
 
 template <typename Tin>
-hipError_t launch_tg(const TGArgs& g, hipStream_t s) {
+hipError_t launch_tg(const TGArgs& g, hipStream_t s, bool upper = false) {
   const int nb = max((g.K + 15) / 16, (g.N + 15) / 16);
   const bool rowout = g.cns == 1 && g.crs != 1;
   if (g.M <= 0 || g.K <= 0 || g.N <= 0 || g.nbatch <= 0 || nb > 7) return hipErrorInvalidValue;
+  if (upper && (rowout || !std::is_same<Tin, double>::value)) return hipErrorInvalidValue;
   const size_t lds = (size_t)16 * nb * (16 * nb + 2) * sizeof(double);
   const int64_t ntile = (g.M * g.nbatch + 15) / 16;
   const dim3 grid((unsigned)std::min<int64_t>((ntile + TG_WAVES - 1) / TG_WAVES, 256));
   const void* k = nullptr;
   const bool trim = g.K <= 16 * nb - 8;
-  switch (nb * 4 + (trim ? 2 : 0) + (rowout ? 1 : 0)) {
+  if (upper) {   // column-major output, FP64 input
+    switch (nb * 2 + (trim ? 1 : 0)) {
+#define TG_UCASE(NBV) \
+  case 2 * NBV: k = (const void*)tall_gemm_kernel<NBV, false, false, true, double>; break; \
+  case 2 * NBV + 1: k = (const void*)tall_gemm_kernel<NBV, true, false, true, double>; break;
+      TG_UCASE(1) TG_UCASE(2) TG_UCASE(3) TG_UCASE(4) TG_UCASE(5) TG_UCASE(6) TG_UCASE(7)
+#undef TG_UCASE
+    }
+  } else {
+    switch (nb * 4 + (trim ? 2 : 0) + (rowout ? 1 : 0)) {
 #define TG_CASE(NBV) \
-  case 4 * NBV: k = (const void*)tall_gemm_kernel<NBV, false, false, Tin>; break; \
-  case 4 * NBV + 1: k = (const void*)tall_gemm_kernel<NBV, false, true, Tin>; break; \
-  case 4 * NBV + 2: k = (const void*)tall_gemm_kernel<NBV, true, false, Tin>; break; \
-  case 4 * NBV + 3: k = (const void*)tall_gemm_kernel<NBV, true, true, Tin>; break;
-    TG_CASE(1) TG_CASE(2) TG_CASE(3) TG_CASE(4) TG_CASE(5) TG_CASE(6) TG_CASE(7)
+  case 4 * NBV: k = (const void*)tall_gemm_kernel<NBV, false, false, false, Tin>; break; \
+  case 4 * NBV + 1: k = (const void*)tall_gemm_kernel<NBV, false, true, false, Tin>; break; \
+  case 4 * NBV + 2: k = (const void*)tall_gemm_kernel<NBV, true, false, false, Tin>; break; \
+  case 4 * NBV + 3: k = (const void*)tall_gemm_kernel<NBV, true, true, false, Tin>; break;
+      TG_CASE(1) TG_CASE(2) TG_CASE(3) TG_CASE(4) TG_CASE(5) TG_CASE(6) TG_CASE(7)
 #undef TG_CASE
+    }
   }
   if (lds > 64 * 1024) {
     const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -1445,7 +1462,7 @@ hipError_t launch_shift_and_add(double* G, int n, int64_t m, double* sbuf, hipSt
 }
 
 hipError_t launch_tall_gemm(const double* A, int64_t lda, int64_t M, int K, const double* B, int ldb, int N,
-                            double* C, int64_t ldc, hipStream_t s) {
+                            double* C, int64_t ldc, hipStream_t s, bool b_upper) {
   TGArgs g{A, 1, lda, 0, M, K, B, ldb, N, C, 1, ldc, 0, 1, 1.0};
-  return launch_tg<double>(g, s);
+  return launch_tg<double>(g, s, b_upper);
 }

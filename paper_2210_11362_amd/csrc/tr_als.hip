@@ -1363,7 +1363,7 @@ int update_mode_qr(tr_als_ctx* c, int m, int prec, bool in_sweep) {
     if (it == 2) break;   // Q_0 = A L_3^{-T} is applied to W_n instead
     HIPCHK(c, launch_trsm_rhs(c->qL[it], c->rdiag, n, nullptr, n, c->qRi, 0, c->status, s, 1));
     if (n <= 112) {
-      HIPCHK(c, launch_tall_gemm(A, Jp, Jp, n, c->qRi, n, n, bufs[it & 1], Jp, s));
+      HIPCHK(c, launch_tall_gemm(A, Jp, Jp, n, c->qRi, n, n, bufs[it & 1], Jp, s, true));
     } else {
       MatView Av{A, Jp, 0, 0, 0}, Ri{c->qRi, n, 0, 0, 0};
       HIPCHK(c, launch_gemm64(Jp, n, n, 1.0, Av, Ri, 0.0, nullptr, 0, bufs[it & 1], Jp, s));
