@@ -416,6 +416,7 @@ void check_extents(const std::string& full, const std::string& nm, void** a, std
     r->push_back({D(0), b, "S"});
     r->push_back({D(2), b, "L"});
     r->push_back({D(3), b, "LT"});
+    r->push_back({D(5), (size_t)((I(1) + 7) / 8 * 8 * 8), "rdiag"});   // padded to 8-column blocks
   } else if (nm == "trsm_rhs_kernel") {     // (L, rdiag, n, Rhs, I, G, accumulate, status, mode)
     const int64_t n = I(2), rows = L(4);
     r->push_back({D(0), (size_t)(n * n * 8), "L"});
