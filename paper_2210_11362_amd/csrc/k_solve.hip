@@ -28,7 +28,7 @@ __device__ __forceinline__ double bcast(double v, int src) {
 }
 
 // Right-looking blocked Cholesky.  The matrix is padded in LDS to np (a
-// multiple of 16) with an identity block, so every block has 16 columns and
+// multiple of NB) with an identity block, so every block has NB columns and
 // the inner loops have fixed trip counts: blockdiag(S, I) = blockdiag(L, I) L^T.
 __global__ __launch_bounds__(256) void chol_lds_kernel(const double* S, int n, double* L, double* LT, int* status,
                                                        double* rdg) {
