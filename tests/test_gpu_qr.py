@@ -23,6 +23,7 @@ QR_SHAPES = [
     ((11, 13, 9), (3, 3, 3)),              # odd V_n[2] height: the LDS-staged Gram
     ((60, 60, 60), (7, 7, 7)),             # odd height, four 16-column blocks
     ((110, 110, 110), (10, 10, 10)),       # even height, seven blocks: the register-fragment Gram
+    ((24, 26, 22), (8, 14, 8)),            # n = 112: tall products with all seven k blocks (none trimmed)
 ]
 
 
