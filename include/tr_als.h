@@ -58,7 +58,10 @@ enum {
 };
 
 /*
- * tr_als_init -- create a context for one decomposition job.
+ * tr_als_init -- create a context for one decomposition job: the tensor and
+ * initial cores of the TR format (Sec. 2) that the ALS sweeps of Alg. 1-4
+ * start from, with the per-core state those updates reuse (Grams for
+ * Prop. 3.1's ring product; core QRs and R-cores for Alg. 3 and Alg. 4).
  *   ctx      host out: the new context (NULL on failure).
  *   N        tensor order, 2 <= N <= 8.
  *   dims     host, I_1..I_N, each >= 1; prod(I_n) < 2^62.
@@ -356,8 +359,9 @@ typedef struct {
  * tr_srv_create -- start a server on the current device.
  *   hbm_budget_bytes  size of the device arena all jobs are carved from
  *                     (0: 90% of the free device memory); allocated here.
- *   max_slots         concurrent jobs, 1..64; each slot owns a thread and
- *                     two streams (default priority).
+ *   max_slots         concurrent jobs, 1..64; each slot owns two streams
+ *                     (default priority); one executor thread drives all
+ *                     slots and is the only caller of HIP.
  *   flags             TR_SRV_BATCH: run small jobs in the batch lanes.
  * Returns TR_EINVAL, TR_ENOMEM (arena allocation) or TR_EHIP on failure.
  */
