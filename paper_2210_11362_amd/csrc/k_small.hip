@@ -126,21 +126,22 @@ __global__ __launch_bounds__(256) void commit_gram_kernel(const double* G, int64
 
 // ---------------------------------------------------------------------------
 // Normal-equation apply with iterative refinement (Alg. 2 solve step): for a
-// block of NE_APPLY_ROWS rows of M, G = M S^{-1}, then per refinement step
+// block of RB rows of M, G = M S^{-1}, then per refinement step
 // R = M - G S and G += R S^{-1}; the row blocks stay in LDS (k-major) between
 // the products, the n x n operands are read from L2 (32 values of k in flight
 // per thread).  RG row groups split the 256 threads so that small n keeps
 // every thread busy.  A non-finite entry of the final G latches ST_NONFINITE.
-// (Staging the operand in LDS and 8- or 16-row blocks measured slower.)
+// Blocks of 2 rows (twice the workgroups of 4) for n > 64; 4 rows with four
+// row groups for smaller n.  (Staging the operand in LDS and 8- or 16-row
+// blocks measured slower.)
 // ---------------------------------------------------------------------------
-constexpr int NE_APPLY_ROWS = 4;
 
-template <int RG>
+template <int RB, int RG>
 __global__ __launch_bounds__(256) void ne_apply_kernel(const double* __restrict__ M, int64_t I, int n,
                                                        const double* __restrict__ S,
                                                        const double* __restrict__ Sinv, int refine,
                                                        double* __restrict__ G, int* status) {
-  constexpr int RB = NE_APPLY_ROWS, RPT = RB / RG, CT = 256 / RG, KB = 32;
+  constexpr int RPT = RB / RG, CT = 256 / RG, KB = 32;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* Ms = reinterpret_cast<double*>(smem_raw);
   double* Gs = Ms + RB * n;
@@ -901,9 +902,10 @@ hipError_t launch_fit(const void* X, int xdt, int64_t I, int64_t K, const double
 
 hipError_t launch_ne_apply(const double* M, int64_t I, int n, const double* S, const double* Sinv, int refine,
                            double* G, int* status, hipStream_t s) {
-  const size_t lds = (size_t)3 * NE_APPLY_ROWS * n * sizeof(double);
-  const dim3 grid((unsigned)cdiv(I, NE_APPLY_ROWS));
-  const void* k = n <= 64 ? (const void*)ne_apply_kernel<4> : (const void*)ne_apply_kernel<2>;
+  const int rb = n <= 64 ? 4 : 2;
+  const size_t lds = (size_t)3 * rb * n * sizeof(double);
+  const dim3 grid((unsigned)cdiv(I, rb));
+  const void* k = n <= 64 ? (const void*)ne_apply_kernel<4, 4> : (const void*)ne_apply_kernel<2, 2>;
   LDSCHK(k, lds);
   void* args[] = {(void*)&M, (void*)&I, (void*)&n, (void*)&S, (void*)&Sinv, (void*)&refine, (void*)&G, (void*)&status};
   return hipLaunchKernel(k, grid, dim3(256), args, lds, s);
